@@ -1,0 +1,230 @@
+/*
+ * fd.h -- C ABI of the MI355X acoustic isotropic finite-difference library
+ * (libfd.so, HIP for gfx950).
+ *
+ * What it computes.  The acoustic isotropic wave-propagation kernel that the
+ * paper evaluates as its real-world application (Sec. 4.5, Minimod: a
+ * finite-difference discretised wave equation with a high-order stencil, run
+ * on 1200^3 grids for 1000 steps), on ONE device's subdomain, together with
+ * the pack and unpack of the subdomain's boundary planes that the paper's
+ * halo exchange moves between neighbouring ranks with one-sided puts and a
+ * fence (Listing 1).  The paper does not state the stencil; this library uses
+ *   - 8th order in space: per axis the 9-point central second difference
+ *     c0 = -205/72, c1 = 8/5, c2 = -1/5, c3 = 8/315, c4 = -1/560, divided by
+ *     the squared spacing; the three axes summed (a 25-point star, radius 4);
+ *   - 2nd order in time (leapfrog) with an optional damping sponge eta >= 0:
+ *       u_next = (2 u - (1 - eta) u_prev + vdt2 * L u) / (1 + eta),
+ *     where vdt2 = (v dt)^2 and eta = eta_x[i] + eta_y[j] + eta_z[k];
+ *   - a point source added after the update: u_next[s] += vdt2[s] w / (1+eta[s]);
+ *   - receivers sampling the updated field.
+ * All arithmetic on the device is FP32.
+ *
+ * Memory layout.  Every volume array is FP32, x fastest, with a halo of
+ * H = 4 points on each face.  Interior point (i, j, k), 0 <= i < nx etc., is
+ * element  origin + k*zstride + j*ystride + i;  halo points use i, j or k in
+ * [-4, 0) or [n, n+4).  fd_grid_init picks an origin and strides that put
+ * every interior row start on a 128-byte boundary.
+ *
+ * Conventions.
+ *   - Pointers named *_dev or documented as "device" are device pointers
+ *     owned by the caller; the library never frees or retains them.  The
+ *     stepping calls (fd_step ... fd_grad_finalize) never allocate.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work on it and return without synchronising, except
+ *     where a call says it synchronises.
+ *   - Return value: FD_OK or a negative FD_E* code; nothing is enqueued when
+ *     a call returns an error.  fd_strerror() names a code; fd_last_error()
+ *     returns a thread-local detail string for the last failing call.
+ *   - Device faults in enqueued kernels surface at the caller's next
+ *     synchronisation, as for any HIP kernel.
+ *   - No C++ exception crosses this boundary.
+ */
+#ifndef FD_H
+#define FD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FD_HALO 4
+
+enum {
+  FD_OK = 0,
+  FD_ENOTFOUND = -2,   /* unknown shot id                                  */
+  FD_EDEVICE = -5,     /* a HIP runtime or launch error                    */
+  FD_EAGAIN = -11,     /* shot not finished yet                            */
+  FD_ENOMEM = -12,     /* cannot fit in the given memory                   */
+  FD_EINVAL = -22,     /* invalid argument, geometry or aliasing           */
+  FD_ECANCELED = -125  /* shot cancelled by server shutdown                */
+};
+
+/* Geometry shared by every volume array of one call. */
+typedef struct fd_grid {
+  int32_t nx, ny, nz;       /* interior extent, each >= 1                            */
+  int32_t halo;             /* must be FD_HALO (the stencil radius)                  */
+  int64_t origin;           /* element offset of interior (0,0,0); >= 4*zstride+4*ystride+4 */
+  int64_t ystride, zstride; /* element strides; ystride >= nx+8,
+                               zstride >= ystride*(ny+8), zstride <= INT32_MAX       */
+  double dx, dy, dz;        /* grid spacing (metres), finite and > 0                 */
+} fd_grid;
+
+/* Damping tables (device pointers, FP32, lengths nx, ny, nz).  All three NULL
+ * (or a NULL fd_sponge*) means no sponge.  eta = (dt/2) * sigma, see
+ * fd_sponge_eta_max / fd_sponge_profile. */
+typedef struct fd_sponge {
+  const float* eta_x;
+  const float* eta_y;
+  const float* eta_z;
+} fd_sponge;
+
+/* A point source term: w added at interior point (i, j, k). */
+typedef struct fd_source {
+  int32_t i, j, k;
+  float w;
+} fd_source;
+
+/* ------------------------------------------------------------- errors */
+
+/* Static description of a return code; never NULL. */
+const char* fd_strerror(int code);
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* fd_last_error(void);
+/* ABI version (major*10000 + minor*100 + patch). */
+int fd_version(void);
+
+/* ----------------------------------------------------------- geometry */
+
+/* Fill *g for an nx*ny*nz interior with spacing (dx,dy,dz): halo 4, the
+ * interior row start 128-byte aligned (32 floats of left padding, of which
+ * the last 4 are the x halo), ystride a multiple of 32 floats, zstride =
+ * ystride*(ny+8).  FD_EINVAL on bad sizes or spacing, or if zstride would
+ * exceed INT32_MAX. */
+int fd_grid_init(fd_grid* g, int32_t nx, int32_t ny, int32_t nz, double dx,
+                 double dy, double dz);
+/* Floats the caller must allocate per volume array (origin + the furthest
+ * halo element + 1); -1 for an invalid grid. */
+int64_t fd_grid_elems(const fd_grid* g);
+/* Floats of face buffer `face` (0..5 = -x,+x,-y,+y,-z,+z): 4*ny*nz for x
+ * faces, 4*nx*nz for y faces, 4*nx*ny for z faces; -1 if invalid. */
+int64_t fd_face_elems(const fd_grid* g, int32_t face);
+/* Element offset of point (i,j,k) (halo indices allowed); -1 if outside
+ * [-4, n+4) on an axis. */
+int64_t fd_offset(const fd_grid* g, int32_t i, int32_t j, int32_t k);
+
+/* Performance knob: number of z planes each block of the stencil kernels
+ * marches through (0 = automatic, the default).  Process-wide; results do not
+ * depend on it. */
+int fd_set_kchunk(int32_t kchunk);
+
+/* ----------------------------------------------------------- model prep
+ * (set-up, step S0; not on the per-step path) */
+
+/* Device reduction of max(v) over the interior of v; writes it to
+ * *vmax_host and computes dt = courant * min(dx,dy,dz) / max(v) into *dt_out
+ * (either pointer may be NULL).  SYNCHRONISES `stream`.  `scratch_dev` is a
+ * caller-owned device buffer of at least 2 int32.  FD_EINVAL unless every
+ * interior velocity is > 0 and the maximum is finite. */
+int fd_cfl_dt(const fd_grid* g, const float* v, double courant, int32_t* scratch_dev,
+              double* vmax_host, double* dt_out, void* stream);
+
+/* vdt2 = (v*dt)^2, evaluated in FP64 and rounded to FP32, on every point of
+ * the padded box [-4,n+4)^3 of vdt2: the interior from v's interior, each
+ * face halo from the periodic image of the interior (i mod n), edges and
+ * corners 0.  Only v's interior is read.  v and vdt2 must not overlap. */
+int fd_prepare_vdt2(const fd_grid* g, const float* v, float* vdt2, double dt,
+                    void* stream);
+
+/* Host helper: peak eta = (dt/2) * sigma_max of a quadratic absorbing layer
+ * of `width` cells with target normal-incidence reflection R, where
+ * sigma_max = 3 vmax ln(1/R) / (2 width d) (Collino & Tsogka 2001).
+ * Returns 0 for width <= 0, negative FD_EINVAL on bad input. */
+double fd_sponge_eta_max(double vmax, double d, double dt, int32_t width, double R);
+
+/* Host helper: eta(i) = eta_max * (delta(i)/width)^2 for i < n, where
+ * delta(i) = max(width - i, i - (n-1-width), 0); all zeros for width <= 0.
+ * host_out has n floats. */
+int fd_sponge_profile(float* host_out, int32_t n, int32_t width, double eta_max);
+
+/* Host helper: Ricker wavelet w[n] = (1 - 2a) exp(-a), a = (pi f0 (t-t0))^2,
+ * t = (n0+n)*dt, evaluated in FP64 and stored as FP32; host_out has nt floats. */
+int fd_ricker(float* host_out, int32_t nt, int32_t n0, double dt, double f0, double t0);
+
+/* Host helper: element offsets of nrec receivers given as (i,j,k) triples
+ * (3*nrec int32, host) into off_host (nrec int64, host).  FD_EINVAL if a
+ * receiver lies outside the interior. */
+int fd_receiver_offsets(const fd_grid* g, const int32_t* ijk_host, int32_t nrec,
+                        int64_t* off_host);
+
+/* ------------------------------------------------------- per-step path */
+
+/* S4: one leapfrog update of every interior point,
+ *   u_next = (2u - (1-eta) u_prev + vdt2 * L u) / (1+eta)
+ * (eta = 0 without a sponge).  L reads u's face halos as they are (zeros for
+ * a Dirichlet boundary, or what halo_unpack wrote).  Reads only interior
+ * points of u_prev and vdt2; writes only interior points of u_next.
+ * u_next may alias u_prev (in-place two-array stepping); it must not overlap
+ * u.  sp may be NULL. */
+int fd_step(const fd_grid* g, const float* u_prev, const float* u, float* u_next,
+            const float* vdt2, const fd_sponge* sp, void* stream);
+
+/* S5: u_next[s] += vdt2[s] * w / (1+eta[s]) at interior point s = (i,j,k). */
+int inject_source(const fd_grid* g, float* u_next, const float* vdt2,
+                  const fd_sponge* sp, int32_t i, int32_t j, int32_t k, float w,
+                  void* stream);
+
+/* S6: trace_row[r] = u[rec_off[r]] for r < nrec (rec_off: device int64
+ * element offsets, e.g. from fd_receiver_offsets; trace_row: device). */
+int record_receivers(const fd_grid* g, const float* u, const int64_t* rec_off,
+                     int32_t nrec, float* trace_row, void* stream);
+
+/* S1: copy the 4 outermost interior planes of u on each face into the six
+ * contiguous device buffers face[0..5] = -x,+x,-y,+y,-z,+z (the data a halo
+ * exchange sends to the neighbour on that side).  Layouts, x fastest, q = 0..3
+ * counting from the lower index:
+ *   -x, +x: [nz][ny][4], -x holds i = q, +x holds i = nx-4+q;
+ *   -y, +y: [nz][4][nx], -y holds j = q, +y holds j = ny-4+q;
+ *   -z, +z: [4][ny][nx], -z holds k = q, +z holds k = nz-4+q.
+ * A NULL face is skipped.  Faces need n >= 4 on their axis (else FD_EINVAL). */
+int halo_pack(const fd_grid* g, const float* u, float* const face[6], void* stream);
+
+/* S3: write six receive buffers (same layouts as halo_pack) into the face
+ * halos of u: face[0] (-x, from the -x neighbour's +x face) fills
+ * i = -4+q, face[1] (+x) fills i = nx+q, and likewise for y and z.  Edges and
+ * corners of the halo are never touched.  A NULL face leaves that halo as it
+ * is.  Passing {send[1],send[0],send[3],send[2],send[5],send[4]} of a
+ * halo_pack of the same u gives periodic boundaries (single-device loopback). */
+int halo_unpack(const fd_grid* g, float* u, const float* const face[6], void* stream);
+
+/* ----------------------------------------------------------- adjoint
+ * Transpose of the forward step, for the FWI gradient with respect to
+ * squared slowness.  With D = 1/(1+eta), E = 1-eta, Q = vdt2, the forward
+ * step is u^{n+1} = D (2u^n - E u^{n-1} + Q (L u^n + f^n)). */
+
+/* S11: a_out = 2 D a_n1 + L(Q D a_n1) - E D a_nn on the interior, where the
+ * halo of Q D a_n1 is taken from a_n1's halo (as given: zero for Dirichlet),
+ * vdt2's halo (as fd_prepare_vdt2 writes it) and eta at the periodic image.
+ * a_nn may be NULL (treated as zero).  a_out may alias a_nn, never a_n1.
+ * If g_vdt2 is non-NULL, also g_vdt2 += D a_n1 (L u_n + f) with u_n's halo as
+ * given and f = src->w at src (src may be NULL: no source term); u_n must
+ * then be non-NULL. */
+int fd_adjoint_step(const fd_grid* g, const float* a_nn, const float* a_n1,
+                    float* a_out, const float* vdt2, const fd_sponge* sp,
+                    const float* u_n, float* g_vdt2, const fd_source* src,
+                    void* stream);
+
+/* a[off[r]] += vals[r] for r < n (device arrays; duplicate offsets add). */
+int fd_scatter_add(const fd_grid* g, float* a, const int64_t* off, const float* vals,
+                   int32_t n, void* stream);
+
+/* grad_m = -g_vdt2 * vdt2^2 / dt^2 on the interior (m = 1/v^2, dt fixed). */
+int fd_grad_finalize(const fd_grid* g, const float* g_vdt2, const float* vdt2,
+                     double dt, float* grad_m, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FD_H */

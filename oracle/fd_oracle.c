@@ -278,15 +278,15 @@ void ora_step_points(int nx, int ny, int nz, double dx, double dy, double dz,
   const int n3[3] = {nx, ny, nz};
 #pragma omp parallel for schedule(static)
   for (int p = 0; p < npts; ++p) {
-    int q[3] = {pts[3 * p], pts[3 * p + 1], pts[3 * p + 2]};
-    int64_t c = ((int64_t)q[2] * ny + q[1]) * nx + q[0];
+    int pt[3] = {pts[3 * p], pts[3 * p + 1], pts[3 * p + 2]};
+    int64_t c = ((int64_t)pt[2] * ny + pt[1]) * nx + pt[0];
     double lap = 0.0;
     for (int a = 0; a < 3; ++a) {
       double s = CM[0] * (double)u[c];
       for (int m = 1; m <= 4; ++m) {
         double pair = 0.0;
         for (int sgn = -1; sgn <= 1; sgn += 2) {
-          int r[3] = {q[0], q[1], q[2]};
+          int r[3] = {pt[0], pt[1], pt[2]};
           r[a] += sgn * m;
           if (r[a] < 0 || r[a] >= n3[a]) {
             if (!periodic) continue;
@@ -298,10 +298,10 @@ void ora_step_points(int nx, int ny, int nz, double dx, double dy, double dz,
       }
       lap += s * id2[a];
     }
-    double eta = eta_at(ex, ey, ez, q[0], q[1], q[2]);
+    double eta = eta_at(ex, ey, ez, pt[0], pt[1], pt[2]);
     double vdt2 = q[c];
     double r = (2.0 * (double)u[c] - (1.0 - eta) * (double)up[c] + vdt2 * lap) / (1.0 + eta);
-    if (q[0] == si && q[1] == sj && q[2] == sk) r += vdt2 * w_src / (1.0 + eta);
+    if (pt[0] == si && pt[1] == sj && pt[2] == sk) r += vdt2 * w_src / (1.0 + eta);
     out[p] = r;
   }
 }

@@ -1,0 +1,310 @@
+"""Torch-facing wrappers of the libfd C ABI.
+
+Torch only allocates device memory and supplies the current HIP stream; every step of
+the computation runs in the library's HIP kernels.  All tensors are float32 on a ROCm
+device.  Volume tensors are flat buffers of ``Grid.elems`` floats in the library's
+padded layout (x fastest, 4-point halo); ``Grid.interior`` / ``Grid.padded`` give
+strided views of them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, fd_grid, fd_source, fd_sponge, lib
+
+COURANT = 0.4
+RICKER_F0 = 15.0
+SPONGE_R = 1e-3
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+class Grid:
+    """One subdomain geometry (``fd_grid``): interior ``nx*ny*nz``, spacing ``d``."""
+
+    def __init__(self, nx: int, ny: int, nz: int, d=(10.0, 10.0, 10.0)):
+        self.c = fd_grid()
+        check(lib().fd_grid_init(C.byref(self.c), nx, ny, nz, *map(float, d)), "fd_grid_init")
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.d = tuple(float(x) for x in d)
+        self.elems = check(lib().fd_grid_elems(C.byref(self.c)), "fd_grid_elems")
+        self.ref = C.byref(self.c)
+
+    @property
+    def origin(self) -> int:
+        return self.c.origin
+
+    @property
+    def strides(self) -> tuple[int, int]:
+        return self.c.ystride, self.c.zstride
+
+    def face_elems(self, face: int) -> int:
+        return check(lib().fd_face_elems(self.ref, face), "fd_face_elems")
+
+    def zeros(self, device="cuda") -> torch.Tensor:
+        return torch.zeros(self.elems, dtype=torch.float32, device=device)
+
+    def interior(self, t: torch.Tensor) -> torch.Tensor:
+        ys, zs = self.strides
+        return t.as_strided((self.nz, self.ny, self.nx), (zs, ys, 1), self.origin)
+
+    def padded(self, t: torch.Tensor) -> torch.Tensor:
+        ys, zs = self.strides
+        return t.as_strided((self.nz + 8, self.ny + 8, self.nx + 8), (zs, ys, 1),
+                            self.origin - 4 * zs - 4 * ys - 4)
+
+    def check(self, t: torch.Tensor, name: str):
+        if t is None:
+            return
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
+            raise TypeError(f"{name}: expected a float32 ROCm tensor")
+        if not t.is_contiguous() or t.numel() < self.elems:
+            raise ValueError(f"{name}: expected a contiguous buffer of >= {self.elems} floats")
+
+    def offsets(self, ijk: np.ndarray) -> np.ndarray:
+        ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
+        out = np.empty(ijk.shape[0], dtype=np.int64)
+        check(lib().fd_receiver_offsets(self.ref, ijk.ctypes.data, ijk.shape[0],
+                                        out.ctypes.data), "fd_receiver_offsets")
+        return out
+
+
+class Sponge:
+    """Damping tables eta_x, eta_y, eta_z on the device (``fd_sponge``)."""
+
+    def __init__(self, grid: Grid, width: int, vmax: float, dt: float, R: float = SPONGE_R,
+                 device="cuda"):
+        self.width = width
+        tabs = []
+        for n, d in zip((grid.nx, grid.ny, grid.nz), grid.d):
+            emax = lib().fd_sponge_eta_max(vmax, d, dt, width, R)
+            if emax < 0:
+                check(int(emax), "fd_sponge_eta_max")
+            h = np.empty(n, dtype=np.float32)
+            check(lib().fd_sponge_profile(h.ctypes.data, n, width, emax), "fd_sponge_profile")
+            tabs.append(torch.from_numpy(h).to(device))
+        self.eta_x, self.eta_y, self.eta_z = tabs
+        self.c = fd_sponge(self.eta_x.data_ptr(), self.eta_y.data_ptr(), self.eta_z.data_ptr())
+        self.ref = C.byref(self.c)
+
+
+def sponge_ref(sp: Sponge | None):
+    return None if sp is None else sp.ref
+
+
+# ----------------------------------------------------------------- set-up (S0)
+
+def cfl_dt(grid: Grid, v: torch.Tensor, courant: float = COURANT, stream=None):
+    """(dt, vmax) from a device reduction of max(v); synchronises the stream."""
+    grid.check(v, "v")
+    scratch = torch.empty(2, dtype=torch.int32, device=v.device)
+    vmax = C.c_double()
+    dt = C.c_double()
+    check(lib().fd_cfl_dt(grid.ref, v.data_ptr(), courant, scratch.data_ptr(), C.byref(vmax),
+                          C.byref(dt), _stream(stream)), "fd_cfl_dt")
+    return dt.value, vmax.value
+
+
+def prepare_vdt2(grid: Grid, v: torch.Tensor, vdt2: torch.Tensor, dt: float, stream=None):
+    grid.check(v, "v")
+    grid.check(vdt2, "vdt2")
+    check(lib().fd_prepare_vdt2(grid.ref, v.data_ptr(), vdt2.data_ptr(), dt, _stream(stream)),
+          "fd_prepare_vdt2")
+
+
+def ricker(nt: int, dt: float, f0: float = RICKER_F0, t0: float | None = None,
+           n0: int = 0) -> np.ndarray:
+    if t0 is None:
+        t0 = 1.0 / f0
+    w = np.empty(max(nt, 1), dtype=np.float32)
+    check(lib().fd_ricker(w.ctypes.data, nt, n0, dt, f0, t0), "fd_ricker")
+    return w[:nt]
+
+
+# ----------------------------------------------------------------- per-step path
+
+def step(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None = None, stream=None):
+    for n, t in (("u_prev", u_prev), ("u", u), ("u_next", u_next), ("vdt2", vdt2)):
+        grid.check(t, n)
+    check(lib().fd_step(grid.ref, u_prev.data_ptr(), u.data_ptr(), u_next.data_ptr(),
+                        vdt2.data_ptr(), sponge_ref(sponge), _stream(stream)), "fd_step")
+
+
+def inject_source(grid: Grid, u_next, vdt2, sponge, ijk, w: float, stream=None):
+    grid.check(u_next, "u_next")
+    grid.check(vdt2, "vdt2")
+    i, j, k = (int(x) for x in ijk)
+    check(lib().inject_source(grid.ref, u_next.data_ptr(), vdt2.data_ptr(), sponge_ref(sponge),
+                              i, j, k, float(w), _stream(stream)), "inject_source")
+
+
+def record_receivers(grid: Grid, u, rec_off: torch.Tensor, trace_row: torch.Tensor,
+                     stream=None):
+    grid.check(u, "u")
+    n = rec_off.numel()
+    if rec_off.dtype != torch.int64 or trace_row.dtype != torch.float32 or trace_row.numel() < n:
+        raise TypeError("record_receivers: rec_off int64, trace_row float32 of >= nrec")
+    check(lib().record_receivers(grid.ref, u.data_ptr(), rec_off.data_ptr(), n,
+                                 trace_row.data_ptr(), _stream(stream)), "record_receivers")
+
+
+def _faces(faces):
+    arr = _lib._FACES()
+    for i in range(6):
+        f = faces[i]
+        arr[i] = None if f is None else f.data_ptr()
+    return arr
+
+
+def halo_pack(grid: Grid, u, faces, stream=None):
+    grid.check(u, "u")
+    check(lib().halo_pack(grid.ref, u.data_ptr(), _faces(faces), _stream(stream)), "halo_pack")
+
+
+def halo_unpack(grid: Grid, u, faces, stream=None):
+    grid.check(u, "u")
+    check(lib().halo_unpack(grid.ref, u.data_ptr(), _faces(faces), _stream(stream)),
+          "halo_unpack")
+
+
+def face_buffers(grid: Grid, device="cuda"):
+    return [torch.zeros(grid.face_elems(f), dtype=torch.float32, device=device)
+            for f in range(6)]
+
+
+def loopback(faces):
+    """Receive buffers of a single-device exchange: each face receives what the
+    opposite face sent, which makes the subdomain periodic."""
+    return [faces[1], faces[0], faces[3], faces[2], faces[5], faces[4]]
+
+
+# ----------------------------------------------------------------- adjoint
+
+def adjoint_step(grid: Grid, a_nn, a_n1, a_out, vdt2, sponge=None, u_n=None, g_vdt2=None,
+                 src=None, stream=None):
+    for n, t in (("a_nn", a_nn), ("a_n1", a_n1), ("a_out", a_out), ("vdt2", vdt2),
+                 ("u_n", u_n), ("g_vdt2", g_vdt2)):
+        grid.check(t, n)
+    sref = None
+    if src is not None:
+        (i, j, k), w = src
+        sref = C.byref(fd_source(int(i), int(j), int(k), float(w)))
+    check(lib().fd_adjoint_step(grid.ref, _ptr(a_nn), a_n1.data_ptr(), a_out.data_ptr(),
+                                vdt2.data_ptr(), sponge_ref(sponge), _ptr(u_n), _ptr(g_vdt2),
+                                sref, _stream(stream)), "fd_adjoint_step")
+
+
+def scatter_add(grid: Grid, a, off: torch.Tensor, vals: torch.Tensor, stream=None):
+    grid.check(a, "a")
+    check(lib().fd_scatter_add(grid.ref, a.data_ptr(), off.data_ptr(), vals.data_ptr(),
+                               off.numel(), _stream(stream)), "fd_scatter_add")
+
+
+def grad_finalize(grid: Grid, g_vdt2, vdt2, dt: float, grad_m, stream=None):
+    for n, t in (("g_vdt2", g_vdt2), ("vdt2", vdt2), ("grad_m", grad_m)):
+        grid.check(t, n)
+    check(lib().fd_grad_finalize(grid.ref, g_vdt2.data_ptr(), vdt2.data_ptr(), dt,
+                                 grad_m.data_ptr(), _stream(stream)), "fd_grad_finalize")
+
+
+def set_kchunk(kchunk: int):
+    check(lib().fd_set_kchunk(int(kchunk)), "fd_set_kchunk")
+
+
+# ----------------------------------------------------------------- forward model
+
+@dataclass
+class Geometry:
+    """Source and receivers of one shot (0-based interior indices)."""
+    src: tuple[int, int, int] | None = None
+    rec: np.ndarray | None = None  # int32 (nrec, 3)
+    f0: float = RICKER_F0
+    t0: float | None = None
+
+
+class Simulation:
+    """Forward model of one subdomain: S0 set-up once, then S1-S7 per step.
+
+    ``exchange="loopback"`` packs the six faces of u^n each step and unpacks each
+    into the opposite halo (periodic subdomain); ``None`` keeps zero (Dirichlet)
+    halos.  The wavefields stay on the device; ``run`` returns device traces."""
+
+    def __init__(self, v: np.ndarray | torch.Tensor, d=(10.0, 10.0, 10.0),
+                 courant: float = COURANT, sponge_width: int = 0, geom: Geometry | None = None,
+                 exchange: str | None = None, dt: float | None = None, device="cuda",
+                 sponge_vmax: float | None = None):
+        nz, ny, nx = v.shape
+        self.grid = g = Grid(nx, ny, nz, d)
+        self.device = device
+        vt = g.zeros(device)
+        g.interior(vt).copy_(torch.as_tensor(v, dtype=torch.float32))
+        self.v = vt
+        dt_cfl, vmax = cfl_dt(g, vt, courant)
+        self.vmax = vmax
+        self.dt = dt_cfl if dt is None else float(dt)
+        self.vdt2 = g.zeros(device)
+        prepare_vdt2(g, vt, self.vdt2, self.dt)
+        self.sponge = (Sponge(g, sponge_width, vmax if sponge_vmax is None else sponge_vmax,
+                              self.dt, device=device) if sponge_width > 0 else None)
+        self.geom = geom or Geometry()
+        self.u_prev = g.zeros(device)
+        self.u = g.zeros(device)
+        self.u_next = g.zeros(device)
+        self.n = 0
+        self.exchange = exchange
+        if exchange not in (None, "loopback"):
+            raise ValueError("exchange must be None or 'loopback'")
+        self.send = face_buffers(g, device) if exchange else None
+        self.recv = loopback(self.send) if exchange else None
+        rec = self.geom.rec
+        if rec is not None and len(rec):
+            self.rec_off = torch.from_numpy(g.offsets(rec)).to(device)
+        else:
+            self.rec_off = None
+
+    @property
+    def nrec(self) -> int:
+        return 0 if self.rec_off is None else self.rec_off.numel()
+
+    def run(self, nt: int, traces: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Advance ``nt`` steps; returns (nt, nrec) device traces (u^{n+1} at receivers)."""
+        g = self.grid
+        if traces is None:
+            traces = torch.zeros((nt, max(self.nrec, 1)), dtype=torch.float32, device=self.device)
+        geom = self.geom
+        w = None
+        if geom.src is not None:
+            w = ricker(nt, self.dt, geom.f0, geom.t0, n0=self.n)
+        for s in range(nt):
+            if self.exchange:
+                halo_pack(g, self.u, self.send, stream)
+                halo_unpack(g, self.u, self.recv, stream)
+            step(g, self.u_prev, self.u, self.u_next, self.vdt2, self.sponge, stream)
+            if w is not None:
+                inject_source(g, self.u_next, self.vdt2, self.sponge, geom.src, float(w[s]), stream)
+            if self.rec_off is not None:
+                record_receivers(g, self.u_next, self.rec_off, traces[s], stream)
+            self.u_prev, self.u, self.u_next = self.u, self.u_next, self.u_prev
+            self.n += 1
+        return traces[:, :self.nrec]
+
+    def state(self):
+        """Interior views of (u^{n-1}, u^n)."""
+        return self.grid.interior(self.u_prev), self.grid.interior(self.u)

@@ -1,0 +1,402 @@
+// fd_abi.cpp -- the C ABI of libfd: argument validation, error reporting,
+// geometry and the small host-side set-up helpers.  Every entry point checks
+// its arguments before enqueuing anything and converts HIP errors to
+// FD_EDEVICE; no C++ exception escapes.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <limits>
+
+#include "fd_internal.h"
+
+namespace fd {
+
+static thread_local char t_err[512];
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(t_err, sizeof(t_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return FD_OK;
+  return fail(FD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// 8th-order weights (exact rationals) of the second derivative on unit spacing.
+static const double kC[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+Coef make_coef(const fd_grid* g) {
+  Coef c;
+  const double ix = 1.0 / (g->dx * g->dx), iy = 1.0 / (g->dy * g->dy), iz = 1.0 / (g->dz * g->dz);
+  c.cx[0] = c.cy[0] = c.cz[0] = 0.f;
+  for (int m = 1; m <= 4; ++m) {
+    c.cx[m] = (float)(kC[m] * ix);
+    c.cy[m] = (float)(kC[m] * iy);
+    c.cz[m] = (float)(kC[m] * iz);
+  }
+  c.cc = (float)(kC[0] * (ix + iy + iz));
+  return c;
+}
+
+void set_kchunk_override(int kc);
+
+}  // namespace fd
+
+using namespace fd;
+
+namespace {
+
+bool finite_pos(double d) { return isfinite(d) && d > 0.0; }
+
+int check_grid(const fd_grid* g) {
+  if (!g) return fail(FD_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+    return fail(FD_EINVAL, "interior extent %d x %d x %d: each must be >= 1", g->nx, g->ny, g->nz);
+  if (g->nx > (1 << 24) || g->ny > 65000 || g->nz > 65000)
+    return fail(FD_EINVAL, "interior extent %d x %d x %d too large", g->nx, g->ny, g->nz);
+  if (g->halo != FD_HALO) return fail(FD_EINVAL, "halo is %d, must be %d", g->halo, FD_HALO);
+  if (g->ystride < (int64_t)g->nx + 8)
+    return fail(FD_EINVAL, "ystride %lld < nx+8", (long long)g->ystride);
+  if (g->zstride < g->ystride * ((int64_t)g->ny + 8))
+    return fail(FD_EINVAL, "zstride %lld < ystride*(ny+8)", (long long)g->zstride);
+  if (g->zstride > (int64_t)std::numeric_limits<int32_t>::max())
+    return fail(FD_EINVAL, "zstride %lld exceeds INT32_MAX", (long long)g->zstride);
+  if (g->origin < 4 * g->zstride + 4 * g->ystride + 4)
+    return fail(FD_EINVAL, "origin %lld leaves no room for the halo", (long long)g->origin);
+  if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dz))
+    return fail(FD_EINVAL, "grid spacing must be finite and > 0");
+  return FD_OK;
+}
+
+int check_sponge(const fd_sponge* sp, const float** ex, const float** ey, const float** ez) {
+  *ex = *ey = *ez = nullptr;
+  if (!sp) return FD_OK;
+  const int n = (sp->eta_x != nullptr) + (sp->eta_y != nullptr) + (sp->eta_z != nullptr);
+  if (n == 0) return FD_OK;
+  if (n != 3) return fail(FD_EINVAL, "sponge: give all three eta tables or none");
+  *ex = sp->eta_x;
+  *ey = sp->eta_y;
+  *ez = sp->eta_z;
+  return FD_OK;
+}
+
+int64_t last_elem(const fd_grid* g) {
+  return g->origin + (int64_t)(g->nz + 3) * g->zstride + (int64_t)(g->ny + 3) * g->ystride +
+         g->nx + 3;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Two volume arrays of one grid overlap iff their padded extents intersect.
+bool overlaps(const fd_grid* g, const float* a, const float* b) {
+  if (!a || !b) return false;
+  const int64_t n = last_elem(g) + 1;
+  return a < b + n && b < a + n;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fd_strerror(int code) {
+  switch (code) {
+    case FD_OK: return "success";
+    case FD_ENOTFOUND: return "not found";
+    case FD_EDEVICE: return "device (HIP) error";
+    case FD_EAGAIN: return "not finished yet";
+    case FD_ENOMEM: return "out of memory";
+    case FD_EINVAL: return "invalid argument";
+    case FD_ECANCELED: return "cancelled";
+    default: return "unknown error code";
+  }
+}
+
+const char* fd_last_error(void) { return t_err; }
+
+int fd_version(void) { return 10000; }
+
+int fd_grid_init(fd_grid* g, int32_t nx, int32_t ny, int32_t nz, double dx, double dy,
+                 double dz) {
+  if (!g) return fail(FD_EINVAL, "grid is NULL");
+  fd_grid t;
+  t.nx = nx;
+  t.ny = ny;
+  t.nz = nz;
+  t.halo = FD_HALO;
+  t.dx = dx;
+  t.dy = dy;
+  t.dz = dz;
+  if (nx < 1 || ny < 1 || nz < 1) return fail(FD_EINVAL, "interior extent must be >= 1");
+  const int64_t pad = 32;  // left padding: 128 bytes, the last 4 floats are the x halo
+  const int64_t row = ((pad + nx + 4) + 31) / 32 * 32;
+  t.ystride = row;
+  t.zstride = row * ((int64_t)ny + 8);
+  t.origin = 4 * t.zstride + 4 * t.ystride + pad;
+  const int rc = check_grid(&t);
+  if (rc != FD_OK) return rc;
+  *g = t;
+  return FD_OK;
+}
+
+int64_t fd_grid_elems(const fd_grid* g) {
+  if (check_grid(g) != FD_OK) return -1;
+  return last_elem(g) + 1;
+}
+
+int64_t fd_face_elems(const fd_grid* g, int32_t face) {
+  if (check_grid(g) != FD_OK) return -1;
+  switch (face) {
+    case 0: case 1: return 4LL * g->ny * g->nz;
+    case 2: case 3: return 4LL * g->nx * g->nz;
+    case 4: case 5: return 4LL * g->nx * g->ny;
+    default: fail(FD_EINVAL, "face %d not in 0..5", face); return -1;
+  }
+}
+
+int64_t fd_offset(const fd_grid* g, int32_t i, int32_t j, int32_t k) {
+  if (check_grid(g) != FD_OK) return -1;
+  if (i < -4 || i >= g->nx + 4 || j < -4 || j >= g->ny + 4 || k < -4 || k >= g->nz + 4) {
+    fail(FD_EINVAL, "point (%d,%d,%d) outside the padded box", i, j, k);
+    return -1;
+  }
+  return g->origin + (int64_t)k * g->zstride + (int64_t)j * g->ystride + i;
+}
+
+int fd_set_kchunk(int32_t kchunk) {
+  if (kchunk < 0) return fail(FD_EINVAL, "kchunk must be >= 0 (0 = automatic)");
+  set_kchunk_override(kchunk);
+  return FD_OK;
+}
+
+int fd_cfl_dt(const fd_grid* g, const float* v, double courant, int32_t* scratch_dev,
+              double* vmax_host, double* dt_out, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!v || !scratch_dev) return fail(FD_EINVAL, "fd_cfl_dt: NULL array");
+  if (!finite_pos(courant)) return fail(FD_EINVAL, "fd_cfl_dt: courant must be > 0");
+  hipStream_t s = as_stream(stream);
+  rc = check_hip(launch_vmax(make_geo(g), v, scratch_dev, s), "vmax launch");
+  if (rc) return rc;
+  int32_t host[2];
+  rc = check_hip(hipMemcpyAsync(host, scratch_dev, sizeof(host), hipMemcpyDeviceToHost, s),
+                 "vmax copy");
+  if (rc) return rc;
+  rc = check_hip(hipStreamSynchronize(s), "vmax sync");
+  if (rc) return rc;
+  float vmax, vmin;
+  memcpy(&vmax, &host[0], 4);
+  memcpy(&vmin, &host[1], 4);
+  if (!(isfinite(vmax) && vmax > 0.f) || !(vmin > 0.f))
+    return fail(FD_EINVAL, "velocity must be finite and > 0 (max %g, min %g)", vmax, vmin);
+  double dmin = g->dx;
+  if (g->dy < dmin) dmin = g->dy;
+  if (g->dz < dmin) dmin = g->dz;
+  if (vmax_host) *vmax_host = vmax;
+  if (dt_out) *dt_out = courant * dmin / (double)vmax;
+  return FD_OK;
+}
+
+int fd_prepare_vdt2(const fd_grid* g, const float* v, float* vdt2, double dt, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!v || !vdt2) return fail(FD_EINVAL, "fd_prepare_vdt2: NULL array");
+  if (overlaps(g, v, vdt2)) return fail(FD_EINVAL, "fd_prepare_vdt2: v and vdt2 overlap");
+  if (!finite_pos(dt)) return fail(FD_EINVAL, "fd_prepare_vdt2: dt must be > 0");
+  return check_hip(launch_prepare_vdt2(make_geo(g), v, vdt2, dt, as_stream(stream)),
+                   "prepare_vdt2 launch");
+}
+
+double fd_sponge_eta_max(double vmax, double d, double dt, int32_t width, double R) {
+  if (width <= 0) return 0.0;
+  if (!finite_pos(vmax) || !finite_pos(d) || !finite_pos(dt) || !(R > 0.0 && R < 1.0))
+    return (double)fail(FD_EINVAL, "fd_sponge_eta_max: bad argument");
+  const double sigma_max = 3.0 * vmax * log(1.0 / R) / (2.0 * (double)width * d);
+  return 0.5 * dt * sigma_max;
+}
+
+int fd_sponge_profile(float* host_out, int32_t n, int32_t width, double eta_max) {
+  if (!host_out || n < 1) return fail(FD_EINVAL, "fd_sponge_profile: bad output");
+  if (!(eta_max >= 0.0) || !isfinite(eta_max))
+    return fail(FD_EINVAL, "fd_sponge_profile: eta_max must be finite and >= 0");
+  for (int32_t i = 0; i < n; ++i) {
+    double e = 0.0;
+    if (width > 0) {
+      int32_t d = width - i;
+      const int32_t d2 = i - (n - 1 - width);
+      if (d2 > d) d = d2;
+      if (d > 0) {
+        const double r = (double)d / (double)width;
+        e = eta_max * r * r;
+      }
+    }
+    host_out[i] = (float)e;
+  }
+  return FD_OK;
+}
+
+int fd_ricker(float* host_out, int32_t nt, int32_t n0, double dt, double f0, double t0) {
+  if (!host_out || nt < 0) return fail(FD_EINVAL, "fd_ricker: bad output");
+  if (!finite_pos(dt) || !finite_pos(f0) || !isfinite(t0))
+    return fail(FD_EINVAL, "fd_ricker: bad dt, f0 or t0");
+  const double pi = 3.14159265358979323846;
+  for (int32_t n = 0; n < nt; ++n) {
+    const double t = (double)(n0 + n) * dt - t0;
+    const double a = (pi * f0 * t) * (pi * f0 * t);
+    host_out[n] = (float)((1.0 - 2.0 * a) * exp(-a));
+  }
+  return FD_OK;
+}
+
+int fd_receiver_offsets(const fd_grid* g, const int32_t* ijk, int32_t nrec, int64_t* off) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (nrec < 0 || (nrec > 0 && (!ijk || !off)))
+    return fail(FD_EINVAL, "fd_receiver_offsets: bad arrays");
+  for (int32_t r = 0; r < nrec; ++r) {
+    const int32_t i = ijk[3 * r], j = ijk[3 * r + 1], k = ijk[3 * r + 2];
+    if (i < 0 || i >= g->nx || j < 0 || j >= g->ny || k < 0 || k >= g->nz)
+      return fail(FD_EINVAL, "receiver %d at (%d,%d,%d) is outside the interior", r, i, j, k);
+    off[r] = g->origin + (int64_t)k * g->zstride + (int64_t)j * g->ystride + i;
+  }
+  return FD_OK;
+}
+
+int fd_step(const fd_grid* g, const float* u_prev, const float* u, float* u_next,
+            const float* vdt2, const fd_sponge* sp, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!u_prev || !u || !u_next || !vdt2) return fail(FD_EINVAL, "fd_step: NULL array");
+  if (overlaps(g, u, u_next)) return fail(FD_EINVAL, "fd_step: u_next overlaps u");
+  if (overlaps(g, vdt2, u_next)) return fail(FD_EINVAL, "fd_step: u_next overlaps vdt2");
+  if (u_next != u_prev && overlaps(g, u_prev, u_next))
+    return fail(FD_EINVAL, "fd_step: u_next partially overlaps u_prev");
+  const float *ex, *ey, *ez;
+  rc = check_sponge(sp, &ex, &ey, &ez);
+  if (rc) return rc;
+  return check_hip(launch_step(make_geo(g), make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez,
+                               as_stream(stream)),
+                   "fd_step launch");
+}
+
+int inject_source(const fd_grid* g, float* u_next, const float* vdt2, const fd_sponge* sp,
+                  int32_t i, int32_t j, int32_t k, float w, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!u_next || !vdt2) return fail(FD_EINVAL, "inject_source: NULL array");
+  if (i < 0 || i >= g->nx || j < 0 || j >= g->ny || k < 0 || k >= g->nz)
+    return fail(FD_EINVAL, "inject_source: (%d,%d,%d) outside the interior", i, j, k);
+  const float *ex, *ey, *ez;
+  rc = check_sponge(sp, &ex, &ey, &ez);
+  if (rc) return rc;
+  return check_hip(
+      launch_inject(make_geo(g), u_next, vdt2, ex, ey, ez, i, j, k, w, as_stream(stream)),
+      "inject_source launch");
+}
+
+int record_receivers(const fd_grid* g, const float* u, const int64_t* rec_off, int32_t nrec,
+                     float* trace_row, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (nrec < 0) return fail(FD_EINVAL, "record_receivers: nrec < 0");
+  if (nrec == 0) return FD_OK;
+  if (!u || !rec_off || !trace_row) return fail(FD_EINVAL, "record_receivers: NULL array");
+  return check_hip(launch_record(u, rec_off, nrec, trace_row, as_stream(stream)),
+                   "record_receivers launch");
+}
+
+static int check_faces(const fd_grid* g, const void* const* face, const char* who) {
+  if (!face) return fail(FD_EINVAL, "%s: face array is NULL", who);
+  const int n3[3] = {g->nx, g->ny, g->nz};
+  for (int f = 0; f < 6; ++f) {
+    if (!face[f]) continue;
+    if (n3[f / 2] < 4)
+      return fail(FD_EINVAL, "%s: face %d needs at least 4 interior planes on its axis", who, f);
+    if (fd_face_elems(g, f) > (int64_t)std::numeric_limits<int32_t>::max())
+      return fail(FD_EINVAL, "%s: face %d larger than INT32_MAX elements", who, f);
+  }
+  return FD_OK;
+}
+
+int halo_pack(const fd_grid* g, const float* u, float* const face[6], void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!u) return fail(FD_EINVAL, "halo_pack: u is NULL");
+  rc = check_faces(g, (const void* const*)face, "halo_pack");
+  if (rc) return rc;
+  return check_hip(launch_pack(make_geo(g), u, face, as_stream(stream)), "halo_pack launch");
+}
+
+int halo_unpack(const fd_grid* g, float* u, const float* const face[6], void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!u) return fail(FD_EINVAL, "halo_unpack: u is NULL");
+  rc = check_faces(g, (const void* const*)face, "halo_unpack");
+  if (rc) return rc;
+  return check_hip(launch_unpack(make_geo(g), u, face, as_stream(stream)),
+                   "halo_unpack launch");
+}
+
+int fd_adjoint_step(const fd_grid* g, const float* a_nn, const float* a_n1, float* a_out,
+                    const float* vdt2, const fd_sponge* sp, const float* u_n, float* g_vdt2,
+                    const fd_source* src, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!a_n1 || !a_out || !vdt2) return fail(FD_EINVAL, "fd_adjoint_step: NULL array");
+  if (overlaps(g, a_n1, a_out)) return fail(FD_EINVAL, "fd_adjoint_step: a_out overlaps a_n1");
+  if (overlaps(g, vdt2, a_out)) return fail(FD_EINVAL, "fd_adjoint_step: a_out overlaps vdt2");
+  if (a_nn && a_out != a_nn && overlaps(g, a_nn, a_out))
+    return fail(FD_EINVAL, "fd_adjoint_step: a_out partially overlaps a_nn");
+  if (g_vdt2) {
+    if (!u_n) return fail(FD_EINVAL, "fd_adjoint_step: gradient needs u_n");
+    if (overlaps(g, g_vdt2, a_out) || overlaps(g, g_vdt2, a_n1) || overlaps(g, g_vdt2, u_n) ||
+        overlaps(g, g_vdt2, vdt2) || (a_nn && overlaps(g, g_vdt2, a_nn)))
+      return fail(FD_EINVAL, "fd_adjoint_step: g_vdt2 overlaps another array");
+    if (src && (src->i < 0 || src->i >= g->nx || src->j < 0 || src->j >= g->ny || src->k < 0 ||
+                src->k >= g->nz))
+      return fail(FD_EINVAL, "fd_adjoint_step: source outside the interior");
+  }
+  const float *ex, *ey, *ez;
+  rc = check_sponge(sp, &ex, &ey, &ez);
+  if (rc) return rc;
+  const Geo geo = make_geo(g);
+  const Coef c = make_coef(g);
+  hipStream_t s = as_stream(stream);
+  // the gradient reads a_n1 pointwise and must see it before a_out (which may
+  // alias a_nn, not a_n1) is written; both kernels leave a_n1 untouched
+  if (g_vdt2) {
+    rc = check_hip(launch_grad(geo, c, u_n, a_n1, g_vdt2, ex, ey, ez, src, s), "gradient launch");
+    if (rc) return rc;
+  }
+  return check_hip(launch_adjoint(geo, c, a_nn, a_n1, a_out, vdt2, ex, ey, ez, s),
+                   "fd_adjoint_step launch");
+}
+
+int fd_scatter_add(const fd_grid* g, float* a, const int64_t* off, const float* vals, int32_t n,
+                   void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (n < 0) return fail(FD_EINVAL, "fd_scatter_add: n < 0");
+  if (n == 0) return FD_OK;
+  if (!a || !off || !vals) return fail(FD_EINVAL, "fd_scatter_add: NULL array");
+  return check_hip(launch_scatter_add(a, off, vals, n, as_stream(stream)),
+                   "fd_scatter_add launch");
+}
+
+int fd_grad_finalize(const fd_grid* g, const float* g_vdt2, const float* vdt2, double dt,
+                     float* grad_m, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!g_vdt2 || !vdt2 || !grad_m) return fail(FD_EINVAL, "fd_grad_finalize: NULL array");
+  if (!finite_pos(dt)) return fail(FD_EINVAL, "fd_grad_finalize: dt must be > 0");
+  if (overlaps(g, vdt2, grad_m)) return fail(FD_EINVAL, "fd_grad_finalize: grad_m overlaps vdt2");
+  return check_hip(launch_grad_finalize(make_geo(g), g_vdt2, vdt2, dt, grad_m, as_stream(stream)),
+                   "fd_grad_finalize launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,274 @@
+// fd_aux.hip -- the small kernels around the stencil: halo face pack/unpack,
+// source injection, receiver sampling, adjoint residual scatter, model prep
+// (vdt2 and max velocity) and the gradient's change of variable.
+#include "fd_internal.h"
+
+namespace fd {
+namespace {
+
+constexpr int BS = 256;
+
+struct Faces {
+  float* p[6];
+};
+struct CFaces {
+  const float* p[6];
+};
+
+__device__ __forceinline__ long long face_count(const Geo& g, int face) {
+  if (face < 2) return 4LL * g.ny * g.nz;
+  if (face < 4) return 4LL * g.nx * g.nz;
+  return 4LL * g.nx * g.ny;
+}
+
+// Interior coordinates (i,j,k) of element e of face buffer `face` in the
+// layouts of halo_pack; `q` in 0..3 counts planes from the lower index.
+__device__ __forceinline__ void face_coord(const Geo& g, int face, unsigned e, int& q, int& a,
+                                           int& b) {
+  if (face < 2) {  // [nz][ny][4]: a = j, b = k
+    q = e & 3u;
+    const unsigned t = e >> 2;
+    a = t % (unsigned)g.ny;
+    b = t / (unsigned)g.ny;
+  } else if (face < 4) {  // [nz][4][nx]: a = i, b = k
+    a = e % (unsigned)g.nx;
+    const unsigned t = e / (unsigned)g.nx;
+    q = t & 3u;
+    b = t >> 2;
+  } else {  // [4][ny][nx]: a = i, b = j
+    a = e % (unsigned)g.nx;
+    const unsigned t = e / (unsigned)g.nx;
+    b = t % (unsigned)g.ny;
+    q = t / (unsigned)g.ny;
+  }
+}
+
+__device__ __forceinline__ long long at(const Geo& g, int i, int j, int k) {
+  return g.org + (long long)k * g.sz + (long long)j * g.sy + i;
+}
+
+__global__ void __launch_bounds__(BS) pack_kernel(Geo g, const float* __restrict__ u, Faces f) {
+  const int face = blockIdx.y;
+  float* __restrict__ dst = f.p[face];
+  if (!dst) return;
+  const unsigned n = (unsigned)face_count(g, face);
+  for (unsigned e = blockIdx.x * BS + threadIdx.x; e < n; e += gridDim.x * BS) {
+    int q, a, b;
+    face_coord(g, face, e, q, a, b);
+    long long src;
+    switch (face) {
+      case 0: src = at(g, q, a, b); break;
+      case 1: src = at(g, g.nx - 4 + q, a, b); break;
+      case 2: src = at(g, a, q, b); break;
+      case 3: src = at(g, a, g.ny - 4 + q, b); break;
+      case 4: src = at(g, a, b, q); break;
+      default: src = at(g, a, b, g.nz - 4 + q); break;
+    }
+    dst[e] = u[src];
+  }
+}
+
+__global__ void __launch_bounds__(BS) unpack_kernel(Geo g, float* __restrict__ u, CFaces f) {
+  const int face = blockIdx.y;
+  const float* __restrict__ src = f.p[face];
+  if (!src) return;
+  const unsigned n = (unsigned)face_count(g, face);
+  for (unsigned e = blockIdx.x * BS + threadIdx.x; e < n; e += gridDim.x * BS) {
+    int q, a, b;
+    face_coord(g, face, e, q, a, b);
+    long long dst;
+    switch (face) {
+      case 0: dst = at(g, q - 4, a, b); break;
+      case 1: dst = at(g, g.nx + q, a, b); break;
+      case 2: dst = at(g, a, q - 4, b); break;
+      case 3: dst = at(g, a, g.ny + q, b); break;
+      case 4: dst = at(g, a, b, q - 4); break;
+      default: dst = at(g, a, b, g.nz + q); break;
+    }
+    u[dst] = src[e];
+  }
+}
+
+__global__ void inject_kernel(float* un, const float* q, const float* ex, const float* ey,
+                              const float* ez, long long o, int i, int j, int k, float w) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float eta = 0.f;
+  if (ex) eta = ex[i] + ey[j] + ez[k];
+  un[o] += q[o] * w / (1.f + eta);
+}
+
+__global__ void __launch_bounds__(BS) record_kernel(const float* __restrict__ u,
+                                                    const int64_t* __restrict__ off, int n,
+                                                    float* __restrict__ out) {
+  const int r = blockIdx.x * BS + threadIdx.x;
+  if (r < n) out[r] = u[off[r]];
+}
+
+__global__ void __launch_bounds__(BS) scatter_add_kernel(float* a, const int64_t* __restrict__ off,
+                                                         const float* __restrict__ vals, int n) {
+  const int r = blockIdx.x * BS + threadIdx.x;
+  if (r < n) atomicAdd(a + off[r], vals[r]);
+}
+
+// One thread per element of the padded box [-4,n+4)^3, one block row per
+// (j,k) line: interior from v, face halo from the periodic image, edges 0.
+__global__ void __launch_bounds__(BS) prep_vdt2_kernel(Geo g, const float* __restrict__ v,
+                                                       float* __restrict__ q, double dt) {
+  const int jj = blockIdx.y - 4;  // j in [-4, ny+4)
+  const int kk = blockIdx.z - 4;  // k in [-4, nz+4)
+  for (int ii = (int)(blockIdx.x * BS + threadIdx.x) - 4; ii < g.nx + 4; ii += gridDim.x * BS) {
+    const int oi = (ii < 0) + (ii >= g.nx);
+    const int oj = (jj < 0) + (jj >= g.ny);
+    const int ok = (kk < 0) + (kk >= g.nz);
+    float val = 0.f;
+    if (oi + oj + ok <= 1) {
+      const int si = ii < 0 ? ii + g.nx : (ii >= g.nx ? ii - g.nx : ii);
+      const int sj = jj < 0 ? jj + g.ny : (jj >= g.ny ? jj - g.ny : jj);
+      const int sk = kk < 0 ? kk + g.nz : (kk >= g.nz ? kk - g.nz : kk);
+      // a face halo wider than the axis wraps more than once
+      int ci = si, cj = sj, ck = sk;
+      while (ci < 0) ci += g.nx;
+      while (ci >= g.nx) ci -= g.nx;
+      while (cj < 0) cj += g.ny;
+      while (cj >= g.ny) cj -= g.ny;
+      while (ck < 0) ck += g.nz;
+      while (ck >= g.nz) ck -= g.nz;
+      const double vv = (double)v[at(g, ci, cj, ck)] * dt;
+      val = (float)(vv * vv);
+    }
+    q[at(g, ii, jj, kk)] = val;
+  }
+}
+
+__global__ void vmax_init_kernel(int32_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = 0;           // max of the float bit patterns (positive floats order as ints)
+    out[1] = 0x7f800000;  // min, starting at +inf
+  }
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+__global__ void __launch_bounds__(BS) vmax_kernel(Geo g, const float* __restrict__ v,
+                                                  int32_t* out) {
+  const long long nline = (long long)g.ny * g.nz;
+  int mx = 0, mn = 0x7f800000;
+  for (long long line = blockIdx.x; line < nline; line += gridDim.x) {
+    const int j = (int)(line % g.ny);
+    const int k = (int)(line / g.ny);
+    const float* row = v + at(g, 0, j, k);
+    for (int i = threadIdx.x; i < g.nx; i += BS) {
+      const int bits = __float_as_int(row[i]);
+      mx = max(mx, bits);
+      mn = min(mn, bits);
+    }
+  }
+  mx = wave_max(mx);
+  mn = wave_min(mn);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, mx);
+    atomicMin(out + 1, mn);
+  }
+}
+
+__global__ void __launch_bounds__(BS) grad_finalize_kernel(Geo g, const float* __restrict__ gq,
+                                                           const float* __restrict__ q, float s,
+                                                           float* __restrict__ gm) {
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  for (int i = blockIdx.x * BS + threadIdx.x; i < g.nx; i += gridDim.x * BS) {
+    const long long o = at(g, i, j, k);
+    const float qq = q[o];
+    gm[o] = -gq[o] * qq * qq * s;
+  }
+}
+
+unsigned blocks_for(long long n, unsigned cap) {
+  long long b = (n + BS - 1) / BS;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_pack(const Geo& g, const float* u, float* const face[6], hipStream_t s) {
+  Faces f;
+  long long mx = 0;
+  for (int i = 0; i < 6; ++i) {
+    f.p[i] = face[i];
+    const long long c = i < 2 ? 4LL * g.ny * g.nz : (i < 4 ? 4LL * g.nx * g.nz : 4LL * g.nx * g.ny);
+    if (face[i] && c > mx) mx = c;
+  }
+  if (mx == 0) return hipSuccess;
+  hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(mx, 4096), 6), dim3(BS), 0, s, g, u, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Geo& g, float* u, const float* const face[6], hipStream_t s) {
+  CFaces f;
+  long long mx = 0;
+  for (int i = 0; i < 6; ++i) {
+    f.p[i] = face[i];
+    const long long c = i < 2 ? 4LL * g.ny * g.nz : (i < 4 ? 4LL * g.nx * g.nz : 4LL * g.nx * g.ny);
+    if (face[i] && c > mx) mx = c;
+  }
+  if (mx == 0) return hipSuccess;
+  hipLaunchKernelGGL(unpack_kernel, dim3(blocks_for(mx, 4096), 6), dim3(BS), 0, s, g, u, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject(const Geo& g, float* un, const float* q, const float* ex,
+                         const float* ey, const float* ez, int i, int j, int k, float w,
+                         hipStream_t s) {
+  const long long o = g.org + (long long)k * g.sz + (long long)j * g.sy + i;
+  hipLaunchKernelGGL(inject_kernel, dim3(1), dim3(64), 0, s, un, q, ex, ey, ez, o, i, j, k, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_record(const float* u, const int64_t* off, int n, float* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(record_kernel, dim3((n + BS - 1) / BS), dim3(BS), 0, s, u, off, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_add(float* a, const int64_t* off, const float* vals, int n,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_add_kernel, dim3((n + BS - 1) / BS), dim3(BS), 0, s, a, off, vals,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_vdt2(const Geo& g, const float* v, float* q, double dt,
+                               hipStream_t s) {
+  const unsigned bx = blocks_for(g.nx + 8, 64);
+  hipLaunchKernelGGL(prep_vdt2_kernel, dim3(bx, g.ny + 8, g.nz + 8), dim3(BS), 0, s, g, v, q,
+                     dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_vmax(const Geo& g, const float* v, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(vmax_init_kernel, dim3(1), dim3(64), 0, s, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(vmax_kernel, dim3(2048), dim3(BS), 0, s, g, v, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_finalize(const Geo& g, const float* gq, const float* q, double dt,
+                                float* gm, hipStream_t s) {
+  const float sc = (float)(1.0 / (dt * dt));
+  hipLaunchKernelGGL(grad_finalize_kernel, dim3(blocks_for(g.nx, 64), g.ny, g.nz), dim3(BS), 0,
+                     s, g, gq, q, sc, gm);
+  return hipGetLastError();
+}
+
+}  // namespace fd

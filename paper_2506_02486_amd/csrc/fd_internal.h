@@ -1,0 +1,70 @@
+// fd_internal.h -- declarations shared by the host ABI layer and the HIP
+// kernel files of libfd (not installed, not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fd.h"
+
+namespace fd {
+
+// Thread-local error detail; returns `code` so callers can `return fail(...)`.
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+// Map a HIP error to FD_EDEVICE with detail, or FD_OK.
+int check_hip(hipError_t e, const char* what);
+
+// Geometry in the form the kernels take (by value).
+struct Geo {
+  int nx, ny, nz;
+  int sy;          // ystride (elements)
+  int sz;          // zstride (elements), <= INT32_MAX
+  long long org;   // origin (elements)
+};
+
+inline Geo make_geo(const fd_grid* g) {
+  Geo q;
+  q.nx = g->nx;
+  q.ny = g->ny;
+  q.nz = g->nz;
+  q.sy = (int)g->ystride;
+  q.sz = (int)g->zstride;
+  q.org = g->origin;
+  return q;
+}
+
+// Stencil weights divided by the squared spacing, rounded to FP32 from FP64:
+// cx[m], cy[m], cz[m] for m = 1..4 (index 0 unused) and the merged centre weight.
+struct Coef {
+  float cx[5], cy[5], cz[5];
+  float cc;
+};
+Coef make_coef(const fd_grid* g);
+
+// ------------------------------------------------------------ launchers
+// All validate nothing (the ABI layer has) and return a HIP error code.
+hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float* u,
+                       float* un, const float* q, const float* ex, const float* ey,
+                       const float* ez, hipStream_t s);
+hipError_t launch_adjoint(const Geo& g, const Coef& c, const float* ann, const float* an1,
+                          float* aout, const float* q, const float* ex, const float* ey,
+                          const float* ez, hipStream_t s);
+hipError_t launch_grad(const Geo& g, const Coef& c, const float* u, const float* an1,
+                       float* gq, const float* ex, const float* ey, const float* ez,
+                       const fd_source* src, hipStream_t s);
+hipError_t launch_inject(const Geo& g, float* un, const float* q, const float* ex,
+                         const float* ey, const float* ez, int i, int j, int k, float w,
+                         hipStream_t s);
+hipError_t launch_record(const float* u, const int64_t* off, int n, float* out,
+                         hipStream_t s);
+hipError_t launch_scatter_add(float* a, const int64_t* off, const float* vals, int n,
+                              hipStream_t s);
+hipError_t launch_pack(const Geo& g, const float* u, float* const face[6], hipStream_t s);
+hipError_t launch_unpack(const Geo& g, float* u, const float* const face[6], hipStream_t s);
+hipError_t launch_prepare_vdt2(const Geo& g, const float* v, float* q, double dt,
+                               hipStream_t s);
+hipError_t launch_vmax(const Geo& g, const float* v, int32_t* out, hipStream_t s);
+hipError_t launch_grad_finalize(const Geo& g, const float* gq, const float* q, double dt,
+                                float* gm, hipStream_t s);
+
+}  // namespace fd

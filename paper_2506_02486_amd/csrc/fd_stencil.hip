@@ -1,0 +1,435 @@
+// fd_stencil.hip -- the 25-point 8th-order star stencil on gfx950.
+//
+// One z-marching engine serves three operations:
+//   FWD  : u_next = (2u - (1-eta) u_prev + vdt2 * L u) / (1+eta)      (fd_step)
+//   ADJ  : a_out  = 2 D c + L(vdt2 D c) - E D a_nn,  D = 1/(1+eta),
+//          E = 1-eta, c = a^{n+1}                                  (fd_adjoint_step)
+//   GRAD : g     += D c (L u + f)                                  (fused gradient)
+//
+// Work decomposition (2.5-D blocking).  A block of 256 threads = 4 waves of
+// 64 lanes owns an x-y tile of 64 x (4*RY) points and marches along z through
+// a chunk of `kchunk` planes.  Lane = x (one 256-byte coalesced row segment
+// per load); each wave owns RY consecutive rows.  Per plane:
+//   * the stencil field of the current plane (tile + 4-wide x and y halos) is
+//     staged in LDS (double buffered, so one barrier per plane);
+//   * x neighbours come from LDS; y neighbours from the thread's own registers
+//     when the row is its own, else from LDS;
+//   * z neighbours come from a 9-deep register queue per row, so every plane of
+//     the field is read from global memory once per block (plus the 8-plane
+//     z halo of each chunk);
+//   * the next plane of every operand is prefetched one iteration ahead;
+//   * pointwise operands (u_prev, vdt2, ...) are streamed with non-temporal
+//     loads and the result with non-temporal stores, leaving L2 to the field
+//     whose x/y halos neighbouring tiles re-read.
+// Blocks are renumbered so that each of the 8 XCDs (each with its own L2) gets
+// one contiguous run of tiles: hardware dispatches block b to XCD b % 8.
+#include "fd_internal.h"
+
+namespace fd {
+namespace {
+
+constexpr int TX = 64;  // lanes per wave = tile width in x
+constexpr int NW = 4;   // waves per block
+
+enum Mode { FWD = 0, ADJ = 1, GRAD = 2 };
+
+struct Params {
+  Geo g;
+  Coef c;
+  // stencil field: FWD/GRAD read f; ADJ forms vdt2 * D * f from f = a^{n+1} and fq = vdt2
+  const float* f;
+  const float* fq;
+  // pointwise operands
+  const float* pa;  // FWD: u_prev   ADJ: a_nn (may be null)  GRAD: a^{n+1}
+  const float* pb;  // FWD: vdt2     ADJ: -                   GRAD: -
+  float* out;       // FWD: u_next   ADJ: a_out               GRAD: g (read-modify-write)
+  const float* ex;
+  const float* ey;
+  const float* ez;
+  int tiles_x, tiles_y, kchunk;
+  int si, sj, sk;   // GRAD source point (si < 0: none)
+  float sw;         // GRAD source amplitude
+};
+
+__device__ __forceinline__ int remap_block(int bid, int nb) {
+  const int per = nb >> 3;
+  if (bid < (per << 3)) return (bid & 7) * per + (bid >> 3);
+  return bid;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  while (i < 0) i += n;
+  while (i >= n) i -= n;
+  return i;
+}
+
+__device__ __forceinline__ float ldg_nt(const float* p) { return __builtin_nontemporal_load(p); }
+
+template <int RY, int MODE, bool SPONGE>
+__global__ void __launch_bounds__(TX * NW) stencil_kernel(Params p) {
+  constexpr int TY = NW * RY;
+  constexpr int LX = TX + 8;
+  constexpr int LY = TY + 8;
+  __shared__ float sm[2][LY * LX];
+
+  const int lane = threadIdx.x;
+  const int w = threadIdx.y;
+  const int logical = remap_block(blockIdx.x, gridDim.x);
+  const int bx = logical % p.tiles_x;
+  const int rest = logical / p.tiles_x;
+  const int by = rest % p.tiles_y;
+  const int bz = rest / p.tiles_y;
+
+  const int nx = p.g.nx, ny = p.g.ny, nz = p.g.nz;
+  const int sy = p.g.sy;
+  const long long sz = p.g.sz;
+  const int x0 = bx * TX;
+  const int y0 = by * TY;
+  const int kb = bz * p.kchunk;
+  const int ke = min(kb + p.kchunk, nz);
+  const int x = x0 + lane;
+  const int yr = y0 + w * RY;
+
+  // ---- per-thread geometry of the cells it loads every plane
+  int coff[RY];
+  bool cld[RY], act[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int yy = yr + r;
+    coff[r] = yy * sy + x;
+    cld[r] = (x < nx + 4) && (yy < ny + 4);
+    act[r] = (x < nx) && (yy < ny);
+  }
+  // y-halo rows: this wave loads row y0-4+w (top) and y0+TY+w (bottom) at column x
+  const int ht_y = y0 - 4 + w;
+  const int hb_y = y0 + TY + w;
+  const int ht_off = ht_y * sy + x;
+  const int hb_off = hb_y * sy + x;
+  const bool ht_ld = x < nx + 4;
+  const bool hb_ld = (x < nx + 4) && (hb_y < ny + 4);
+  // x-halo columns: lanes < 8*RY of each wave load (row yr + lane/8, column c = lane%8)
+  const int hx_r = lane >> 3;
+  const int hx_c = lane & 7;
+  const int hx_x = hx_c < 4 ? x0 - 4 + hx_c : x0 + TX + (hx_c - 4);
+  const int hx_y = yr + hx_r;
+  const bool hx_on = lane < 8 * RY;
+  const bool hx_ld = hx_on && (hx_x < nx + 4) && (hx_y < ny + 4);
+  const int hx_off = hx_y * sy + hx_x;
+  const int hx_lds = (4 + w * RY + hx_r) * LX + (hx_c < 4 ? hx_c : TX + hx_c);
+
+  // ---- sponge factors that are constant along z for this thread
+  float ex_c = 0.f, ex_h = 0.f, ey_r[RY], ey_t = 0.f, ey_b = 0.f, ey_h = 0.f;
+#pragma unroll
+  for (int r = 0; r < RY; ++r) ey_r[r] = 0.f;
+  if (SPONGE) {
+    if (MODE == ADJ) {  // halo cells take eta of their periodic image
+      if (x < nx + 4) ex_c = p.ex[wrapi(x, nx)];
+      if (hx_ld) ex_h = p.ex[wrapi(hx_x, nx)];
+      if (hx_ld) ey_h = p.ey[wrapi(hx_y, ny)];
+      ey_t = p.ey[wrapi(ht_y, ny)];
+      if (hb_y < ny + 4) ey_b = p.ey[wrapi(hb_y, ny)];
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+        if (yr + r < ny + 4) ey_r[r] = p.ey[wrapi(yr + r, ny)];
+    } else {
+      if (x < nx) ex_c = p.ex[x];
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+        if (yr + r < ny) ey_r[r] = p.ey[yr + r];
+    }
+  }
+
+  const float* __restrict__ fbase = p.f + p.g.org;
+  const float* __restrict__ qbase = p.fq + p.g.org;
+
+  // Field value at an in-plane offset of plane k (k in [-4, nz+4)).  ADJ forms
+  // vdt2 * c / (1 + eta) with eta of the periodic image.
+  auto fld = [&](int k, int off, bool ld, float exv, float eyv, float ezv) -> float {
+    if (!ld) return 0.f;
+    const long long pk = (long long)k * sz;
+    if (MODE == ADJ) {
+      const float cv = fbase[pk + off];
+      const float qv = qbase[pk + off];
+      float v = qv * cv;
+      if (SPONGE) v *= __builtin_amdgcn_rcpf(1.f + (exv + eyv + ezv));
+      return v;
+    } else {
+      return fbase[pk + off];
+    }
+  };
+  auto ezw = [&](int k) -> float {
+    if (!SPONGE) return 0.f;
+    if (MODE == ADJ) return p.ez[wrapi(k, nz)];
+    return (k >= 0 && k < nz) ? p.ez[k] : 0.f;
+  };
+
+  // ---- prologue: z queue for planes kb-4 .. kb+4, halos of plane kb
+  float zq[9][RY];
+  float cq[5][RY];  // ADJ: a^{n+1} of planes k .. k+4 (centre column)
+#pragma unroll
+  for (int s = 0; s < 9; ++s) {
+    const int k = kb - 4 + s;
+    const float ezv = ezw(k);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      zq[s][r] = fld(k, coff[r], cld[r], ex_c, ey_r[r], ezv);
+      if (MODE == ADJ && s >= 4)
+        cq[s - 4][r] = cld[r] ? fbase[(long long)k * sz + coff[r]] : 0.f;
+    }
+  }
+  float ht, hb, hx;
+  {
+    const float ezv = ezw(kb);
+    ht = fld(kb, ht_off, ht_ld, ex_c, ey_t, ezv);
+    hb = fld(kb, hb_off, hb_ld, ex_c, ey_b, ezv);
+    hx = fld(kb, hx_off, hx_ld, ex_h, ey_h, ezv);
+  }
+  float pa[RY], pb[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const long long o = p.g.org + (long long)kb * sz + coff[r];
+    pa[r] = 0.f;
+    pb[r] = 0.f;
+    if (act[r] && kb < ke) {
+      if (MODE == FWD) {
+        pa[r] = ldg_nt(p.pa + o);
+        pb[r] = ldg_nt(p.pb + o);
+      } else if (MODE == ADJ) {
+        if (p.pa) pa[r] = ldg_nt(p.pa + o);
+      } else {
+        pa[r] = ldg_nt(p.pa + o);
+        pb[r] = p.out[o];
+      }
+    }
+  }
+
+  for (int k = kb; k < ke; ++k) {
+    const int buf = (k - kb) & 1;
+    // ---- prefetch for the next iteration
+    float nzq[RY], ncq[RY], npa[RY], npb[RY];
+    float nht = 0.f, nhb = 0.f, nhx = 0.f;
+    {
+      const int kn = k + 5;
+      const bool need = kn < ke + 4;
+      const float ezv = ezw(kn);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        nzq[r] = need ? fld(kn, coff[r], cld[r], ex_c, ey_r[r], ezv) : 0.f;
+        if (MODE == ADJ)
+          ncq[r] = (need && cld[r]) ? fbase[(long long)kn * sz + coff[r]] : 0.f;
+      }
+    }
+    const bool more = k + 1 < ke;
+    if (more) {
+      const float ezv = ezw(k + 1);
+      nht = fld(k + 1, ht_off, ht_ld, ex_c, ey_t, ezv);
+      nhb = fld(k + 1, hb_off, hb_ld, ex_c, ey_b, ezv);
+      nhx = fld(k + 1, hx_off, hx_ld, ex_h, ey_h, ezv);
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      npa[r] = 0.f;
+      npb[r] = 0.f;
+      if (more && act[r]) {
+        const long long o = p.g.org + (long long)(k + 1) * sz + coff[r];
+        if (MODE == FWD) {
+          npa[r] = ldg_nt(p.pa + o);
+          npb[r] = ldg_nt(p.pb + o);
+        } else if (MODE == ADJ) {
+          if (p.pa) npa[r] = ldg_nt(p.pa + o);
+        } else {
+          npa[r] = ldg_nt(p.pa + o);
+          npb[r] = p.out[o];
+        }
+      }
+    }
+
+    // ---- stage plane k of the field in LDS
+    float* s = sm[buf];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) s[(4 + w * RY + r) * LX + 4 + lane] = zq[4][r];
+    s[w * LX + 4 + lane] = ht;
+    s[(TY + 4 + w) * LX + 4 + lane] = hb;
+    if (hx_on) s[hx_lds] = hx;
+    __syncthreads();
+
+    // ---- compute
+    const float ezk = SPONGE ? p.ez[k] : 0.f;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const float* row = s + (4 + w * RY + r) * LX + 4 + lane;
+      const float uc = zq[4][r];
+      float lap = p.c.cc * uc;
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) lap += p.c.cx[m] * (row[m] + row[-m]);
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) {
+        const float up_ = (r + m < RY) ? zq[4][(r + m) % RY] : row[m * LX];
+        const float dn_ = (r - m >= 0) ? zq[4][(r - m + RY) % RY] : row[-m * LX];
+        lap += p.c.cy[m] * (up_ + dn_);
+      }
+#pragma unroll
+      for (int m = 1; m <= 4; ++m) lap += p.c.cz[m] * (zq[4 + m][r] + zq[4 - m][r]);
+
+      if (act[r]) {
+        const long long o = p.g.org + (long long)k * sz + coff[r];
+        float eta = 0.f;
+        if (SPONGE) eta = ex_c + ey_r[r] + ezk;
+        if (MODE == FWD) {
+          float v;
+          if (SPONGE && eta != 0.f)
+            v = (2.f * uc - (1.f - eta) * pa[r] + pb[r] * lap) * __builtin_amdgcn_rcpf(1.f + eta);
+          else
+            v = 2.f * uc - pa[r] + pb[r] * lap;
+          __builtin_nontemporal_store(v, p.out + o);
+        } else if (MODE == ADJ) {
+          const float c = cq[0][r];
+          float v;
+          if (SPONGE && eta != 0.f) {
+            const float D = __builtin_amdgcn_rcpf(1.f + eta);
+            v = 2.f * D * c + lap - (1.f - eta) * D * pa[r];
+          } else {
+            v = 2.f * c + lap - pa[r];
+          }
+          __builtin_nontemporal_store(v, p.out + o);
+        } else {
+          float src = 0.f;
+          if (x == p.si && yr + r == p.sj && k == p.sk) src = p.sw;
+          float D = 1.f;
+          if (SPONGE && eta != 0.f) D = __builtin_amdgcn_rcpf(1.f + eta);
+          p.out[o] = pb[r] + D * pa[r] * (lap + src);
+        }
+      }
+    }
+
+    // ---- rotate queues
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) zq[t][r] = zq[t + 1][r];
+      zq[8][r] = nzq[r];
+      if (MODE == ADJ) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cq[t][r] = cq[t + 1][r];
+        cq[4][r] = ncq[r];
+      }
+      pa[r] = npa[r];
+      pb[r] = npb[r];
+    }
+    ht = nht;
+    hb = nhb;
+    hx = nhx;
+  }
+}
+
+struct LaunchShape {
+  int tiles_x, tiles_y, kchunk, zchunks;
+};
+
+int g_kchunk_override = 0;
+
+template <int RY>
+LaunchShape shape_for(const Geo& g) {
+  LaunchShape s;
+  s.tiles_x = (g.nx + TX - 1) / TX;
+  s.tiles_y = (g.ny + NW * RY - 1) / (NW * RY);
+  const long long tiles = (long long)s.tiles_x * s.tiles_y;
+  int kc;
+  if (g_kchunk_override > 0) {
+    kc = g_kchunk_override;
+  } else {
+    // aim at >= 4 resident blocks per CU (256 CUs) while keeping the z halo
+    // re-read (8 planes per chunk) small
+    const long long target = 1024;
+    long long chunks = (target + tiles - 1) / tiles;
+    if (chunks < 1) chunks = 1;
+    kc = (int)((g.nz + chunks - 1) / chunks);
+    if (kc < 32) kc = 32;
+  }
+  if (kc > g.nz) kc = g.nz;
+  s.kchunk = kc;
+  s.zchunks = (g.nz + kc - 1) / kc;
+  return s;
+}
+
+template <int RY, int MODE, bool SPONGE>
+hipError_t launch_mode(Params p, hipStream_t st) {
+  const LaunchShape sh = shape_for<RY>(p.g);
+  p.tiles_x = sh.tiles_x;
+  p.tiles_y = sh.tiles_y;
+  p.kchunk = sh.kchunk;
+  const long long nb = (long long)sh.tiles_x * sh.tiles_y * sh.zchunks;
+  if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((stencil_kernel<RY, MODE, SPONGE>), dim3((unsigned)nb), dim3(TX, NW), 0,
+                     st, p);
+  return hipGetLastError();
+}
+
+Params base_params(const Geo& g, const Coef& c, const float* ex, const float* ey,
+                   const float* ez) {
+  Params p{};
+  p.g = g;
+  p.c = c;
+  p.ex = ex;
+  p.ey = ey;
+  p.ez = ez;
+  p.si = -1;
+  p.sj = -1;
+  p.sk = -1;
+  p.sw = 0.f;
+  return p;
+}
+
+constexpr int RY_FWD = 4;
+constexpr int RY_ADJ = 2;
+
+}  // namespace
+
+void set_kchunk_override(int kc) { g_kchunk_override = kc; }
+
+hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float* u,
+                       float* un, const float* q, const float* ex, const float* ey,
+                       const float* ez, hipStream_t s) {
+  Params p = base_params(g, c, ex, ey, ez);
+  p.f = u;
+  p.fq = u;
+  p.pa = up;
+  p.pb = q;
+  p.out = un;
+  if (ex) return launch_mode<RY_FWD, FWD, true>(p, s);
+  return launch_mode<RY_FWD, FWD, false>(p, s);
+}
+
+hipError_t launch_adjoint(const Geo& g, const Coef& c, const float* ann, const float* an1,
+                          float* aout, const float* q, const float* ex, const float* ey,
+                          const float* ez, hipStream_t s) {
+  Params p = base_params(g, c, ex, ey, ez);
+  p.f = an1;
+  p.fq = q;
+  p.pa = ann;
+  p.pb = nullptr;
+  p.out = aout;
+  if (ex) return launch_mode<RY_ADJ, ADJ, true>(p, s);
+  return launch_mode<RY_ADJ, ADJ, false>(p, s);
+}
+
+hipError_t launch_grad(const Geo& g, const Coef& c, const float* u, const float* an1,
+                       float* gq, const float* ex, const float* ey, const float* ez,
+                       const fd_source* src, hipStream_t s) {
+  Params p = base_params(g, c, ex, ey, ez);
+  p.f = u;
+  p.fq = u;
+  p.pa = an1;
+  p.pb = nullptr;
+  p.out = gq;
+  if (src) {
+    p.si = src->i;
+    p.sj = src->j;
+    p.sk = src->k;
+    p.sw = src->w;
+  }
+  if (ex) return launch_mode<RY_FWD, GRAD, true>(p, s);
+  return launch_mode<RY_FWD, GRAD, false>(p, s);
+}
+
+}  // namespace fd

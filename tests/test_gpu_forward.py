@@ -1,0 +1,254 @@
+"""GPU parity of the forward path (S0-S7) against the FP64 oracle, through the C ABI.
+
+Tolerances: the FP32 wavefield must match the FP64 oracle to relative L2 <= 1e-6 for one
+step fed with the GPU's own state, and <= 1e-4 after 100 steps.  Integer/byte work
+(pack/unpack, vdt2 rounding, dt) must be bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as ora
+from workloads import (center_source, layered_velocity, random_field, receivers_plane,
+                       receivers_xline, smooth_velocity)
+
+pytestmark = pytest.mark.gpu
+
+api = pytest.importorskip("paper_2506_02486_amd.api")
+D10 = (10.0, 10.0, 10.0)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_eta(sim, width, vmax, dt, d=D10):
+    nz, ny, nx = sim.grid.nz, sim.grid.ny, sim.grid.nx
+    return ora.sponge_tables(nx, ny, nz, width, vmax, d, dt)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def test_setup_is_bit_exact_with_oracle():
+    v = layered_velocity(37, 21, 19, seed=1)
+    sim = api.Simulation(v, d=(10.0, 12.0, 9.0))
+    dt_o = ora.cfl_dt(v, 9.0)
+    assert sim.dt == dt_o
+    q = sim.grid.interior(sim.vdt2).cpu().numpy()
+    assert np.array_equal(q, ora.vdt2(v, dt_o).astype(np.float32))
+    # face halos of vdt2 carry the periodic image, edges stay zero
+    P = sim.grid.padded(sim.vdt2).cpu().numpy()
+    assert np.array_equal(P[4:-4, 4:-4, :4], q[:, :, -4:])
+    assert np.array_equal(P[4:-4, -4:, 4:-4], q[:, :4, :])
+    assert np.array_equal(P[:4, 4:-4, 4:-4], q[-4:, :, :])
+    assert np.all(P[:4, :4, :] == 0)
+    w = api.ricker(50, dt_o)
+    assert np.allclose(w, ora.ricker(50, dt_o), rtol=0, atol=2e-7)
+    for n, width in ((37, 16), (21, 5)):
+        emax = api.lib().fd_sponge_eta_max(4500.0, 10.0, dt_o, width, 1e-3)
+        h = np.empty(n, np.float32)
+        api.lib().fd_sponge_profile(h.ctypes.data, n, width, emax)
+        assert np.allclose(h, ora.sponge_eta(n, width, 4500.0, 10.0, dt_o), rtol=1e-6, atol=0)
+
+
+def test_config1_plain_forward_64cubed_100_steps():
+    """64^3 layered model, Dirichlet, Ricker 15 Hz at the centre, receivers on k=0."""
+    n = 64
+    v = layered_velocity(n, n, n, seed=1)
+    src = center_source(n, n, n)
+    rec = receivers_plane(n, n, 0)
+    sim = api.Simulation(v, geom=api.Geometry(src=src, rec=rec))
+    tr = sim.run(100).cpu().numpy()
+    dt = ora.cfl_dt(v, 10.0)
+    w = ora.ricker(100, dt)
+    tr_o, up_o, u_o = ora.forward(v, 100, dt, src=src, w=w, rec=rec)
+    up, u = (x.cpu().numpy() for x in sim.state())
+    assert rel_l2(u, u_o) <= 1e-4
+    assert rel_l2(up, up_o) <= 1e-4
+    assert rel_l2(tr, tr_o) <= 1e-4
+    assert np.abs(tr).max() > 0
+
+
+def _per_step_check(sim, steps, eta=(None, None, None), periodic=False):
+    """Advance the GPU and, at each listed step, feed its FP32 (u^{n-1}, u^n) to one
+    oracle step and compare u^{n+1} over the whole interior."""
+    g = sim.grid
+    q = ora.vdt2(g.interior(sim.v).cpu().numpy(), sim.dt)
+    worst = 0.0
+    last = sim.n
+    for n in steps:
+        if n > last:
+            sim.run(n - last)
+        up, u = (x.cpu().numpy() for x in sim.state())
+        w_src = 0.0
+        src = sim.geom.src
+        if src is not None:
+            w_src = float(ora.ricker(1, sim.dt, n0=n)[0])
+        sim.run(1)
+        got = g.interior(sim.u).cpu().numpy()
+        k, j, i = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+        pts = np.stack([i.ravel(), j.ravel(), k.ravel()], 1).astype(np.int32)
+        want = ora.step_points(up, u, q, pts, d=g.d, eta=eta, periodic=periodic, src=src,
+                               w_src=w_src).reshape(got.shape)
+        worst = max(worst, rel_l2(got, want))
+        last = n + 1
+    return worst
+
+
+def test_config1_per_step_parity():
+    n = 64
+    v = layered_velocity(n, n, n, seed=1)
+    sim = api.Simulation(v, geom=api.Geometry(src=center_source(n, n, n)))
+    assert _per_step_check(sim, [1, 10, 40, 99]) <= 1e-6
+
+
+@pytest.mark.parametrize("shape", [(100, 37, 45), (67, 19, 33), (130, 70, 9)])
+def test_ragged_sponge_loopback_parity(shape):
+    """Several tiles plus ragged tails in x and y, chunked z, sponge, periodic loopback
+    exchange every step: 60 steps vs the oracle, then per-step parity."""
+    nx, ny, nz = shape
+    v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
+    src = (nx // 3, ny // 2, nz // 2)
+    rec = receivers_xline(nx, ny // 2, 4)
+    width = 6
+    sim = api.Simulation(v, sponge_width=width, exchange="loopback",
+                         geom=api.Geometry(src=src, rec=rec))
+    tr = sim.run(60).cpu().numpy()
+    dt = sim.dt
+    eta = oracle_eta(sim, width, float(v.max()), dt)
+    tr_o, up_o, u_o = ora.forward(v, 60, dt, src=src, w=ora.ricker(60, dt), eta=eta,
+                                  periodic=True, rec=rec)
+    assert rel_l2(sim.state()[1].cpu().numpy(), u_o) <= 1e-4
+    assert rel_l2(tr, tr_o) <= 1e-4
+    assert _per_step_check(sim, [60, 75], eta=eta, periodic=True) <= 1e-6
+    assert sim.n == 76
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 2), (4, 4, 4), (65, 17, 1)])
+def test_degenerate_small_grids(shape):
+    nx, ny, nz = shape
+    v = np.full((nz, ny, nx), 2000.0, np.float32)
+    src = (nx // 2, ny // 2, nz // 2)
+    sim = api.Simulation(v, geom=api.Geometry(src=src, rec=np.array([src], np.int32)))
+    tr = sim.run(12).cpu().numpy()
+    tr_o, _, u_o = ora.forward(v, 12, sim.dt, src=src, w=ora.ricker(12, sim.dt),
+                               rec=np.array([src], np.int32))
+    assert rel_l2(sim.state()[1].cpu().numpy(), u_o) <= 1e-5
+    assert rel_l2(tr, tr_o) <= 1e-5
+
+
+def test_in_place_two_array_stepping_matches_three_arrays():
+    n = 40
+    v = layered_velocity(n, n, n, seed=1)
+    sim = api.Simulation(v, sponge_width=8)
+    g = sim.grid
+    rng = np.random.default_rng(3)
+    a = torch.from_numpy(rng.standard_normal(g.elems).astype(np.float32)).cuda()
+    b = torch.from_numpy(rng.standard_normal(g.elems).astype(np.float32)).cuda()
+    for t in (a, b):  # Dirichlet halos
+        P = g.padded(t)
+        P[:4] = 0; P[-4:] = 0; P[:, :4] = 0; P[:, -4:] = 0; P[:, :, :4] = 0; P[:, :, -4:] = 0
+    out = g.zeros()
+    api.step(g, a, b, out, sim.vdt2, sim.sponge)
+    a2 = a.clone()
+    api.step(g, a2, b, a2, sim.vdt2, sim.sponge)
+    torch.cuda.synchronize()
+    assert torch.equal(g.interior(out), g.interior(a2))
+
+
+def test_mirror_symmetry_is_bitwise():
+    n = 45
+    a = smooth_velocity(n, n, n, seed=7, sigma=3.0).astype(np.float64)
+    for ax in range(3):
+        a = 0.5 * (a + np.flip(a, axis=ax))
+    v = a.astype(np.float32)
+    sim = api.Simulation(v, sponge_width=8, geom=api.Geometry(src=(22, 22, 22)))
+    sim.run(50)
+    u = sim.state()[1].cpu().numpy()
+    assert np.abs(u).max() > 0
+    for ax in range(3):
+        assert np.array_equal(u, np.flip(u, axis=ax))
+
+
+def test_resume_is_bitwise():
+    n = 48
+    v = layered_velocity(n, n, n, seed=1)
+    geom = api.Geometry(src=(20, 24, 26), rec=receivers_plane(n, n, 2))
+    a = api.Simulation(v, sponge_width=6, geom=geom, exchange="loopback")
+    ta = torch.cat([a.run(30), a.run(20)])
+    b = api.Simulation(v, sponge_width=6, geom=geom, exchange="loopback")
+    tb = b.run(50)
+    assert torch.equal(ta, tb)
+    assert torch.equal(a.state()[1], b.state()[1])
+
+
+def test_pack_unpack_bit_exact():
+    nx, ny, nz = 70, 9, 13
+    g = api.Grid(nx, ny, nz)
+    u = torch.from_numpy(random_field((g.elems,), 5)).cuda()
+    faces = api.face_buffers(g)
+    api.halo_pack(g, u, faces)
+    I = g.interior(u).cpu().numpy()
+    f = [x.cpu().numpy() for x in faces]
+    assert np.array_equal(f[0].reshape(nz, ny, 4), I[:, :, :4])
+    assert np.array_equal(f[1].reshape(nz, ny, 4), I[:, :, -4:])
+    assert np.array_equal(f[2].reshape(nz, 4, nx), I[:, :4, :])
+    assert np.array_equal(f[3].reshape(nz, 4, nx), I[:, -4:, :])
+    assert np.array_equal(f[4].reshape(4, ny, nx), I[:4])
+    assert np.array_equal(f[5].reshape(4, ny, nx), I[-4:])
+    before = g.padded(u).cpu().numpy()
+    api.halo_unpack(g, u, api.loopback(faces))
+    P = g.padded(u).cpu().numpy()
+    assert np.array_equal(P[4:-4, 4:-4, :4], I[:, :, -4:])
+    assert np.array_equal(P[4:-4, 4:-4, -4:], I[:, :, :4])
+    assert np.array_equal(P[4:-4, :4, 4:-4], I[:, -4:, :])
+    assert np.array_equal(P[4:-4, -4:, 4:-4], I[:, :4, :])
+    assert np.array_equal(P[:4, 4:-4, 4:-4], I[-4:])
+    assert np.array_equal(P[-4:, 4:-4, 4:-4], I[:4])
+    # interior, edges and corners untouched
+    assert np.array_equal(P[4:-4, 4:-4, 4:-4], before[4:-4, 4:-4, 4:-4])
+    assert np.array_equal(P[:4, :4], before[:4, :4])
+    # a NULL face leaves its halo alone
+    full = g.zeros()
+    g.padded(full).copy_(torch.from_numpy(before))
+    api.halo_unpack(g, full, [None, faces[0], None, None, None, None])
+    P2 = g.padded(full).cpu().numpy()
+    assert np.array_equal(P2[4:-4, 4:-4, :4], before[4:-4, 4:-4, :4])
+    assert np.array_equal(P2[4:-4, 4:-4, -4:], I[:, :, :4])
+    assert np.array_equal(P2[4:-4, :4], before[4:-4, :4])
+
+
+def test_full_size_512_sampled_per_step_parity():
+    """The benchmark's own shape and launch configuration (512^3, sponge 16, loopback
+    exchange): after 30 steps, one GPU step is checked against the oracle at sampled
+    points (faces, edges, corners, sponge, source, random interior)."""
+    n = 512
+    v = smooth_velocity(n, n, n, seed=2)
+    src = center_source(n, n, n)
+    sim = api.Simulation(v, sponge_width=16, exchange="loopback", geom=api.Geometry(src=src))
+    sim.run(30)
+    up, u = (x.cpu().numpy() for x in sim.state())
+    w_src = float(ora.ricker(1, sim.dt, n0=30)[0])
+    sim.run(1)
+    got = sim.state()[1].cpu().numpy()
+    rng = np.random.default_rng(9)
+    edge = np.array([0, 1, 3, 4, 15, 16, 17, 63, 64, 255, 256, 494, 495, 496, 507, 508, 510, 511])
+    pts = [np.stack(np.meshgrid(edge, edge, edge, indexing="ij"), -1).reshape(-1, 3)]
+    pts.append(rng.integers(0, n, size=(4000, 3)))
+    pts.append(np.array([src]) + rng.integers(-6, 7, size=(500, 3)))
+    pts = np.ascontiguousarray(np.concatenate(pts), dtype=np.int32)
+    q = ora.vdt2(v, sim.dt)
+    eta = ora.sponge_tables(n, n, n, 16, float(v.max()), D10, sim.dt)
+    want = ora.step_points(up, u, q, pts, eta=eta, periodic=True, src=src, w_src=w_src)
+    gv = got[pts[:, 2], pts[:, 1], pts[:, 0]]
+    assert np.abs(want).max() > 0
+    assert rel_l2(gv, want) <= 1e-6
+    assert np.abs(gv - want).max() <= 1e-5 * np.abs(want).max()
