@@ -1,0 +1,250 @@
+"""Benchmark of the acoustic FD hot path on one MI355X.
+
+``python bench.py [--gpus 1] [--steps K] [--warmup W]`` times K time steps of the
+single-subdomain workload -- a 512^3 interior with a radius-4 halo, smooth random
+velocity in [1500, 4500] m/s, 16-cell quadratic sponge, 15 Hz Ricker source at the
+centre, receivers on the centre x-line, the six faces packed and unpacked into
+contiguous buffers every step (loopback exchange) -- after W untimed warm-up steps,
+and prints one JSON line.
+
+A step is one pass of the per-step path: halo_pack, halo_unpack, fd_step,
+inject_source, record_receivers, pointer rotation.  ``value`` is interior points x
+steps / wall time in Gpts/s with every array resident in HBM.  ``roofline`` rates the
+dominant kernel (the fd_step stencil) by its algorithmic bytes (16 B per interior
+point: u^n, u^{n-1} and vdt2 read once, u^{n+1} written once) over its average launch
+time from HIP events on its own stream.  ``cpu_baseline`` times the FP64 CPU oracle on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "Gpts/s + % HBM roofline; shots/s and p50/p99 latency vs plain per-shot loop"
+STENCIL_SRC = os.path.join(ROOT, "paper_2506_02486_amd", "csrc", "fd_stencil.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fd_step_512_traffic.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stencil_hash() -> str:
+    with open(STENCIL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per fd_step launch from the committed counter summary, if it was
+    taken on the current stencil source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_h = re.search(r"stencil_source_sha256_16:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_h or not m_b or m_h.group(1) != stencil_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time) of a plain copy."""
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2 * nbytes / s / 1e9
+
+
+def cpu_baseline(v, dt, src, steps):
+    """FP64 oracle on the same 512^3 workload: (time of 1+steps) - (time of 1 step)."""
+    import numpy as np
+
+    import oracle
+
+    n = v.shape[0]
+    q = oracle.vdt2(v, dt)
+    eta = oracle.sponge_tables(n, n, n, 16, float(v.max()), (10.0,) * 3, dt)
+    w = oracle.ricker(steps + 1, dt)
+    t0 = time.perf_counter()
+    oracle.forward(None, 1, dt, src=src, w=w[:1], eta=eta, periodic=True, q=q)
+    t1 = time.perf_counter()
+    oracle.forward(None, steps + 1, dt, src=src, w=w, eta=eta, periodic=True, q=q)
+    t2 = time.perf_counter()
+    per_step = ((t2 - t1) - (t1 - t0)) / steps
+    del q
+    return {
+        "value": round(n ** 3 / per_step / 1e9, 5),
+        "unit": "Gpts/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": f"FP64 oracle, same {n}^3 sponge-16 periodic workload, {steps} steps "
+                  f"(time of {steps + 1} steps minus 1 step, set-up excluded); "
+                  f"{per_step:.3f} s/step",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512, help="interior edge (default 512)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, run a plain 1 GiB device copy (for counters)")
+    ap.add_argument("--kchunk", type=int, default=0)
+    ap.add_argument("--vcache", default=None,
+                    help="optional .npy path to cache the generated velocity model")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding of the subdomain is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2506_02486_amd import api
+    from workloads import center_source, receivers_xline, smooth_velocity
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm device"
+    torch.cuda.set_device(0)
+    n = args.n
+    log(f"bench: generating {n}^3 smooth velocity model")
+    if args.vcache and os.path.exists(args.vcache):
+        v = np.load(args.vcache)
+    else:
+        v = smooth_velocity(n, n, n, seed=2)
+        if args.vcache:
+            np.save(args.vcache, v)
+    src = center_source(n, n, n)
+    rec = receivers_xline(n, n // 2, n // 2)
+    sim = api.Simulation(v, sponge_width=16, exchange="loopback",
+                         geom=api.Geometry(src=src, rec=rec))
+    if args.kchunk:
+        api.set_kchunk(args.kchunk)
+    g = sim.grid
+    K, W = args.steps, args.warmup
+    log(f"bench: dt={sim.dt:.6e} s, vmax={sim.vmax:.1f}; warm-up {W} steps")
+    sim.run(W)
+    torch.cuda.synchronize()
+
+    w = api.ricker(K, sim.dt, n0=sim.n)
+    traces = torch.zeros((K, sim.nrec), dtype=torch.float32, device="cuda")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    log(f"bench: timing {K} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(K):
+        api.halo_pack(g, sim.u, sim.send)
+        api.halo_unpack(g, sim.u, sim.recv)
+        ev[s][0].record()
+        api.step(g, sim.u_prev, sim.u, sim.u_next, sim.vdt2, sim.sponge)
+        ev[s][1].record()
+        api.inject_source(g, sim.u_next, sim.vdt2, sim.sponge, src, float(w[s]))
+        api.record_receivers(g, sim.u_next, sim.rec_off, traces[s])
+        sim.u_prev, sim.u, sim.u_next = sim.u, sim.u_next, sim.u_prev
+        sim.n += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    avg_ms = float(np.mean(kern_ms))
+    pts = n ** 3
+    gpts = pts * K / elapsed / 1e9
+    algo_bytes = 16.0 * pts
+    achieved = algo_bytes / (avg_ms / 1e3) / 1e9
+    face_pts = 6 * 4 * n * n
+    path_bytes = algo_bytes + 8.0 * face_pts
+    finite = bool(torch.isfinite(g.interior(sim.u)).all().item())
+    log(f"bench: {elapsed * 1e3 / K:.3f} ms/step, fd_step {avg_ms * 1e3:.1f} us avg, "
+        f"{gpts:.1f} Gpts/s, finite={finite}")
+
+    copy_gbps = copy_bandwidth(torch)
+    if args.copy_calibration:
+        # a plain copy of exactly 1 GiB read + 1 GiB written, for the counter factor
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    traffic = read_traffic()
+    out = {
+        "metric": METRIC,
+        "value": round(gpts, 3),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(elapsed * 1e3 / K, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"single-subdomain step: {n}^3 interior + radius-4 halo, smooth random "
+                        f"velocity 1500-4500 m/s (seed 2, Gaussian sigma 8), 16-cell quadratic "
+                        f"sponge, Ricker 15 Hz at the centre, receivers on the centre x-line, "
+                        f"six faces packed/unpacked each step (loopback)",
+            "grid": [n, n, n],
+            "halo": 4,
+            "stencil": "25-point star, 8th order space, 2nd order time",
+            "steps_timed": K,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "fd_step (stencil_kernel<4,FWD,sponge>)",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBPS, 4),
+            "traffic": (round(traffic) if traffic is not None else None),
+            "algorithmic_bytes_per_launch": algo_bytes,
+            "avg_launch_ms": round(avg_ms, 5),
+        },
+        "path": {
+            "algorithmic_bytes_per_step": path_bytes,
+            "achieved_GBps": round(path_bytes / (elapsed / K) / 1e9, 1),
+            "frac": round(path_bytes / (elapsed / K) / 1e9 / PEAK_HBM_GBPS, 4),
+        },
+        "copy_GBps": round(copy_gbps, 1),
+        "gpu": torch.cuda.get_device_name(0),
+        "hip": torch.version.hip,
+        "finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle baseline ({args.cpu_steps} steps of {n}^3)")
+        out["cpu_baseline"] = cpu_baseline(v, sim.dt, src, args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

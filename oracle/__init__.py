@@ -102,8 +102,15 @@ def lib():
         L.ora_fwi_gradient.argtypes = [i32, i32, i32, f64, f64, f64, _dp, f64, i32, _dpn,
                                        i32, i32, i32, _dpn, _dpn, _dpn, i32, i32, _ipn,
                                        _dp, _dpn, _dpn, _dpn, _dpn]
+        L.ora_threads.restype = i32
+        L.ora_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return lib().ora_threads()
 
 
 # ------------------------------------------------------------------ layout helpers

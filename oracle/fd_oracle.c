@@ -24,6 +24,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define OH 4
 
@@ -436,4 +437,15 @@ double ora_fwi_gradient(int nx, int ny, int nz, double dx, double dy, double dz,
   free(vdt2); free(states); free(zero); free(res); free(g);
   for (int t = 0; t < 3; ++t) free(A[t]);
   return J;
+}
+
+/* Threads an OpenMP region of this library uses (for reporting only). */
+int ora_threads(void) {
+  int n = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    n = omp_get_num_threads();
+  }
+  return n;
 }
