@@ -137,6 +137,12 @@ int fd_cfl_dt(const fd_grid* g, const float* v, double courant, int32_t* scratch
 int fd_prepare_vdt2(const fd_grid* g, const float* v, float* vdt2, double dt,
                     void* stream);
 
+/* As fd_prepare_vdt2 from squared slowness m = 1/v^2: vdt2 = dt^2 / m
+ * (FP64, rounded to FP32), same halo treatment.  FD_EINVAL on bad input;
+ * m must be > 0 on the interior (not checked on the device). */
+int fd_prepare_vdt2_m(const fd_grid* g, const float* m, float* vdt2, double dt,
+                      void* stream);
+
 /* Host helper: peak eta = (dt/2) * sigma_max of a quadratic absorbing layer
  * of `width` cells with target normal-incidence reflection R, where
  * sigma_max = 3 vmax ln(1/R) / (2 width d) (Collino & Tsogka 2001).

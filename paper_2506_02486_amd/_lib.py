@@ -59,6 +59,7 @@ SIGNATURES = {
     "fd_set_kchunk": (C.c_int, [_i32]),
     "fd_cfl_dt": (C.c_int, [_G, _P, _f64, _P, C.POINTER(_f64), C.POINTER(_f64), _P]),
     "fd_prepare_vdt2": (C.c_int, [_G, _P, _P, _f64, _P]),
+    "fd_prepare_vdt2_m": (C.c_int, [_G, _P, _P, _f64, _P]),
     "fd_sponge_eta_max": (_f64, [_f64, _f64, _f64, _i32, _f64]),
     "fd_sponge_profile": (C.c_int, [_P, _i32, _i32, _f64]),
     "fd_ricker": (C.c_int, [_P, _i32, _i32, _f64, _f64, _f64]),
@@ -66,8 +67,8 @@ SIGNATURES = {
     "fd_step": (C.c_int, [_G, _P, _P, _P, _P, _S, _P]),
     "inject_source": (C.c_int, [_G, _P, _P, _S, _i32, _i32, _i32, _f32, _P]),
     "record_receivers": (C.c_int, [_G, _P, _P, _i32, _P, _P]),
-    "halo_pack": (C.c_int, [_G, _P, _FACES, _P]),
-    "halo_unpack": (C.c_int, [_G, _P, _FACES, _P]),
+    "halo_pack": (C.c_int, [_G, _P, C.POINTER(_P), _P]),
+    "halo_unpack": (C.c_int, [_G, _P, C.POINTER(_P), _P]),
     "fd_adjoint_step": (C.c_int, [_G, _P, _P, _P, _P, _S, _P, _P, C.POINTER(fd_source), _P]),
     "fd_scatter_add": (C.c_int, [_G, _P, _P, _P, _i32, _P]),
     "fd_grad_finalize": (C.c_int, [_G, _P, _P, _f64, _P, _P]),

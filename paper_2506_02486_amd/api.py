@@ -129,6 +129,14 @@ def prepare_vdt2(grid: Grid, v: torch.Tensor, vdt2: torch.Tensor, dt: float, str
           "fd_prepare_vdt2")
 
 
+def prepare_vdt2_m(grid: Grid, m: torch.Tensor, vdt2: torch.Tensor, dt: float, stream=None):
+    """vdt2 = dt^2 / m from squared slowness m (same layout and halo treatment)."""
+    grid.check(m, "m")
+    grid.check(vdt2, "vdt2")
+    check(lib().fd_prepare_vdt2_m(grid.ref, m.data_ptr(), vdt2.data_ptr(), dt, _stream(stream)),
+          "fd_prepare_vdt2_m")
+
+
 def ricker(nt: int, dt: float, f0: float = RICKER_F0, t0: float | None = None,
            n0: int = 0) -> np.ndarray:
     if t0 is None:

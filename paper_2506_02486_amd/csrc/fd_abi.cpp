@@ -208,8 +208,18 @@ int fd_prepare_vdt2(const fd_grid* g, const float* v, float* vdt2, double dt, vo
   if (!v || !vdt2) return fail(FD_EINVAL, "fd_prepare_vdt2: NULL array");
   if (overlaps(g, v, vdt2)) return fail(FD_EINVAL, "fd_prepare_vdt2: v and vdt2 overlap");
   if (!finite_pos(dt)) return fail(FD_EINVAL, "fd_prepare_vdt2: dt must be > 0");
-  return check_hip(launch_prepare_vdt2(make_geo(g), v, vdt2, dt, as_stream(stream)),
+  return check_hip(launch_prepare_vdt2(make_geo(g), v, vdt2, dt, false, as_stream(stream)),
                    "prepare_vdt2 launch");
+}
+
+int fd_prepare_vdt2_m(const fd_grid* g, const float* m, float* vdt2, double dt, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!m || !vdt2) return fail(FD_EINVAL, "fd_prepare_vdt2_m: NULL array");
+  if (overlaps(g, m, vdt2)) return fail(FD_EINVAL, "fd_prepare_vdt2_m: m and vdt2 overlap");
+  if (!finite_pos(dt)) return fail(FD_EINVAL, "fd_prepare_vdt2_m: dt must be > 0");
+  return check_hip(launch_prepare_vdt2(make_geo(g), m, vdt2, dt, true, as_stream(stream)),
+                   "prepare_vdt2_m launch");
 }
 
 double fd_sponge_eta_max(double vmax, double d, double dt, int32_t width, double R) {

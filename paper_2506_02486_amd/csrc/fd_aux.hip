@@ -113,7 +113,8 @@ __global__ void __launch_bounds__(BS) scatter_add_kernel(float* a, const int64_t
 // One thread per element of the padded box [-4,n+4)^3, one block row per
 // (j,k) line: interior from v, face halo from the periodic image, edges 0.
 __global__ void __launch_bounds__(BS) prep_vdt2_kernel(Geo g, const float* __restrict__ v,
-                                                       float* __restrict__ q, double dt) {
+                                                       float* __restrict__ q, double dt,
+                                                       bool from_m) {
   const int jj = blockIdx.y - 4;  // j in [-4, ny+4)
   const int kk = blockIdx.z - 4;  // k in [-4, nz+4)
   for (int ii = (int)(blockIdx.x * BS + threadIdx.x) - 4; ii < g.nx + 4; ii += gridDim.x * BS) {
@@ -133,8 +134,12 @@ __global__ void __launch_bounds__(BS) prep_vdt2_kernel(Geo g, const float* __res
       while (cj >= g.ny) cj -= g.ny;
       while (ck < 0) ck += g.nz;
       while (ck >= g.nz) ck -= g.nz;
-      const double vv = (double)v[at(g, ci, cj, ck)] * dt;
-      val = (float)(vv * vv);
+      if (from_m) {
+        val = (float)(dt * dt / (double)v[at(g, ci, cj, ck)]);
+      } else {
+        const double vv = (double)v[at(g, ci, cj, ck)] * dt;
+        val = (float)(vv * vv);
+      }
     }
     q[at(g, ii, jj, kk)] = val;
   }
@@ -247,11 +252,11 @@ hipError_t launch_scatter_add(float* a, const int64_t* off, const float* vals, i
   return hipGetLastError();
 }
 
-hipError_t launch_prepare_vdt2(const Geo& g, const float* v, float* q, double dt,
+hipError_t launch_prepare_vdt2(const Geo& g, const float* v, float* q, double dt, bool from_m,
                                hipStream_t s) {
   const unsigned bx = blocks_for(g.nx + 8, 64);
   hipLaunchKernelGGL(prep_vdt2_kernel, dim3(bx, g.ny + 8, g.nz + 8), dim3(BS), 0, s, g, v, q,
-                     dt);
+                     dt, from_m);
   return hipGetLastError();
 }
 

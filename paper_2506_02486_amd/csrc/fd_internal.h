@@ -61,7 +61,9 @@ hipError_t launch_scatter_add(float* a, const int64_t* off, const float* vals, i
                               hipStream_t s);
 hipError_t launch_pack(const Geo& g, const float* u, float* const face[6], hipStream_t s);
 hipError_t launch_unpack(const Geo& g, float* u, const float* const face[6], hipStream_t s);
-hipError_t launch_prepare_vdt2(const Geo& g, const float* v, float* q, double dt,
+// from_m: the input is squared slowness m and vdt2 = dt^2/m; else velocity v and
+// vdt2 = (v dt)^2
+hipError_t launch_prepare_vdt2(const Geo& g, const float* v, float* q, double dt, bool from_m,
                                hipStream_t s);
 hipError_t launch_vmax(const Geo& g, const float* v, int32_t* out, hipStream_t s);
 hipError_t launch_grad_finalize(const Geo& g, const float* gq, const float* q, double dt,

@@ -6,10 +6,11 @@
 //          E = 1-eta, c = a^{n+1}                                  (fd_adjoint_step)
 //   GRAD : g     += D c (L u + f)                                  (fused gradient)
 //
-// Work decomposition (2.5-D blocking).  A block of 256 threads = 4 waves of
-// 64 lanes owns an x-y tile of 64 x (4*RY) points and marches along z through
-// a chunk of `kchunk` planes.  Lane = x (one 256-byte coalesced row segment
-// per load); each wave owns RY consecutive rows.  Per plane:
+// Work decomposition (2.5-D blocking).  A block of TXT x NY threads owns an
+// x-y tile of TXT x (NY*RY) points and marches along z through a chunk of
+// `kchunk` planes.  threadIdx.x = x (TXT/64 waves side by side, each load a
+// 256-byte coalesced row segment per wave); each thread row owns RY
+// consecutive y rows.  Per plane:
 //   * the stencil field of the current plane (tile + 4-wide x and y halos) is
 //     staged in LDS (double buffered, so one barrier per plane);
 //   * x neighbours come from LDS; y neighbours from the thread's own registers
@@ -28,8 +29,6 @@
 namespace fd {
 namespace {
 
-constexpr int TX = 64;  // lanes per wave = tile width in x
-constexpr int NW = 4;   // waves per block
 
 enum Mode { FWD = 0, ADJ = 1, GRAD = 2 };
 
@@ -65,11 +64,15 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 
 __device__ __forceinline__ float ldg_nt(const float* p) { return __builtin_nontemporal_load(p); }
 
-template <int RY, int MODE, bool SPONGE>
-__global__ void __launch_bounds__(TX * NW) stencil_kernel(Params p) {
-  constexpr int TY = NW * RY;
+template <int TXT, int NY, int RY, int MODE, bool SPONGE>
+__global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
+  constexpr int TX = TXT;
+  constexpr int TY = NY * RY;
   constexpr int LX = TX + 8;
   constexpr int LY = TY + 8;
+  constexpr int HPT = 8 / NY;  // y-halo rows each thread row loads per plane
+  static_assert(NY == 1 || NY == 2 || NY == 4 || NY == 8, "NY must divide 8");
+  static_assert(8 * RY <= TXT, "x-halo cells must fit in one thread row");
   __shared__ float sm[2][LY * LX];
 
   const int lane = threadIdx.x;
@@ -100,14 +103,19 @@ __global__ void __launch_bounds__(TX * NW) stencil_kernel(Params p) {
     cld[r] = (x < nx + 4) && (yy < ny + 4);
     act[r] = (x < nx) && (yy < ny);
   }
-  // y-halo rows: this wave loads row y0-4+w (top) and y0+TY+w (bottom) at column x
-  const int ht_y = y0 - 4 + w;
-  const int hb_y = y0 + TY + w;
-  const int ht_off = ht_y * sy + x;
-  const int hb_off = hb_y * sy + x;
-  const bool ht_ld = x < nx + 4;
-  const bool hb_ld = (x < nx + 4) && (hb_y < ny + 4);
-  // x-halo columns: lanes < 8*RY of each wave load (row yr + lane/8, column c = lane%8)
+  // y-halo rows: thread row w loads halo rows hr = w + h*NY (h < HPT) at column
+  // x; hr < 4 are the rows above the tile, hr >= 4 the rows below
+  int hy_y[HPT], hy_off[HPT], hy_lds[HPT];
+  bool hy_ld[HPT];
+#pragma unroll
+  for (int h = 0; h < HPT; ++h) {
+    const int hr = w + h * NY;
+    hy_y[h] = hr < 4 ? y0 - 4 + hr : y0 + TY + (hr - 4);
+    hy_off[h] = hy_y[h] * sy + x;
+    hy_lds[h] = (hr < 4 ? hr : TY + hr) * LX + 4 + lane;
+    hy_ld[h] = (x < nx + 4) && (hy_y[h] < ny + 4);
+  }
+  // x-halo columns: lanes < 8*RY of each thread row load (row yr + lane/8, column c = lane%8)
   const int hx_r = lane >> 3;
   const int hx_c = lane & 7;
   const int hx_x = hx_c < 4 ? x0 - 4 + hx_c : x0 + TX + (hx_c - 4);
@@ -118,16 +126,19 @@ __global__ void __launch_bounds__(TX * NW) stencil_kernel(Params p) {
   const int hx_lds = (4 + w * RY + hx_r) * LX + (hx_c < 4 ? hx_c : TX + hx_c);
 
   // ---- sponge factors that are constant along z for this thread
-  float ex_c = 0.f, ex_h = 0.f, ey_r[RY], ey_t = 0.f, ey_b = 0.f, ey_h = 0.f;
+  float ex_c = 0.f, ex_h = 0.f, ey_r[RY], ey_hy[HPT], ey_h = 0.f;
 #pragma unroll
   for (int r = 0; r < RY; ++r) ey_r[r] = 0.f;
+#pragma unroll
+  for (int h = 0; h < HPT; ++h) ey_hy[h] = 0.f;
   if (SPONGE) {
     if (MODE == ADJ) {  // halo cells take eta of their periodic image
       if (x < nx + 4) ex_c = p.ex[wrapi(x, nx)];
       if (hx_ld) ex_h = p.ex[wrapi(hx_x, nx)];
       if (hx_ld) ey_h = p.ey[wrapi(hx_y, ny)];
-      ey_t = p.ey[wrapi(ht_y, ny)];
-      if (hb_y < ny + 4) ey_b = p.ey[wrapi(hb_y, ny)];
+#pragma unroll
+      for (int h = 0; h < HPT; ++h)
+        if (hy_y[h] < ny + 4) ey_hy[h] = p.ey[wrapi(hy_y[h], ny)];
 #pragma unroll
       for (int r = 0; r < RY; ++r)
         if (yr + r < ny + 4) ey_r[r] = p.ey[wrapi(yr + r, ny)];
@@ -177,11 +188,11 @@ __global__ void __launch_bounds__(TX * NW) stencil_kernel(Params p) {
         cq[s - 4][r] = cld[r] ? fbase[(long long)k * sz + coff[r]] : 0.f;
     }
   }
-  float ht, hb, hx;
+  float hy[HPT], hx;
   {
     const float ezv = ezw(kb);
-    ht = fld(kb, ht_off, ht_ld, ex_c, ey_t, ezv);
-    hb = fld(kb, hb_off, hb_ld, ex_c, ey_b, ezv);
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) hy[h] = fld(kb, hy_off[h], hy_ld[h], ex_c, ey_hy[h], ezv);
     hx = fld(kb, hx_off, hx_ld, ex_h, ey_h, ezv);
   }
   float pa[RY], pb[RY];
@@ -206,8 +217,10 @@ __global__ void __launch_bounds__(TX * NW) stencil_kernel(Params p) {
   for (int k = kb; k < ke; ++k) {
     const int buf = (k - kb) & 1;
     // ---- prefetch for the next iteration
-    float nzq[RY], ncq[RY], npa[RY], npb[RY];
-    float nht = 0.f, nhb = 0.f, nhx = 0.f;
+    float nzq[RY], ncq[RY], npa[RY], npb[RY], nhy[HPT];
+    float nhx = 0.f;
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) nhy[h] = 0.f;
     {
       const int kn = k + 5;
       const bool need = kn < ke + 4;
@@ -222,8 +235,9 @@ __global__ void __launch_bounds__(TX * NW) stencil_kernel(Params p) {
     const bool more = k + 1 < ke;
     if (more) {
       const float ezv = ezw(k + 1);
-      nht = fld(k + 1, ht_off, ht_ld, ex_c, ey_t, ezv);
-      nhb = fld(k + 1, hb_off, hb_ld, ex_c, ey_b, ezv);
+#pragma unroll
+      for (int h = 0; h < HPT; ++h)
+        nhy[h] = fld(k + 1, hy_off[h], hy_ld[h], ex_c, ey_hy[h], ezv);
       nhx = fld(k + 1, hx_off, hx_ld, ex_h, ey_h, ezv);
     }
 #pragma unroll
@@ -248,8 +262,8 @@ __global__ void __launch_bounds__(TX * NW) stencil_kernel(Params p) {
     float* s = sm[buf];
 #pragma unroll
     for (int r = 0; r < RY; ++r) s[(4 + w * RY + r) * LX + 4 + lane] = zq[4][r];
-    s[w * LX + 4 + lane] = ht;
-    s[(TY + 4 + w) * LX + 4 + lane] = hb;
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) s[hy_lds[h]] = hy[h];
     if (hx_on) s[hx_lds] = hx;
     __syncthreads();
 
@@ -316,8 +330,8 @@ __global__ void __launch_bounds__(TX * NW) stencil_kernel(Params p) {
       pa[r] = npa[r];
       pb[r] = npb[r];
     }
-    ht = nht;
-    hb = nhb;
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) hy[h] = nhy[h];
     hx = nhx;
   }
 }
@@ -328,17 +342,16 @@ struct LaunchShape {
 
 int g_kchunk_override = 0;
 
-template <int RY>
-LaunchShape shape_for(const Geo& g) {
+LaunchShape shape_for(const Geo& g, int tx, int ty) {
   LaunchShape s;
-  s.tiles_x = (g.nx + TX - 1) / TX;
-  s.tiles_y = (g.ny + NW * RY - 1) / (NW * RY);
+  s.tiles_x = (g.nx + tx - 1) / tx;
+  s.tiles_y = (g.ny + ty - 1) / ty;
   const long long tiles = (long long)s.tiles_x * s.tiles_y;
   int kc;
   if (g_kchunk_override > 0) {
     kc = g_kchunk_override;
   } else {
-    // aim at >= 4 resident blocks per CU (256 CUs) while keeping the z halo
+    // aim at about 1024 blocks (4 per CU on 256 CUs) while keeping the z halo
     // re-read (8 planes per chunk) small
     const long long target = 1024;
     long long chunks = (target + tiles - 1) / tiles;
@@ -352,16 +365,16 @@ LaunchShape shape_for(const Geo& g) {
   return s;
 }
 
-template <int RY, int MODE, bool SPONGE>
+template <int TXT, int NY, int RY, int MODE, bool SPONGE>
 hipError_t launch_mode(Params p, hipStream_t st) {
-  const LaunchShape sh = shape_for<RY>(p.g);
+  const LaunchShape sh = shape_for(p.g, TXT, NY * RY);
   p.tiles_x = sh.tiles_x;
   p.tiles_y = sh.tiles_y;
   p.kchunk = sh.kchunk;
   const long long nb = (long long)sh.tiles_x * sh.tiles_y * sh.zchunks;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((stencil_kernel<RY, MODE, SPONGE>), dim3((unsigned)nb), dim3(TX, NW), 0,
-                     st, p);
+  hipLaunchKernelGGL((stencil_kernel<TXT, NY, RY, MODE, SPONGE>), dim3((unsigned)nb),
+                     dim3(TXT, NY), 0, st, p);
   return hipGetLastError();
 }
 
@@ -380,8 +393,9 @@ Params base_params(const Geo& g, const Coef& c, const float* ex, const float* ey
   return p;
 }
 
-constexpr int RY_FWD = 4;
-constexpr int RY_ADJ = 2;
+// tile shapes (threads in x, thread rows, y rows per thread)
+#define FWD_SHAPE 64, 4, 4
+#define ADJ_SHAPE 64, 4, 2
 
 }  // namespace
 
@@ -396,8 +410,8 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
   p.pa = up;
   p.pb = q;
   p.out = un;
-  if (ex) return launch_mode<RY_FWD, FWD, true>(p, s);
-  return launch_mode<RY_FWD, FWD, false>(p, s);
+  if (ex) return launch_mode<FWD_SHAPE, FWD, true>(p, s);
+  return launch_mode<FWD_SHAPE, FWD, false>(p, s);
 }
 
 hipError_t launch_adjoint(const Geo& g, const Coef& c, const float* ann, const float* an1,
@@ -409,8 +423,8 @@ hipError_t launch_adjoint(const Geo& g, const Coef& c, const float* ann, const f
   p.pa = ann;
   p.pb = nullptr;
   p.out = aout;
-  if (ex) return launch_mode<RY_ADJ, ADJ, true>(p, s);
-  return launch_mode<RY_ADJ, ADJ, false>(p, s);
+  if (ex) return launch_mode<ADJ_SHAPE, ADJ, true>(p, s);
+  return launch_mode<ADJ_SHAPE, ADJ, false>(p, s);
 }
 
 hipError_t launch_grad(const Geo& g, const Coef& c, const float* u, const float* an1,
@@ -428,8 +442,8 @@ hipError_t launch_grad(const Geo& g, const Coef& c, const float* u, const float*
     p.sk = src->k;
     p.sw = src->w;
   }
-  if (ex) return launch_mode<RY_FWD, GRAD, true>(p, s);
-  return launch_mode<RY_FWD, GRAD, false>(p, s);
+  if (ex) return launch_mode<FWD_SHAPE, GRAD, true>(p, s);
+  return launch_mode<FWD_SHAPE, GRAD, false>(p, s);
 }
 
 }  // namespace fd

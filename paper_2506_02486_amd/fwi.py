@@ -1,0 +1,147 @@
+"""FWI gradient with respect to squared slowness m = 1/v^2 (adjoint-state method).
+
+The forward model is the leapfrog step of the library (Dirichlet halos, optional
+sponge), a Ricker source and receivers; the misfit is any function of the synthetic
+traces.  ``FWIGrad.apply(m, problem)`` returns the traces and, on ``backward``, the
+gradient of the loss with respect to m, computed by
+
+* a forward sweep that keeps ``(u^{n-1}, u^n)`` every ``checkpoint_every`` steps,
+* a reverse sweep over the segments, last first: each segment's wavefields are
+  recomputed from its checkpoint into a segment buffer, then for n descending
+  ``fd_adjoint_step`` forms lambda^n from lambda^{n+1}, lambda^{n+2} with the
+  gradient g += D lambda^{n+1} (L u^n + f^n) fused in, and ``fd_scatter_add`` adds
+  the trace residual of step n-1 at the receivers,
+* ``fd_grad_finalize``: grad_m = -g vdt2^2 / dt^2.
+
+dt and the sponge are fixed when the problem is built (they do not depend on m).
+All device work runs in libfd's kernels; torch allocates buffers and copies
+checkpoints.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import api
+
+
+class FWIProblem:
+    """One shot of an FWI gradient: geometry, time axis, source, receivers."""
+
+    def __init__(self, shape, dt: float, src, rec: np.ndarray, nt: int, d=(10.0, 10.0, 10.0),
+                 sponge_width: int = 16, sponge_vmax: float | None = None,
+                 f0: float = api.RICKER_F0, t0: float | None = None,
+                 checkpoint_every: int = 32, device="cuda"):
+        nx, ny, nz = shape
+        self.grid = g = api.Grid(nx, ny, nz, d)
+        self.dt = float(dt)
+        self.nt = int(nt)
+        self.src = tuple(int(x) for x in src)
+        self.device = device
+        self.C = int(checkpoint_every)
+        if self.C < 1:
+            raise ValueError("checkpoint_every must be >= 1")
+        if sponge_width > 0:
+            if sponge_vmax is None:
+                raise ValueError("a sponge needs the (fixed) vmax it is designed for")
+            self.sponge = api.Sponge(g, sponge_width, sponge_vmax, self.dt, device=device)
+        else:
+            self.sponge = None
+        self.w = api.ricker(self.nt, self.dt, f0, t0)
+        self.rec_off = torch.from_numpy(g.offsets(rec)).to(device)
+        self.nrec = self.rec_off.numel()
+        self.src_off = torch.from_numpy(g.offsets(np.array([self.src], np.int32))).to(device)
+        self.m = g.zeros(device)
+        self.vdt2 = g.zeros(device)
+        self.ckpt: list[tuple[torch.Tensor, torch.Tensor]] = []
+
+    # ------------------------------------------------------------ forward
+    def set_model(self, m_interior: torch.Tensor):
+        g = self.grid
+        g.interior(self.m).copy_(m_interior.detach())
+        # only m's interior is read: vdt2's face halos take its periodic image
+        api.prepare_vdt2_m(g, self.m, self.vdt2, self.dt)
+
+    def forward(self, m_interior: torch.Tensor, checkpoints: bool = True) -> torch.Tensor:
+        """Traces (nt, nrec) of the model m; keeps checkpoints for ``backward``."""
+        g = self.grid
+        self.set_model(m_interior)
+        up, u, un = g.zeros(self.device), g.zeros(self.device), g.zeros(self.device)
+        traces = torch.zeros((self.nt, self.nrec), dtype=torch.float32, device=self.device)
+        self.ckpt = []
+        for n in range(self.nt):
+            if checkpoints and n % self.C == 0:
+                self.ckpt.append((up.clone(), u.clone()))
+            api.step(g, up, u, un, self.vdt2, self.sponge)
+            api.inject_source(g, un, self.vdt2, self.sponge, self.src, float(self.w[n]))
+            api.record_receivers(g, un, self.rec_off, traces[n])
+            up, u, un = u, un, up
+        return traces
+
+    # ------------------------------------------------------------ adjoint
+    def backward(self, res: torch.Tensor, want_lambda_src: bool = False):
+        """grad_m (interior, float32) for trace residual ``res`` (nt, nrec) = dLoss/dtraces.
+        With ``want_lambda_src`` also returns lambda^{n+1} at the source for each n
+        (the adjoint field that the source's own sensitivity is read from)."""
+        g = self.grid
+        nt, C = self.nt, self.C
+        if not self.ckpt:
+            raise RuntimeError("backward needs a forward run with checkpoints")
+        res = res.to(device=self.device, dtype=torch.float32).contiguous()
+        if res.shape != (nt, self.nrec):
+            raise ValueError(f"residual must be ({nt}, {self.nrec})")
+        A = g.zeros(self.device)  # lambda^{n+2}
+        B = g.zeros(self.device)  # lambda^{n+1}
+        api.scatter_add(g, B, self.rec_off, res[nt - 1])
+        gq = g.zeros(self.device)
+        seg = [g.zeros(self.device) for _ in range(min(C, nt))]
+        lam_src = torch.zeros(nt, dtype=torch.float32, device=self.device) if want_lambda_src else None
+        for j in range(len(self.ckpt) - 1, -1, -1):
+            s = j * C
+            e = min(s + C, nt)
+            prev, cur = self.ckpt[j]
+            seg[0].copy_(cur)
+            before = prev
+            for n in range(s, e - 1):  # recompute u^{s+1} .. u^{e-1}
+                i = n - s
+                api.step(g, before, seg[i], seg[i + 1], self.vdt2, self.sponge)
+                api.inject_source(g, seg[i + 1], self.vdt2, self.sponge, self.src, float(self.w[n]))
+                before = seg[i]
+            for n in range(e - 1, s - 1, -1):
+                if lam_src is not None:
+                    api.record_receivers(g, B, self.src_off, lam_src[n:n + 1])
+                api.adjoint_step(g, A, B, A, self.vdt2, self.sponge, u_n=seg[n - s], g_vdt2=gq,
+                                 src=(self.src, float(self.w[n])))
+                if n >= 1:
+                    api.scatter_add(g, A, self.rec_off, res[n - 1])
+                A, B = B, A
+        gm = g.zeros(self.device)
+        api.grad_finalize(g, gq, self.vdt2, self.dt, gm)
+        out = g.interior(gm).clone()
+        if want_lambda_src:
+            return out, lam_src
+        return out
+
+
+class FWIGrad(torch.autograd.Function):
+    """traces = FWIGrad.apply(m, problem); m is the (nz, ny, nx) interior of the
+    squared slowness on the device.  backward gives dLoss/dm."""
+
+    @staticmethod
+    def forward(ctx, m: torch.Tensor, problem: FWIProblem):
+        ctx.problem = problem
+        return problem.forward(m)
+
+    @staticmethod
+    def backward(ctx, grad_traces: torch.Tensor):
+        return ctx.problem.backward(grad_traces), None
+
+
+def misfit_gradient(problem: FWIProblem, m: torch.Tensor, obs: torch.Tensor):
+    """J = 1/2 sum (traces - obs)^2 (accumulated in float64) and dJ/dm."""
+    m = m.detach().clone().requires_grad_(True)
+    tr = FWIGrad.apply(m, problem)
+    r = tr - obs
+    J = 0.5 * float((r.double() ** 2).sum().item())
+    tr.backward(r)
+    return J, m.grad

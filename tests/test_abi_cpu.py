@@ -1,0 +1,158 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every function
+that include/fd.h declares, and rejects invalid arguments before any launch.
+
+Every call that passes fake (never dereferenced) device pointers here is one that
+the validation layer must refuse, so nothing is ever enqueued.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2506_02486_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000  # non-NULL, never dereferenced: each call below fails validation first
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "fd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", src,
+                                 flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def grid(L, nx=64, ny=48, nz=40, d=(10.0, 10.0, 10.0)):
+    g = _lib.fd_grid()
+    assert L.fd_grid_init(C.byref(g), nx, ny, nz, *d) == 0
+    return g
+
+
+def test_every_declared_symbol_is_exported_and_bound(L):
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(_lib.exported_symbols())
+
+
+def test_strerror_and_last_error(L):
+    for code, word in ((0, b"success"), (-22, b"invalid"), (-12, b"memory"), (-2, b"not found"),
+                       (-11, b"not finished"), (-125, b"cancel"), (-5, b"device")):
+        assert word in L.fd_strerror(code)
+    assert L.fd_strerror(12345)
+    g = _lib.fd_grid()
+    assert L.fd_grid_init(C.byref(g), 0, 4, 4, 1, 1, 1) == _lib.FD_EINVAL
+    assert b"extent" in L.fd_last_error()
+
+
+def test_grid_init_layout(L):
+    for n in (1, 5, 63, 64, 100, 512, 1024):
+        g = grid(L, n, 7, 3)
+        assert g.halo == 4
+        assert g.ystride % 32 == 0 and g.ystride >= n + 8
+        assert g.zstride == g.ystride * (7 + 8)
+        assert g.origin % 32 == 0                       # interior rows 128-byte aligned
+        assert (g.origin - 4) % 32 == 28                # x halo sits right before the row
+        last = g.origin + (3 + 3) * g.zstride + (7 + 3) * g.ystride + n + 3
+        assert L.fd_grid_elems(C.byref(g)) == last + 1
+        assert L.fd_offset(C.byref(g), -4, -4, -4) >= 0
+        assert L.fd_offset(C.byref(g), n + 4, 0, 0) == -1
+    g = grid(L, 10, 11, 12)
+    assert [L.fd_face_elems(C.byref(g), f) for f in range(6)] == [4 * 11 * 12] * 2 + \
+        [4 * 10 * 12] * 2 + [4 * 10 * 11] * 2
+    assert L.fd_face_elems(C.byref(g), 6) == -1
+
+
+@pytest.mark.parametrize("bad", ["halo", "ystride", "zstride", "origin", "dx", "nz", "big"])
+def test_invalid_geometry_rejected(L, bad):
+    g = grid(L)
+    if bad == "halo":
+        g.halo = 3
+    elif bad == "ystride":
+        g.ystride = g.nx + 7
+    elif bad == "zstride":
+        g.zstride = g.ystride * (g.ny + 7)
+    elif bad == "origin":
+        g.origin = 4 * g.zstride
+    elif bad == "dx":
+        g.dx = float("nan")
+    elif bad == "nz":
+        g.nz = 0
+    elif bad == "big":
+        g.zstride = 1 << 31
+    assert L.fd_grid_elems(C.byref(g)) == -1
+    assert L.fd_step(C.byref(g), FAKE, FAKE * 2, FAKE * 3, FAKE * 4, None, None) == _lib.FD_EINVAL
+    big = _lib.fd_grid()
+    assert L.fd_grid_init(C.byref(big), 40000, 60000, 8, 1, 1, 1) == _lib.FD_EINVAL  # > 2^31
+
+
+def test_step_argument_checks(L):
+    g = grid(L)
+    n = L.fd_grid_elems(C.byref(g)) * 4
+    a, b, c, q = FAKE, FAKE + 4 * n, FAKE + 8 * n, FAKE + 12 * n
+    EINVAL = _lib.FD_EINVAL
+    assert L.fd_step(C.byref(g), a, b, None, q, None, None) == EINVAL          # NULL
+    assert L.fd_step(C.byref(g), a, b, b, q, None, None) == EINVAL             # u_next == u
+    assert L.fd_step(C.byref(g), a, b, b + 4, q, None, None) == EINVAL         # overlaps u
+    assert L.fd_step(C.byref(g), a, b, q, q, None, None) == EINVAL             # overlaps vdt2
+    assert L.fd_step(C.byref(g), a, b, a + 16, q, None, None) == EINVAL        # partial alias
+    sp = _lib.fd_sponge(FAKE, None, None)
+    assert L.fd_step(C.byref(g), a, b, c, q, C.byref(sp), None) == EINVAL      # 1 of 3 tables
+    assert L.inject_source(C.byref(g), c, q, None, 64, 0, 0, 1.0, None) == EINVAL
+    assert L.inject_source(C.byref(g), c, q, None, -1, 0, 0, 1.0, None) == EINVAL
+    assert L.record_receivers(C.byref(g), a, FAKE, -1, FAKE, None) == EINVAL
+    assert L.record_receivers(C.byref(g), a, FAKE, 0, FAKE, None) == 0         # nothing to do
+    assert L.fd_scatter_add(C.byref(g), a, FAKE, FAKE, -3, None) == EINVAL
+    assert L.fd_prepare_vdt2(C.byref(g), a, a + 4, 1e-3, None) == EINVAL
+    assert L.fd_prepare_vdt2(C.byref(g), a, b, -1.0, None) == EINVAL
+    assert L.fd_grad_finalize(C.byref(g), a, b, 0.0, c, None) == EINVAL
+    assert L.fd_cfl_dt(C.byref(g), a, 0.4, None, None, None, None) == EINVAL
+
+
+def test_halo_and_adjoint_argument_checks(L):
+    EINVAL = _lib.FD_EINVAL
+    small = grid(L, 3, 8, 8)
+    faces = (C.c_void_p * 6)(FAKE, None, None, None, None, None)
+    assert L.halo_pack(C.byref(small), FAKE, faces, None) == EINVAL    # nx < 4 on an x face
+    assert L.halo_unpack(C.byref(small), FAKE, faces, None) == EINVAL
+    assert L.halo_pack(C.byref(small), None, faces, None) == EINVAL
+    assert L.halo_pack(C.byref(small), FAKE, None, None) == EINVAL
+    g = grid(L)
+    n = L.fd_grid_elems(C.byref(g)) * 4
+    a, b, c, q, u, gg = (FAKE + i * 4 * n for i in range(6))
+    assert L.fd_adjoint_step(C.byref(g), a, b, b, q, None, None, None, None, None) == EINVAL
+    assert L.fd_adjoint_step(C.byref(g), a, b, c, q, None, None, gg, None, None) == EINVAL  # no u_n
+    assert L.fd_adjoint_step(C.byref(g), a, b, c, q, None, u, b, None, None) == EINVAL  # g == a_n1
+    src = _lib.fd_source(0, 0, 40, 1.0)
+    assert L.fd_adjoint_step(C.byref(g), a, b, c, q, None, u, gg, C.byref(src), None) == EINVAL
+    assert L.fd_adjoint_step(C.byref(g), a, b, a + 4, q, None, None, None, None, None) == EINVAL
+
+
+def test_host_helpers(L):
+    w = np.empty(8, np.float32)
+    assert L.fd_ricker(w.ctypes.data, 8, 0, 1e-3, 15.0, 1.0 / 15) == 0
+    assert L.fd_ricker(w.ctypes.data, 8, 0, -1.0, 15.0, 1.0 / 15) == _lib.FD_EINVAL
+    e = np.empty(40, np.float32)
+    emax = L.fd_sponge_eta_max(4500.0, 10.0, 0.4 * 10 / 4500.0, 16, 1e-3)
+    assert abs(emax - 3 * np.log(1000) * 0.4 / 64) < 1e-12
+    assert L.fd_sponge_eta_max(4500.0, 10.0, 1e-3, 0, 1e-3) == 0.0
+    assert L.fd_sponge_eta_max(4500.0, 10.0, 1e-3, 16, 2.0) == _lib.FD_EINVAL
+    assert L.fd_sponge_profile(e.ctypes.data, 40, 16, emax) == 0
+    assert e[0] == e[-1] and e[16:24].max() == 0 and e[15] > 0
+    g = grid(L, 10, 10, 10)
+    ijk = np.array([[0, 0, 0], [9, 9, 9]], np.int32)
+    off = np.empty(2, np.int64)
+    assert L.fd_receiver_offsets(C.byref(g), ijk.ctypes.data, 2, off.ctypes.data) == 0
+    assert off[0] == g.origin and off[1] == g.origin + 9 * (g.zstride + g.ystride + 1)
+    ijk[1, 2] = 10
+    assert L.fd_receiver_offsets(C.byref(g), ijk.ctypes.data, 2, off.ctypes.data) == _lib.FD_EINVAL
+    assert L.fd_set_kchunk(-1) == _lib.FD_EINVAL
+    assert L.fd_set_kchunk(0) == 0
