@@ -7,12 +7,13 @@ centre, receivers on the centre x-line, the six faces packed and unpacked into
 contiguous buffers every step (loopback exchange) -- after W untimed warm-up steps,
 and prints one JSON line.
 
-A step is one pass of the per-step path: halo_pack, halo_unpack, fd_step,
-inject_source, record_receivers, pointer rotation.  ``value`` is interior points x
-steps / wall time in Gpts/s with every array resident in HBM.  ``roofline`` rates the
-dominant kernel (the fd_step stencil) by its algorithmic bytes (16 B per interior
-point: u^n, u^{n-1} and vdt2 read once, u^{n+1} written once) over its average launch
-time from HIP events on its own stream.  ``cpu_baseline`` times the FP64 CPU oracle on
+A step is one pass of the per-step path: halo_unpack of the faces packed by the
+previous step, fd_step_fused (leapfrog update with the source term in the same
+kernel), halo_pack of the new field, record_receivers, pointer rotation.  ``value``
+is interior points x steps / wall time in Gpts/s with every array resident in HBM.
+``roofline`` rates the dominant kernel (the stencil of fd_step_fused) by its
+algorithmic bytes (16 B per interior point: u^n, u^{n-1} and vdt2 read once, u^{n+1}
+written once) over its average launch time from HIP events on its own stream.  ``cpu_baseline`` times the FP64 CPU oracle on
 a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -103,6 +104,113 @@ def cpu_baseline(v, dt, src, steps):
     }
 
 
+def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.0,
+                  warm=16, load=2.0):
+    """Poisson stream of shots of uneven size: the batching server against the plain
+    per-shot loop (same kernels, one shot at a time, arrival order)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2506_02486_amd import serving
+    from workloads import poisson_arrivals, receivers_xline, serving_shots, smooth_velocity
+
+    log(f"serving: generating the {hi}^3 shared model")
+    vm = smooth_velocity(hi, hi, hi, seed=2)
+    vd = torch.from_numpy(vm).cuda()
+    vmax = float(vm.max())
+    dt = 0.4 * 10.0 / vmax
+    specs = serving_shots(nshots, seed=3, lo=lo, hi=hi)
+
+    def shot(s):
+        nx, ny, nz = s["nx"], s["ny"], s["nz"]
+        return serving.Shot(vd[:nz, :ny, :nx], nt, dt, s["src"], receivers_xline(nx, ny // 2, 4),
+                            sponge_width=16, sponge_vmax=vmax)
+
+    shots = [shot(s) for s in specs]
+    plain = serving.PlainLoop((hi, hi, hi))
+    # plain-loop service rate from warm-up shots (drawn after the stream's shots)
+    warm_specs = serving_shots(nshots + warm, seed=3, lo=lo, hi=hi)[nshots:]
+    t0 = time.perf_counter()
+    for s in warm_specs:
+        plain.run(shot(s))
+    mu = warm / (time.perf_counter() - t0)
+    lam = load * mu
+    arr = poisson_arrivals(nshots, lam, seed=4)
+    pts = float(sum(np.prod(s.shape) for s in shots)) * nt
+    log(f"serving: plain service rate {mu:.2f} shots/s, arrivals at {lam:.2f} shots/s")
+
+    # --- plain loop, in arrival order
+    log("serving: plain loop")
+    plain_tr = {}
+    lat_p = []
+    base = time.monotonic()
+    for i, s in enumerate(shots):
+        wait = base + arr[i] - time.monotonic()
+        if wait > 0:
+            time.sleep(wait)
+        tr = plain.run(s)
+        lat_p.append(time.monotonic() - (base + arr[i]))
+        if i < 8:
+            plain_tr[i] = tr
+    span_p = time.monotonic() - base
+    del plain
+    torch.cuda.empty_cache()
+
+    # --- batching server
+    log("serving: batching server")
+    srv = serving.ShotServer(int(arena_gb * (1 << 30)), max_slots=max_slots)
+    ids = [None] * nshots
+    t_arr = [0] * nshots
+
+    def submitter():
+        b = time.monotonic()
+        for i, s in enumerate(shots):
+            wait = b + arr[i] - time.monotonic()
+            if wait > 0:
+                time.sleep(wait)
+            t_arr[i] = time.monotonic_ns()
+            ids[i] = srv.submit(s)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    res = [None] * nshots
+    pending = set(range(nshots))
+    while pending:
+        for i in list(pending):
+            if ids[i] is None:
+                continue
+            r = srv.poll(ids[i])
+            if r is not None:
+                res[i] = r
+                pending.discard(i)
+        time.sleep(2e-4)
+    th.join()
+    steps = srv.stats()["steps"]
+    srv.close()
+    codes = [r[0] for r in res]
+    lat_s = [(r[2][2] - t_arr[i]) / 1e9 for i, r in enumerate(res)]
+    span_s = (max(r[2][2] for r in res) - min(t_arr)) / 1e9
+    same = all(np.array_equal(res[i][1], plain_tr[i]) for i in plain_tr)
+    pct = lambda x, q: round(float(np.percentile(np.array(x), q)), 4)  # noqa: E731
+    return {
+        "workload": f"{nshots} shots, grids uniform in [{lo},{hi}]^3 (seed 3), {nt} steps, "
+                    f"sponge 16, Ricker 15 Hz, x-line receivers, Poisson arrivals at "
+                    f"{load:g}x the plain loop's service rate (seed 4)",
+        "arrival_rate": round(lam, 3),
+        "server": {"shots_per_s": round(nshots / span_s, 3), "p50_s": pct(lat_s, 50),
+                   "p99_s": pct(lat_s, 99), "Gpts_per_s": round(pts / span_s / 1e9, 2),
+                   "batched_steps": steps, "all_ok": all(c == 0 for c in codes)},
+        "plain_loop": {"shots_per_s": round(nshots / span_p, 3), "p50_s": pct(lat_p, 50),
+                       "p99_s": pct(lat_p, 99), "Gpts_per_s": round(pts / span_p / 1e9, 2)},
+        "speedup_shots_per_s": round(span_p / span_s, 3),
+        "traces_bitwise_equal_first8": bool(same),
+        "max_slots": max_slots,
+        "arena_GB": arena_gb,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +222,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run a plain 1 GiB device copy (for counters)")
     ap.add_argument("--kchunk", type=int, default=0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--shots", type=int, default=256, help="shots in the serving stream")
     ap.add_argument("--vcache", default=None,
                     help="optional .npy path to cache the generated velocity model")
     args = ap.parse_args()
@@ -156,15 +266,16 @@ def main():
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(K)]
     log(f"bench: timing {K} steps")
+    assert sim._faces_current  # the warm-up left the faces of u^n in the send buffers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(K):
-        api.halo_pack(g, sim.u, sim.send)
         api.halo_unpack(g, sim.u, sim.recv)
         ev[s][0].record()
-        api.step(g, sim.u_prev, sim.u, sim.u_next, sim.vdt2, sim.sponge)
+        api.step_fused(g, sim.u_prev, sim.u, sim.u_next, sim.vdt2, sim.sponge,
+                       (src, float(w[s])), None)
         ev[s][1].record()
-        api.inject_source(g, sim.u_next, sim.vdt2, sim.sponge, src, float(w[s]))
+        api.halo_pack(g, sim.u_next, sim.send)
         api.record_receivers(g, sim.u_next, sim.rec_off, traces[s])
         sim.u_prev, sim.u, sim.u_next = sim.u, sim.u_next, sim.u_prev
         sim.n += 1
@@ -175,10 +286,10 @@ def main():
     avg_ms = float(np.mean(kern_ms))
     pts = n ** 3
     gpts = pts * K / elapsed / 1e9
+    face_pts = 6 * 4 * n * n
     algo_bytes = 16.0 * pts
     achieved = algo_bytes / (avg_ms / 1e3) / 1e9
-    face_pts = 6 * 4 * n * n
-    path_bytes = algo_bytes + 8.0 * face_pts
+    path_bytes = 16.0 * pts + 8.0 * face_pts
     finite = bool(torch.isfinite(g.interior(sim.u)).all().item())
     log(f"bench: {elapsed * 1e3 / K:.3f} ms/step, fd_step {avg_ms * 1e3:.1f} us avg, "
         f"{gpts:.1f} Gpts/s, finite={finite}")
@@ -219,7 +330,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "fd_step (stencil_kernel<4,FWD,sponge>)",
+            "kernel": "fd_step_fused stencil (stencil_kernel<64,8,4,FWD,sponge,source>)",
             "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
@@ -237,12 +348,18 @@ def main():
         "gpu": torch.cuda.get_device_name(0),
         "hip": torch.version.hip,
         "finite": finite,
+        "_dt": sim.dt,
     }
+    del sim, traces
+    torch.cuda.empty_cache()
+    if not args.no_serving:
+        out["serving"] = serving_bench(nshots=args.shots)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline ({args.cpu_steps} steps of {n}^3)")
-        out["cpu_baseline"] = cpu_baseline(v, sim.dt, src, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(v, out["_dt"], src, args.cpu_steps)
     else:
         out["cpu_baseline"] = None
+    out.pop("_dt", None)
     print(json.dumps(out), flush=True)
 
 

@@ -67,7 +67,7 @@ typedef struct fd_grid {
   int32_t halo;             /* must be FD_HALO (the stencil radius)                  */
   int64_t origin;           /* element offset of interior (0,0,0); >= 4*zstride+4*ystride+4 */
   int64_t ystride, zstride; /* element strides; ystride >= nx+8,
-                               zstride >= ystride*(ny+8), zstride <= INT32_MAX       */
+                               zstride >= ystride*(ny+8), zstride <= 2^29            */
   double dx, dy, dz;        /* grid spacing (metres), finite and > 0                 */
 } fd_grid;
 
@@ -101,7 +101,7 @@ int fd_version(void);
  * interior row start 128-byte aligned (32 floats of left padding, of which
  * the last 4 are the x halo), ystride a multiple of 32 floats, zstride =
  * ystride*(ny+8).  FD_EINVAL on bad sizes or spacing, or if zstride would
- * exceed INT32_MAX. */
+ * exceed 2^29 elements. */
 int fd_grid_init(fd_grid* g, int32_t nx, int32_t ny, int32_t nz, double dx,
                  double dy, double dz);
 /* Floats the caller must allocate per volume array (origin + the furthest
@@ -176,6 +176,16 @@ int fd_receiver_offsets(const fd_grid* g, const int32_t* ijk_host, int32_t nrec,
 int fd_step(const fd_grid* g, const float* u_prev, const float* u, float* u_next,
             const float* vdt2, const fd_sponge* sp, void* stream);
 
+/* S4+S5+S1 in one call: fd_step with (src non-NULL) the source term src->w
+ * added in the same kernel exactly as inject_source adds it, then
+ * (face_out non-NULL) the six-face pack of the new u_next exactly as
+ * halo_pack writes it (NULL entries skipped; faces need n >= 4 on their axis
+ * and must not overlap a volume array).  Bitwise the same results as
+ * fd_step + inject_source + halo_pack; one stencil launch plus the pack. */
+int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* u_next,
+                  const float* vdt2, const fd_sponge* sp, const fd_source* src,
+                  float* const face_out[6], void* stream);
+
 /* S5: u_next[s] += vdt2[s] * w / (1+eta[s]) at interior point s = (i,j,k). */
 int inject_source(const fd_grid* g, float* u_next, const float* vdt2,
                   const fd_sponge* sp, int32_t i, int32_t j, int32_t k, float w,
@@ -228,6 +238,76 @@ int fd_scatter_add(const fd_grid* g, float* a, const int64_t* off, const float* 
 /* grad_m = -g_vdt2 * vdt2^2 / dt^2 on the interior (m = 1/v^2, dt fixed). */
 int fd_grad_finalize(const fd_grid* g, const float* g_vdt2, const float* vdt2,
                      double dt, float* grad_m, void* stream);
+
+/* ------------------------------------------------------- shot serving
+ * S8/S9: a server that runs many independent forward-modelling shots of
+ * different grid sizes at once.  Shots are admitted in submission order
+ * (strict FIFO) while a slot is free and the shot's footprint fits in the
+ * caller's device arena; every active shot then advances one time step per
+ * batched launch (one kernel over the tiles of all active grids, each shot
+ * at its own step, followed by one batched receiver kernel), so shots that
+ * arrive while others run share the device.  Finished shots' traces are
+ * copied to pinned host memory on a copy stream and their arena block is
+ * freed.  Each shot is the forward model of fd_step_fused with Dirichlet
+ * halos, a quadratic sponge of `sponge_width` cells (reflection 1e-3) and a
+ * Ricker source; its traces are bitwise those of the same shot run alone
+ * through fd_step_fused + record_receivers with the same dt and sponge. */
+
+typedef struct fd_shot_desc {
+  int32_t nx, ny, nz;        /* interior extent, each >= 1                       */
+  int32_t nt;                /* time steps, >= 1                                  */
+  double dx, dy, dz;         /* spacing, > 0                                       */
+  double dt;                 /* time step; the shot ends with FD_EINVAL at admission
+                                if max(v) dt sqrt(s_pi sum_a 1/d_a^2) > 2, the
+                                leapfrog stability limit of this stencil (s_pi =
+                                6.5016 is its 1-D symbol at the Nyquist wavenumber;
+                                Courant 0.45286 on a cube)                     */
+  double f0, t0;             /* Ricker peak frequency and delay                   */
+  int32_t src[3];            /* source point, inside the interior                 */
+  int32_t sponge_width;      /* damping cells per face (0: none)                  */
+  double sponge_vmax;        /* velocity the sponge is designed for; <= 0: the
+                                shot's own max(v)                                  */
+  const float* v_dev;        /* caller-owned device velocity view: point (i,j,k)
+                                at v_dev[k*v_zstride + j*v_ystride + i]; must stay
+                                valid and unchanged until the shot is done        */
+  int64_t v_ystride, v_zstride;
+  int32_t nrec;              /* receivers, >= 0                                    */
+  const int32_t* rec_ijk_host; /* 3*nrec (i,j,k) triples, copied at submit        */
+} fd_shot_desc;
+
+/* Arena bytes one shot occupies while active (4 padded volumes, sponge
+ * tables, receiver offsets, traces); -1 for an invalid descriptor. */
+int64_t fd_shot_footprint(const fd_shot_desc* d);
+
+/* Create a server over the caller-owned device arena [arena_dev,
+ * arena_dev + arena_bytes) (256-byte aligned; about 1.1 MB of it holds the
+ * server's tables), running at most max_slots (1..64) shots at once.
+ * compute_stream / copy_stream are hipStream_t (NULL: the server creates
+ * its own).  The arena must outlive the server.  Starts the progress thread. */
+int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t max_slots,
+                     void* compute_stream, void* copy_stream);
+/* Queue a shot.  FD_EINVAL for a bad descriptor (sizes, source or receiver
+ * outside the interior, NULL velocity), FD_ENOMEM if its footprint can never
+ * fit the arena, FD_ECANCELED after shutdown.  Thread-safe. */
+int shot_submit(void* srv, const fd_shot_desc* d, int64_t* shot_id);
+/* FD_EAGAIN while queued or running.  When finished: copies min(cap,
+ * nt*nrec) floats of traces ([nt][nrec], u^{n+1} at receiver r after step n)
+ * into traces_host (may be NULL), fills t_ns (may be NULL) with the
+ * submit, admit and done times (steady clock, ns; done = when the server saw
+ * the traces land in host memory), forgets the shot and returns its final
+ * code: FD_OK, FD_EINVAL (rejected at admission, e.g. unstable dt),
+ * FD_EDEVICE or FD_ECANCELED.  FD_ENOTFOUND for an unknown or already
+ * collected id.  Thread-safe. */
+int shot_poll(void* srv, int64_t shot_id, float* traces_host, size_t cap, int64_t t_ns[3]);
+/* Counts of queued, running, finished-but-uncollected shots, and batched
+ * steps launched so far (4 int64).  Thread-safe. */
+int fd_server_stats(void* srv, int64_t out[4]);
+/* Stop the progress thread: queued and running shots finish as
+ * FD_ECANCELED; finished shots stay collectable by shot_poll; later submits
+ * fail with FD_ECANCELED.  Idempotent. */
+int fd_server_shutdown(void* srv);
+/* Shut down (as above) and free the server; its shot ids become invalid. */
+int fd_server_destroy(void* srv);
 
 #ifdef __cplusplus
 }

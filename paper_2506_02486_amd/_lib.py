@@ -35,6 +35,15 @@ class fd_source(C.Structure):
     _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("k", C.c_int32), ("w", C.c_float)]
 
 
+class fd_shot_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nt", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
+                ("f0", C.c_double), ("t0", C.c_double), ("src", C.c_int32 * 3),
+                ("sponge_width", C.c_int32), ("sponge_vmax", C.c_double),
+                ("v_dev", C.c_void_p), ("v_ystride", C.c_int64), ("v_zstride", C.c_int64),
+                ("nrec", C.c_int32), ("rec_ijk_host", C.c_void_p)]
+
+
 class FDError(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
         super().__init__(f"{where}: {detail or 'error'} (code {code})")
@@ -65,6 +74,8 @@ SIGNATURES = {
     "fd_ricker": (C.c_int, [_P, _i32, _i32, _f64, _f64, _f64]),
     "fd_receiver_offsets": (C.c_int, [_G, _P, _i32, _P]),
     "fd_step": (C.c_int, [_G, _P, _P, _P, _P, _S, _P]),
+    "fd_step_fused": (C.c_int, [_G, _P, _P, _P, _P, _S, C.POINTER(fd_source), C.POINTER(_P),
+                                _P]),
     "inject_source": (C.c_int, [_G, _P, _P, _S, _i32, _i32, _i32, _f32, _P]),
     "record_receivers": (C.c_int, [_G, _P, _P, _i32, _P, _P]),
     "halo_pack": (C.c_int, [_G, _P, C.POINTER(_P), _P]),
@@ -72,6 +83,13 @@ SIGNATURES = {
     "fd_adjoint_step": (C.c_int, [_G, _P, _P, _P, _P, _S, _P, _P, C.POINTER(fd_source), _P]),
     "fd_scatter_add": (C.c_int, [_G, _P, _P, _P, _i32, _P]),
     "fd_grad_finalize": (C.c_int, [_G, _P, _P, _f64, _P, _P]),
+    "fd_shot_footprint": (_i64, [C.POINTER(fd_shot_desc)]),
+    "fd_server_create": (C.c_int, [C.POINTER(_P), _P, C.c_size_t, _i32, _P, _P]),
+    "shot_submit": (C.c_int, [_P, C.POINTER(fd_shot_desc), C.POINTER(_i64)]),
+    "shot_poll": (C.c_int, [_P, _i64, _P, C.c_size_t, C.POINTER(_i64)]),
+    "fd_server_stats": (C.c_int, [_P, C.POINTER(_i64)]),
+    "fd_server_shutdown": (C.c_int, [_P]),
+    "fd_server_destroy": (C.c_int, [_P]),
 }
 
 _lib = None

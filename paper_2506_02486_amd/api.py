@@ -155,6 +155,22 @@ def step(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None = None, stre
                         vdt2.data_ptr(), sponge_ref(sponge), _stream(stream)), "fd_step")
 
 
+def step_fused(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None = None, src=None,
+               faces=None, stream=None):
+    """fd_step + inject_source (``src`` = ((i,j,k), w)) + halo_pack of u_next into
+    ``faces`` (six buffers or None entries), in one kernel."""
+    for n, t in (("u_prev", u_prev), ("u", u), ("u_next", u_next), ("vdt2", vdt2)):
+        grid.check(t, n)
+    sref = None
+    if src is not None:
+        (i, j, k), w = src
+        sref = C.byref(fd_source(int(i), int(j), int(k), float(w)))
+    check(lib().fd_step_fused(grid.ref, u_prev.data_ptr(), u.data_ptr(), u_next.data_ptr(),
+                              vdt2.data_ptr(), sponge_ref(sponge), sref,
+                              None if faces is None else _faces(faces), _stream(stream)),
+          "fd_step_fused")
+
+
 def inject_source(grid: Grid, u_next, vdt2, sponge, ijk, w: float, stream=None):
     grid.check(u_next, "u_next")
     grid.check(vdt2, "vdt2")
@@ -281,6 +297,7 @@ class Simulation:
             raise ValueError("exchange must be None or 'loopback'")
         self.send = face_buffers(g, device) if exchange else None
         self.recv = loopback(self.send) if exchange else None
+        self._faces_current = True  # zero state, zero face buffers
         rec = self.geom.rec
         if rec is not None and len(rec):
             self.rec_off = torch.from_numpy(g.offsets(rec)).to(device)
@@ -291,8 +308,15 @@ class Simulation:
     def nrec(self) -> int:
         return 0 if self.rec_off is None else self.rec_off.numel()
 
-    def run(self, nt: int, traces: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """Advance ``nt`` steps; returns (nt, nrec) device traces (u^{n+1} at receivers)."""
+    def run(self, nt: int, traces: torch.Tensor | None = None, stream=None,
+            fused: bool = True) -> torch.Tensor:
+        """Advance ``nt`` steps; returns (nt, nrec) device traces (u^{n+1} at receivers).
+
+        ``fused`` (default) runs per step: halo_unpack of the faces packed during the
+        previous step, then one fd_step_fused (update + source + pack of the new
+        field), then record_receivers.  ``fused=False`` issues the separate calls
+        halo_pack, halo_unpack, fd_step, inject_source, record_receivers.  Both give
+        the same bits."""
         g = self.grid
         if traces is None:
             traces = torch.zeros((nt, max(self.nrec, 1)), dtype=torch.float32, device=self.device)
@@ -300,17 +324,30 @@ class Simulation:
         w = None
         if geom.src is not None:
             w = ricker(nt, self.dt, geom.f0, geom.t0, n0=self.n)
+        if fused and self.exchange and not self._faces_current:
+            halo_pack(g, self.u, self.send, stream)
         for s in range(nt):
-            if self.exchange:
-                halo_pack(g, self.u, self.send, stream)
-                halo_unpack(g, self.u, self.recv, stream)
-            step(g, self.u_prev, self.u, self.u_next, self.vdt2, self.sponge, stream)
-            if w is not None:
-                inject_source(g, self.u_next, self.vdt2, self.sponge, geom.src, float(w[s]), stream)
+            if fused:
+                if self.exchange:
+                    halo_unpack(g, self.u, self.recv, stream)
+                src = None if w is None else (geom.src, float(w[s]))
+                step_fused(g, self.u_prev, self.u, self.u_next, self.vdt2, self.sponge, src,
+                           self.send if self.exchange else None, stream)
+            else:
+                if self.exchange:
+                    halo_pack(g, self.u, self.send, stream)
+                    halo_unpack(g, self.u, self.recv, stream)
+                step(g, self.u_prev, self.u, self.u_next, self.vdt2, self.sponge, stream)
+                if w is not None:
+                    inject_source(g, self.u_next, self.vdt2, self.sponge, geom.src, float(w[s]),
+                                  stream)
             if self.rec_off is not None:
                 record_receivers(g, self.u_next, self.rec_off, traces[s], stream)
             self.u_prev, self.u, self.u_next = self.u, self.u_next, self.u_prev
             self.n += 1
+        # after a fused step the send buffers hold the faces of the current u
+        self._faces_current = bool(fused and self.exchange and nt > 0) or (
+            self._faces_current and nt == 0)
         return traces[:, :self.nrec]
 
     def state(self):

@@ -65,8 +65,8 @@ int check_grid(const fd_grid* g) {
     return fail(FD_EINVAL, "ystride %lld < nx+8", (long long)g->ystride);
   if (g->zstride < g->ystride * ((int64_t)g->ny + 8))
     return fail(FD_EINVAL, "zstride %lld < ystride*(ny+8)", (long long)g->zstride);
-  if (g->zstride > (int64_t)std::numeric_limits<int32_t>::max())
-    return fail(FD_EINVAL, "zstride %lld exceeds INT32_MAX", (long long)g->zstride);
+  if (g->zstride > FD_MAX_ZSTRIDE)
+    return fail(FD_EINVAL, "zstride %lld exceeds 2^29", (long long)g->zstride);
   if (g->origin < 4 * g->zstride + 4 * g->ystride + 4)
     return fail(FD_EINVAL, "origin %lld leaves no room for the halo", (long long)g->origin);
   if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dz))
@@ -290,8 +290,47 @@ int fd_step(const fd_grid* g, const float* u_prev, const float* u, float* u_next
   rc = check_sponge(sp, &ex, &ey, &ez);
   if (rc) return rc;
   return check_hip(launch_step(make_geo(g), make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez,
-                               as_stream(stream)),
+                               nullptr, as_stream(stream)),
                    "fd_step launch");
+}
+
+static int check_faces(const fd_grid* g, const void* const* face, const char* who);
+
+int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* u_next,
+                  const float* vdt2, const fd_sponge* sp, const fd_source* src,
+                  float* const face_out[6], void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!u_prev || !u || !u_next || !vdt2) return fail(FD_EINVAL, "fd_step_fused: NULL array");
+  if (overlaps(g, u, u_next)) return fail(FD_EINVAL, "fd_step_fused: u_next overlaps u");
+  if (overlaps(g, vdt2, u_next)) return fail(FD_EINVAL, "fd_step_fused: u_next overlaps vdt2");
+  if (u_next != u_prev && overlaps(g, u_prev, u_next))
+    return fail(FD_EINVAL, "fd_step_fused: u_next partially overlaps u_prev");
+  if (src && (src->i < 0 || src->i >= g->nx || src->j < 0 || src->j >= g->ny || src->k < 0 ||
+              src->k >= g->nz))
+    return fail(FD_EINVAL, "fd_step_fused: source outside the interior");
+  if (face_out) {
+    rc = check_faces(g, (const void* const*)face_out, "fd_step_fused");
+    if (rc) return rc;
+    for (int f = 0; f < 6; ++f) {
+      const float* fp = face_out[f];
+      if (!fp) continue;
+      const int64_t n = fd_face_elems(g, f);
+      const float* vols[4] = {u_prev, u, u_next, vdt2};
+      for (const float* a : vols)
+        if (fp < a + last_elem(g) + 1 && a < fp + n)
+          return fail(FD_EINVAL, "fd_step_fused: face %d overlaps a volume array", f);
+    }
+  }
+  const float *ex, *ey, *ez;
+  rc = check_sponge(sp, &ex, &ey, &ez);
+  if (rc) return rc;
+  const Geo geo = make_geo(g);
+  hipStream_t s = as_stream(stream);
+  rc = check_hip(launch_step(geo, make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez, src, s),
+                 "fd_step_fused launch");
+  if (rc || !face_out) return rc;
+  return check_hip(launch_pack(geo, u_next, face_out, s), "fd_step_fused pack launch");
 }
 
 int inject_source(const fd_grid* g, float* u_next, const float* vdt2, const fd_sponge* sp,

@@ -112,7 +112,9 @@ __global__ void __launch_bounds__(BS) scatter_add_kernel(float* a, const int64_t
 
 // One thread per element of the padded box [-4,n+4)^3, one block row per
 // (j,k) line: interior from v, face halo from the periodic image, edges 0.
-__global__ void __launch_bounds__(BS) prep_vdt2_kernel(Geo g, const float* __restrict__ v,
+// v0 points at interior (0,0,0) of the input, which has its own strides.
+__global__ void __launch_bounds__(BS) prep_vdt2_kernel(Geo g, const float* __restrict__ v0,
+                                                       long long vsy, long long vsz,
                                                        float* __restrict__ q, double dt,
                                                        bool from_m) {
   const int jj = blockIdx.y - 4;  // j in [-4, ny+4)
@@ -134,10 +136,11 @@ __global__ void __launch_bounds__(BS) prep_vdt2_kernel(Geo g, const float* __res
       while (cj >= g.ny) cj -= g.ny;
       while (ck < 0) ck += g.nz;
       while (ck >= g.nz) ck -= g.nz;
+      const float vin = v0[(long long)ck * vsz + (long long)cj * vsy + ci];
       if (from_m) {
-        val = (float)(dt * dt / (double)v[at(g, ci, cj, ck)]);
+        val = (float)(dt * dt / (double)vin);
       } else {
-        const double vv = (double)v[at(g, ci, cj, ck)] * dt;
+        const double vv = (double)vin * dt;
         val = (float)(vv * vv);
       }
     }
@@ -161,15 +164,16 @@ __device__ __forceinline__ int wave_min(int v) {
   return v;
 }
 
-__global__ void __launch_bounds__(BS) vmax_kernel(Geo g, const float* __restrict__ v,
-                                                  int32_t* out) {
-  const long long nline = (long long)g.ny * g.nz;
+__global__ void __launch_bounds__(BS) vmax_kernel(int nx, int ny, int nz,
+                                                  const float* __restrict__ v0, long long vsy,
+                                                  long long vsz, int32_t* out) {
+  const long long nline = (long long)ny * nz;
   int mx = 0, mn = 0x7f800000;
   for (long long line = blockIdx.x; line < nline; line += gridDim.x) {
-    const int j = (int)(line % g.ny);
-    const int k = (int)(line / g.ny);
-    const float* row = v + at(g, 0, j, k);
-    for (int i = threadIdx.x; i < g.nx; i += BS) {
+    const int j = (int)(line % ny);
+    const int k = (int)(line / ny);
+    const float* row = v0 + (long long)k * vsz + (long long)j * vsy;
+    for (int i = threadIdx.x; i < nx; i += BS) {
       const int bits = __float_as_int(row[i]);
       mx = max(mx, bits);
       mn = min(mn, bits);
@@ -193,6 +197,24 @@ __global__ void __launch_bounds__(BS) grad_finalize_kernel(Geo g, const float* _
     const float qq = q[o];
     gm[o] = -gq[o] * qq * qq * s;
   }
+}
+
+__global__ void __launch_bounds__(BS) zero_kernel(float* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)BS + threadIdx.x; i < n; i += (long long)gridDim.x * BS)
+    dst[i] = 0.f;
+}
+
+// blockIdx.y = position in the active-slot list; x covers that shot's receivers.
+// Runs after the batched step of the same BatchStep: u^{n+1} is in arr[(n+1) % 3].
+__global__ void __launch_bounds__(BS) batched_record_kernel(const BatchShot* __restrict__ shots,
+                                                            const int* __restrict__ slots,
+                                                            BatchStep a) {
+  const int slot = slots[blockIdx.y];
+  const BatchShot& b = shots[slot];
+  const int r = blockIdx.x * BS + threadIdx.x;
+  if (r >= b.nrec) return;
+  const int n = a.n[slot];
+  b.traces[(long long)n * b.nrec + r] = b.arr[(n + 1) % 3][b.rec[r]];
 }
 
 unsigned blocks_for(long long n, unsigned cap) {
@@ -255,17 +277,44 @@ hipError_t launch_scatter_add(float* a, const int64_t* off, const float* vals, i
 hipError_t launch_prepare_vdt2(const Geo& g, const float* v, float* q, double dt, bool from_m,
                                hipStream_t s) {
   const unsigned bx = blocks_for(g.nx + 8, 64);
-  hipLaunchKernelGGL(prep_vdt2_kernel, dim3(bx, g.ny + 8, g.nz + 8), dim3(BS), 0, s, g, v, q,
-                     dt, from_m);
+  hipLaunchKernelGGL(prep_vdt2_kernel, dim3(bx, g.ny + 8, g.nz + 8), dim3(BS), 0, s, g,
+                     v + g.org, (long long)g.sy, (long long)g.sz, q, dt, from_m);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_vdt2_view(const Geo& g, const float* v, long long vsy, long long vsz,
+                                    float* q, double dt, hipStream_t s) {
+  const unsigned bx = blocks_for(g.nx + 8, 64);
+  hipLaunchKernelGGL(prep_vdt2_kernel, dim3(bx, g.ny + 8, g.nz + 8), dim3(BS), 0, s, g, v, vsy,
+                     vsz, q, dt, false);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(float* dst, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(n, 8192)), dim3(BS), 0, s, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_record(const BatchShot* shots, const int* slots, int nslots,
+                                 int max_nrec, const BatchStep& a, hipStream_t s) {
+  if (nslots <= 0 || max_nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batched_record_kernel, dim3((max_nrec + BS - 1) / BS, nslots), dim3(BS), 0,
+                     s, shots, slots, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_vmax_view(int nx, int ny, int nz, const float* v, long long vsy,
+                            long long vsz, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(vmax_init_kernel, dim3(1), dim3(64), 0, s, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(vmax_kernel, dim3(2048), dim3(BS), 0, s, nx, ny, nz, v, vsy, vsz, out);
   return hipGetLastError();
 }
 
 hipError_t launch_vmax(const Geo& g, const float* v, int32_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(vmax_init_kernel, dim3(1), dim3(64), 0, s, out);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(vmax_kernel, dim3(2048), dim3(BS), 0, s, g, v, out);
-  return hipGetLastError();
+  return launch_vmax_view(g.nx, g.ny, g.nz, v + g.org, g.sy, g.sz, out, s);
 }
 
 hipError_t launch_grad_finalize(const Geo& g, const float* gq, const float* q, double dt,

@@ -9,6 +9,9 @@
 
 namespace fd {
 
+// In-plane byte offsets are 32-bit unsigned in the stencil kernels.
+constexpr long long FD_MAX_ZSTRIDE = (1LL << 29);
+
 // Thread-local error detail; returns `code` so callers can `return fail(...)`.
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 // Map a HIP error to FD_EDEVICE with detail, or FD_OK.
@@ -18,7 +21,7 @@ int check_hip(hipError_t e, const char* what);
 struct Geo {
   int nx, ny, nz;
   int sy;          // ystride (elements)
-  int sz;          // zstride (elements), <= INT32_MAX
+  int sz;          // zstride (elements), <= FD_MAX_ZSTRIDE
   long long org;   // origin (elements)
 };
 
@@ -41,11 +44,55 @@ struct Coef {
 };
 Coef make_coef(const fd_grid* g);
 
+// One shot of a batched launch (device memory, written by the shot server).
+struct BatchShot {
+  Geo g;
+  Coef c;
+  float* arr[3];        // wavefields; u^n lives in arr[n % 3]
+  const float* q;       // vdt2
+  const float* ex;      // sponge tables (all zeros when the shot has none)
+  const float* ey;
+  const float* ez;
+  int si, sj, sk;       // source point
+  int kchunk;           // z planes per tile-table entry
+  const int64_t* rec;   // receiver offsets
+  float* traces;        // nt x nrec
+  int nrec;
+  int pad_;
+};
+
+constexpr int MAX_BATCH_SLOTS = 64;
+
+// Per-step arguments of a batched launch (by value).
+struct BatchStep {
+  int n[MAX_BATCH_SLOTS];    // steps done so far by the shot in each slot
+  float w[MAX_BATCH_SLOTS];  // its source amplitude for this step
+};
+
 // ------------------------------------------------------------ launchers
 // All validate nothing (the ABI layer has) and return a HIP error code.
+// src may be NULL (no fused source term)
 hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float* u,
                        float* un, const float* q, const float* ex, const float* ey,
-                       const float* ez, hipStream_t s);
+                       const float* ez, const fd_source* src, hipStream_t s);
+// Tile size (x, y) of the batched kernel; returns threads per block.
+int batch_tile_shape(int* tx, int* ty);
+// One time step of every shot listed in the tile table (entries: slot, bx, by, bz).
+hipError_t launch_batched(const BatchShot* shots, const int4* tiles, int ntiles,
+                          const BatchStep& a, hipStream_t s);
+// trace[n][r] = u^{n+1}[rec[r]] for every active slot (slots[i], i < nslots).
+hipError_t launch_batched_record(const BatchShot* shots, const int* slots, int nslots,
+                                 int max_nrec, const BatchStep& a, hipStream_t s);
+// vdt2 = (v dt)^2 on the padded box of g from a strided velocity view (element
+// (i,j,k) at v[k*vsz + j*vsy + i], interior only read); faces wrap, edges 0.
+hipError_t launch_prepare_vdt2_view(const Geo& g, const float* v, long long vsy, long long vsz,
+                                    float* q, double dt, hipStream_t s);
+// max and min of a strided velocity view's interior into out[0], out[1] (float bits)
+hipError_t launch_vmax_view(int nx, int ny, int nz, const float* v, long long vsy,
+                            long long vsz, int32_t* out, hipStream_t s);
+// dst[i] = 0 for i < n
+hipError_t launch_zero(float* dst, long long n, hipStream_t s);
+
 hipError_t launch_adjoint(const Geo& g, const Coef& c, const float* ann, const float* an1,
                           float* aout, const float* q, const float* ex, const float* ey,
                           const float* ez, hipStream_t s);

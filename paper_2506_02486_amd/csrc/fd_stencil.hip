@@ -2,15 +2,15 @@
 //
 // One z-marching engine serves three operations:
 //   FWD  : u_next = (2u - (1-eta) u_prev + vdt2 * L u) / (1+eta)      (fd_step)
+//          optionally + the source term (FUSE)
 //   ADJ  : a_out  = 2 D c + L(vdt2 D c) - E D a_nn,  D = 1/(1+eta),
 //          E = 1-eta, c = a^{n+1}                                  (fd_adjoint_step)
 //   GRAD : g     += D c (L u + f)                                  (fused gradient)
 //
 // Work decomposition (2.5-D blocking).  A block of TXT x NY threads owns an
 // x-y tile of TXT x (NY*RY) points and marches along z through a chunk of
-// `kchunk` planes.  threadIdx.x = x (TXT/64 waves side by side, each load a
-// 256-byte coalesced row segment per wave); each thread row owns RY
-// consecutive y rows.  Per plane:
+// `kchunk` planes.  threadIdx.x = x (each wave loads a 256-byte coalesced row
+// segment); each thread row owns RY consecutive y rows.  Per plane:
 //   * the stencil field of the current plane (tile + 4-wide x and y halos) is
 //     staged in LDS (double buffered, so one barrier per plane);
 //   * x neighbours come from LDS; y neighbours from the thread's own registers
@@ -22,13 +22,18 @@
 //   * pointwise operands (u_prev, vdt2, ...) are streamed with non-temporal
 //     loads and the result with non-temporal stores, leaving L2 to the field
 //     whose x/y halos neighbouring tiles re-read.
+// Addressing: every load is a 32-bit unsigned byte offset from a block-uniform
+// plane base (the padded corner (-4,-4) of plane k), so the address of each
+// load is one scalar base plus one 32-bit register.
+// Sponge: a block whose x-y tile lies outside the damping layer takes the
+// undamped update on planes where eta_z is zero too (a uniform branch); points
+// with eta == 0 compute the same expression on both paths.
 // Blocks are renumbered so that each of the 8 XCDs (each with its own L2) gets
 // one contiguous run of tiles: hardware dispatches block b to XCD b % 8.
 #include "fd_internal.h"
 
 namespace fd {
 namespace {
-
 
 enum Mode { FWD = 0, ADJ = 1, GRAD = 2 };
 
@@ -46,8 +51,8 @@ struct Params {
   const float* ey;
   const float* ez;
   int tiles_x, tiles_y, kchunk;
-  int si, sj, sk;   // GRAD source point (si < 0: none)
-  float sw;         // GRAD source amplitude
+  int si, sj, sk;   // source point (si < 0: none): FWD adds its term, GRAD its f
+  float sw;         // source amplitude
 };
 
 __device__ __forceinline__ int remap_block(int bid, int nb) {
@@ -62,10 +67,18 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i;
 }
 
-__device__ __forceinline__ float ldg_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld(const char* base, unsigned boff) {
+  return *reinterpret_cast<const float*>(base + boff);
+}
+__device__ __forceinline__ float ld_nt(const char* base, unsigned boff) {
+  return __builtin_nontemporal_load(reinterpret_cast<const float*>(base + boff));
+}
 
-template <int TXT, int NY, int RY, int MODE, bool SPONGE>
-__global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
+// The per-block work of every stencil kernel: tile (bx, by) of the x-y plane,
+// z-chunk bz, of the grid and operands described by p.
+template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE>
+__device__ __forceinline__ void stencil_block(const Params& p, const int bx, const int by,
+                                              const int bz) {
   constexpr int TX = TXT;
   constexpr int TY = NY * RY;
   constexpr int LX = TX + 8;
@@ -77,15 +90,9 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
 
   const int lane = threadIdx.x;
   const int w = threadIdx.y;
-  const int logical = remap_block(blockIdx.x, gridDim.x);
-  const int bx = logical % p.tiles_x;
-  const int rest = logical / p.tiles_x;
-  const int by = rest % p.tiles_y;
-  const int bz = rest / p.tiles_y;
-
   const int nx = p.g.nx, ny = p.g.ny, nz = p.g.nz;
   const int sy = p.g.sy;
-  const long long sz = p.g.sz;
+  const long long szb = 4LL * p.g.sz;  // plane stride in bytes
   const int x0 = bx * TX;
   const int y0 = by * TY;
   const int kb = bz * p.kchunk;
@@ -93,25 +100,31 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
   const int x = x0 + lane;
   const int yr = y0 + w * RY;
 
+  // byte offset of (x, y) inside a plane, from the padded corner (-4, -4)
+  auto boff = [&](int xx, int yy) -> unsigned {
+    return 4u * (unsigned)((yy + 4) * sy + (xx + 4));
+  };
+
   // ---- per-thread geometry of the cells it loads every plane
-  int coff[RY];
+  unsigned cb[RY];
   bool cld[RY], act[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int yy = yr + r;
-    coff[r] = yy * sy + x;
+    cb[r] = boff(x, yy);
     cld[r] = (x < nx + 4) && (yy < ny + 4);
     act[r] = (x < nx) && (yy < ny);
   }
   // y-halo rows: thread row w loads halo rows hr = w + h*NY (h < HPT) at column
   // x; hr < 4 are the rows above the tile, hr >= 4 the rows below
-  int hy_y[HPT], hy_off[HPT], hy_lds[HPT];
+  int hy_y[HPT], hy_lds[HPT];
+  unsigned hyb[HPT];
   bool hy_ld[HPT];
 #pragma unroll
   for (int h = 0; h < HPT; ++h) {
     const int hr = w + h * NY;
     hy_y[h] = hr < 4 ? y0 - 4 + hr : y0 + TY + (hr - 4);
-    hy_off[h] = hy_y[h] * sy + x;
+    hyb[h] = boff(x, hy_y[h]);
     hy_lds[h] = (hr < 4 ? hr : TY + hr) * LX + 4 + lane;
     hy_ld[h] = (x < nx + 4) && (hy_y[h] < ny + 4);
   }
@@ -122,7 +135,7 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
   const int hx_y = yr + hx_r;
   const bool hx_on = lane < 8 * RY;
   const bool hx_ld = hx_on && (hx_x < nx + 4) && (hx_y < ny + 4);
-  const int hx_off = hx_y * sy + hx_x;
+  const unsigned hxb = boff(hx_on ? hx_x : 0, hx_on ? hx_y : 0);
   const int hx_lds = (4 + w * RY + hx_r) * LX + (hx_c < 4 ? hx_c : TX + hx_c);
 
   // ---- sponge factors that are constant along z for this thread
@@ -131,6 +144,7 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
   for (int r = 0; r < RY; ++r) ey_r[r] = 0.f;
 #pragma unroll
   for (int h = 0; h < HPT; ++h) ey_hy[h] = 0.f;
+  bool tile_sponge = false;  // block-uniform: some point of the x-y tile is damped
   if (SPONGE) {
     if (MODE == ADJ) {  // halo cells take eta of their periodic image
       if (x < nx + 4) ex_c = p.ex[wrapi(x, nx)];
@@ -144,28 +158,34 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
         if (yr + r < ny + 4) ey_r[r] = p.ey[wrapi(yr + r, ny)];
     } else {
       if (x < nx) ex_c = p.ex[x];
+      int any = 0;
 #pragma unroll
-      for (int r = 0; r < RY; ++r)
+      for (int r = 0; r < RY; ++r) {
         if (yr + r < ny) ey_r[r] = p.ey[yr + r];
+        any |= act[r] && (ex_c != 0.f || ey_r[r] != 0.f);
+      }
+      tile_sponge = __syncthreads_or(any) != 0;
     }
   }
 
-  const float* __restrict__ fbase = p.f + p.g.org;
-  const float* __restrict__ qbase = p.fq + p.g.org;
+  const long long org_c = p.g.org - 4LL * sy - 4;  // element offset of the padded corner
+  const char* F0 = reinterpret_cast<const char*>(p.f + org_c);
+  const char* Q0 = reinterpret_cast<const char*>(p.fq + org_c);
+  const char* A0 = reinterpret_cast<const char*>(p.pa ? p.pa + org_c : p.f + org_c);
+  const char* B0 = reinterpret_cast<const char*>(p.pb ? p.pb + org_c : p.f + org_c);
+  char* O0 = reinterpret_cast<char*>(p.out + org_c);
 
-  // Field value at an in-plane offset of plane k (k in [-4, nz+4)).  ADJ forms
+  // Field value at byte offset b of plane k (k in [-4, nz+4)).  ADJ forms
   // vdt2 * c / (1 + eta) with eta of the periodic image.
-  auto fld = [&](int k, int off, bool ld, float exv, float eyv, float ezv) -> float {
-    if (!ld) return 0.f;
-    const long long pk = (long long)k * sz;
+  auto fld = [&](const char* fk, const char* qk, unsigned b, bool ok, float exv, float eyv,
+                 float ezv) -> float {
+    if (!ok) return 0.f;
     if (MODE == ADJ) {
-      const float cv = fbase[pk + off];
-      const float qv = qbase[pk + off];
-      float v = qv * cv;
+      float v = ld(qk, b) * ld(fk, b);
       if (SPONGE) v *= __builtin_amdgcn_rcpf(1.f + (exv + eyv + ezv));
       return v;
     } else {
-      return fbase[pk + off];
+      return ld(fk, b);
     }
   };
   auto ezw = [&](int k) -> float {
@@ -181,35 +201,42 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
   for (int s = 0; s < 9; ++s) {
     const int k = kb - 4 + s;
     const float ezv = ezw(k);
+    const char* fk = F0 + (long long)k * szb;
+    const char* qk = Q0 + (long long)k * szb;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      zq[s][r] = fld(k, coff[r], cld[r], ex_c, ey_r[r], ezv);
-      if (MODE == ADJ && s >= 4)
-        cq[s - 4][r] = cld[r] ? fbase[(long long)k * sz + coff[r]] : 0.f;
+      zq[s][r] = fld(fk, qk, cb[r], cld[r], ex_c, ey_r[r], ezv);
+      if (MODE == ADJ && s >= 4) cq[s - 4][r] = cld[r] ? ld(fk, cb[r]) : 0.f;
     }
   }
   float hy[HPT], hx;
   {
     const float ezv = ezw(kb);
+    const char* fk = F0 + (long long)kb * szb;
+    const char* qk = Q0 + (long long)kb * szb;
 #pragma unroll
-    for (int h = 0; h < HPT; ++h) hy[h] = fld(kb, hy_off[h], hy_ld[h], ex_c, ey_hy[h], ezv);
-    hx = fld(kb, hx_off, hx_ld, ex_h, ey_h, ezv);
+    for (int h = 0; h < HPT; ++h) hy[h] = fld(fk, qk, hyb[h], hy_ld[h], ex_c, ey_hy[h], ezv);
+    hx = fld(fk, qk, hxb, hx_ld, ex_h, ey_h, ezv);
   }
   float pa[RY], pb[RY];
+  {
+    const char* ak = A0 + (long long)kb * szb;
+    const char* bk = B0 + (long long)kb * szb;
+    const char* ok = O0 + (long long)kb * szb;
 #pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const long long o = p.g.org + (long long)kb * sz + coff[r];
-    pa[r] = 0.f;
-    pb[r] = 0.f;
-    if (act[r] && kb < ke) {
-      if (MODE == FWD) {
-        pa[r] = ldg_nt(p.pa + o);
-        pb[r] = ldg_nt(p.pb + o);
-      } else if (MODE == ADJ) {
-        if (p.pa) pa[r] = ldg_nt(p.pa + o);
-      } else {
-        pa[r] = ldg_nt(p.pa + o);
-        pb[r] = p.out[o];
+    for (int r = 0; r < RY; ++r) {
+      pa[r] = 0.f;
+      pb[r] = 0.f;
+      if (act[r] && kb < ke) {
+        if (MODE == FWD) {
+          pa[r] = ld_nt(ak, cb[r]);
+          pb[r] = ld_nt(bk, cb[r]);
+        } else if (MODE == ADJ) {
+          if (p.pa) pa[r] = ld_nt(ak, cb[r]);
+        } else {
+          pa[r] = ld_nt(ak, cb[r]);
+          pb[r] = ld(ok, cb[r]);
+        }
       }
     }
   }
@@ -225,35 +252,41 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
       const int kn = k + 5;
       const bool need = kn < ke + 4;
       const float ezv = ezw(kn);
+      const char* fk = F0 + (long long)kn * szb;
+      const char* qk = Q0 + (long long)kn * szb;
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        nzq[r] = need ? fld(kn, coff[r], cld[r], ex_c, ey_r[r], ezv) : 0.f;
-        if (MODE == ADJ)
-          ncq[r] = (need && cld[r]) ? fbase[(long long)kn * sz + coff[r]] : 0.f;
+        nzq[r] = need ? fld(fk, qk, cb[r], cld[r], ex_c, ey_r[r], ezv) : 0.f;
+        if (MODE == ADJ) ncq[r] = (need && cld[r]) ? ld(fk, cb[r]) : 0.f;
       }
     }
     const bool more = k + 1 < ke;
     if (more) {
       const float ezv = ezw(k + 1);
+      const char* fk = F0 + (long long)(k + 1) * szb;
+      const char* qk = Q0 + (long long)(k + 1) * szb;
 #pragma unroll
-      for (int h = 0; h < HPT; ++h)
-        nhy[h] = fld(k + 1, hy_off[h], hy_ld[h], ex_c, ey_hy[h], ezv);
-      nhx = fld(k + 1, hx_off, hx_ld, ex_h, ey_h, ezv);
+      for (int h = 0; h < HPT; ++h) nhy[h] = fld(fk, qk, hyb[h], hy_ld[h], ex_c, ey_hy[h], ezv);
+      nhx = fld(fk, qk, hxb, hx_ld, ex_h, ey_h, ezv);
     }
+    {
+      const char* ak = A0 + (long long)(k + 1) * szb;
+      const char* bk = B0 + (long long)(k + 1) * szb;
+      const char* ok = O0 + (long long)(k + 1) * szb;
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      npa[r] = 0.f;
-      npb[r] = 0.f;
-      if (more && act[r]) {
-        const long long o = p.g.org + (long long)(k + 1) * sz + coff[r];
-        if (MODE == FWD) {
-          npa[r] = ldg_nt(p.pa + o);
-          npb[r] = ldg_nt(p.pb + o);
-        } else if (MODE == ADJ) {
-          if (p.pa) npa[r] = ldg_nt(p.pa + o);
-        } else {
-          npa[r] = ldg_nt(p.pa + o);
-          npb[r] = p.out[o];
+      for (int r = 0; r < RY; ++r) {
+        npa[r] = 0.f;
+        npb[r] = 0.f;
+        if (more && act[r]) {
+          if (MODE == FWD) {
+            npa[r] = ld_nt(ak, cb[r]);
+            npb[r] = ld_nt(bk, cb[r]);
+          } else if (MODE == ADJ) {
+            if (p.pa) npa[r] = ld_nt(ak, cb[r]);
+          } else {
+            npa[r] = ld_nt(ak, cb[r]);
+            npb[r] = ld(ok, cb[r]);
+          }
         }
       }
     }
@@ -269,6 +302,9 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
 
     // ---- compute
     const float ezk = SPONGE ? p.ez[k] : 0.f;
+    // block-uniform: does any point of this tile-plane carry damping?
+    const bool damped = SPONGE && (MODE == ADJ || tile_sponge || ezk != 0.f);
+    char* ok = O0 + (long long)k * szb;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const float* row = s + (4 + w * RY + r) * LX + 4 + lane;
@@ -286,32 +322,36 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
       for (int m = 1; m <= 4; ++m) lap += p.c.cz[m] * (zq[4 + m][r] + zq[4 - m][r]);
 
       if (act[r]) {
-        const long long o = p.g.org + (long long)k * sz + coff[r];
         float eta = 0.f;
-        if (SPONGE) eta = ex_c + ey_r[r] + ezk;
+        if (damped) eta = ex_c + ey_r[r] + ezk;
+        float* dst = reinterpret_cast<float*>(ok + cb[r]);
         if (MODE == FWD) {
           float v;
-          if (SPONGE && eta != 0.f)
+          if (damped && eta != 0.f)
             v = (2.f * uc - (1.f - eta) * pa[r] + pb[r] * lap) * __builtin_amdgcn_rcpf(1.f + eta);
           else
             v = 2.f * uc - pa[r] + pb[r] * lap;
-          __builtin_nontemporal_store(v, p.out + o);
+          if (FUSE) {
+            const int yy = yr + r;
+            if (x == p.si && yy == p.sj && k == p.sk) v += pb[r] * p.sw / (1.f + eta);
+          }
+          __builtin_nontemporal_store(v, dst);
         } else if (MODE == ADJ) {
           const float c = cq[0][r];
           float v;
-          if (SPONGE && eta != 0.f) {
+          if (damped && eta != 0.f) {
             const float D = __builtin_amdgcn_rcpf(1.f + eta);
             v = 2.f * D * c + lap - (1.f - eta) * D * pa[r];
           } else {
             v = 2.f * c + lap - pa[r];
           }
-          __builtin_nontemporal_store(v, p.out + o);
+          __builtin_nontemporal_store(v, dst);
         } else {
           float src = 0.f;
           if (x == p.si && yr + r == p.sj && k == p.sk) src = p.sw;
           float D = 1.f;
-          if (SPONGE && eta != 0.f) D = __builtin_amdgcn_rcpf(1.f + eta);
-          p.out[o] = pb[r] + D * pa[r] * (lap + src);
+          if (damped && eta != 0.f) D = __builtin_amdgcn_rcpf(1.f + eta);
+          *dst = pb[r] + D * pa[r] * (lap + src);
         }
       }
     }
@@ -336,13 +376,52 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
   }
 }
 
+template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE>
+__global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
+  const int logical = remap_block(blockIdx.x, gridDim.x);
+  const int bx = logical % p.tiles_x;
+  const int rest = logical / p.tiles_x;
+  stencil_block<TXT, NY, RY, MODE, SPONGE, FUSE>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
+}
+
+// Many grids in one launch: block b runs tile tiles[remap(b)] = (slot, bx, by, bz)
+// of shot `slot`, whose step is a.n[slot] (u^n in arr[n % 3]) and source
+// amplitude a.w[slot].  Every point runs exactly the code of stencil_kernel.
+template <int TXT, int NY, int RY>
+__global__ void __launch_bounds__(TXT * NY) batched_kernel(const BatchShot* __restrict__ shots,
+                                                           const int4* __restrict__ tiles,
+                                                           BatchStep a) {
+  const int4 t = tiles[remap_block(blockIdx.x, gridDim.x)];
+  const BatchShot& b = shots[t.x];
+  const int n = a.n[t.x];
+  Params p;
+  p.g = b.g;
+  p.c = b.c;
+  p.f = b.arr[n % 3];
+  p.fq = p.f;
+  p.pa = b.arr[(n + 2) % 3];
+  p.pb = b.q;
+  p.out = b.arr[(n + 1) % 3];
+  p.ex = b.ex;
+  p.ey = b.ey;
+  p.ez = b.ez;
+  p.tiles_x = 0;
+  p.tiles_y = 0;
+  p.kchunk = b.kchunk;
+  p.si = b.si;
+  p.sj = b.sj;
+  p.sk = b.sk;
+  p.sw = a.w[t.x];
+  stencil_block<TXT, NY, RY, FWD, true, true>(p, t.y, t.z, t.w);
+}
+
 struct LaunchShape {
   int tiles_x, tiles_y, kchunk, zchunks;
 };
 
 int g_kchunk_override = 0;
 
-LaunchShape shape_for(const Geo& g, int tx, int ty) {
+LaunchShape shape_for(const Geo& g, int tx, int ty, int waves_per_block) {
   LaunchShape s;
   s.tiles_x = (g.nx + tx - 1) / tx;
   s.tiles_y = (g.ny + ty - 1) / ty;
@@ -351,9 +430,9 @@ LaunchShape shape_for(const Geo& g, int tx, int ty) {
   if (g_kchunk_override > 0) {
     kc = g_kchunk_override;
   } else {
-    // aim at about 1024 blocks (4 per CU on 256 CUs) while keeping the z halo
+    // aim at about 4096 waves (16 per CU on 256 CUs) while keeping the z halo
     // re-read (8 planes per chunk) small
-    const long long target = 1024;
+    const long long target = 4096 / waves_per_block;
     long long chunks = (target + tiles - 1) / tiles;
     if (chunks < 1) chunks = 1;
     kc = (int)((g.nz + chunks - 1) / chunks);
@@ -365,15 +444,15 @@ LaunchShape shape_for(const Geo& g, int tx, int ty) {
   return s;
 }
 
-template <int TXT, int NY, int RY, int MODE, bool SPONGE>
+template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE = false>
 hipError_t launch_mode(Params p, hipStream_t st) {
-  const LaunchShape sh = shape_for(p.g, TXT, NY * RY);
+  const LaunchShape sh = shape_for(p.g, TXT, NY * RY, (TXT * NY + 63) / 64);
   p.tiles_x = sh.tiles_x;
   p.tiles_y = sh.tiles_y;
   p.kchunk = sh.kchunk;
   const long long nb = (long long)sh.tiles_x * sh.tiles_y * sh.zchunks;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((stencil_kernel<TXT, NY, RY, MODE, SPONGE>), dim3((unsigned)nb),
+  hipLaunchKernelGGL((stencil_kernel<TXT, NY, RY, MODE, SPONGE, FUSE>), dim3((unsigned)nb),
                      dim3(TXT, NY), 0, st, p);
   return hipGetLastError();
 }
@@ -394,22 +473,48 @@ Params base_params(const Geo& g, const Coef& c, const float* ex, const float* ey
 }
 
 // tile shapes (threads in x, thread rows, y rows per thread)
-#define FWD_SHAPE 64, 4, 4
+#define FWD_SHAPE 64, 8, 4
 #define ADJ_SHAPE 64, 4, 2
+constexpr int BATCH_TX = 64;      // tile width of the batched kernel (FWD_SHAPE)
+constexpr int BATCH_TY = 8 * 4;   // tile height of the batched kernel (FWD_SHAPE)
 
 }  // namespace
 
 void set_kchunk_override(int kc) { g_kchunk_override = kc; }
 
+int batch_tile_shape(int* tx, int* ty) {
+  *tx = BATCH_TX;
+  *ty = BATCH_TY;
+  return BATCH_TX * 8;
+}
+
+hipError_t launch_batched(const BatchShot* shots, const int4* tiles, int ntiles,
+                          const BatchStep& a, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((batched_kernel<FWD_SHAPE>), dim3((unsigned)ntiles), dim3(BATCH_TX, 8), 0, s,
+                     shots, tiles, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float* u,
                        float* un, const float* q, const float* ex, const float* ey,
-                       const float* ez, hipStream_t s) {
+                       const float* ez, const fd_source* src, hipStream_t s) {
   Params p = base_params(g, c, ex, ey, ez);
   p.f = u;
   p.fq = u;
   p.pa = up;
   p.pb = q;
   p.out = un;
+  if (src) {
+    p.si = src->i;
+    p.sj = src->j;
+    p.sk = src->k;
+    p.sw = src->w;
+  }
+  if (src) {
+    if (ex) return launch_mode<FWD_SHAPE, FWD, true, true>(p, s);
+    return launch_mode<FWD_SHAPE, FWD, false, true>(p, s);
+  }
   if (ex) return launch_mode<FWD_SHAPE, FWD, true>(p, s);
   return launch_mode<FWD_SHAPE, FWD, false>(p, s);
 }

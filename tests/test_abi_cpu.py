@@ -156,3 +156,25 @@ def test_host_helpers(L):
     assert L.fd_receiver_offsets(C.byref(g), ijk.ctypes.data, 2, off.ctypes.data) == _lib.FD_EINVAL
     assert L.fd_set_kchunk(-1) == _lib.FD_EINVAL
     assert L.fd_set_kchunk(0) == 0
+
+
+def test_shot_footprint_and_server_argument_checks(L):
+    d = _lib.fd_shot_desc()
+    d.nx, d.ny, d.nz, d.nt = 256, 256, 256, 500
+    d.dx = d.dy = d.dz = 10.0
+    d.nrec = 256
+    fp = L.fd_shot_footprint(C.byref(d))
+    g = grid(L, 256, 256, 256)
+    vol = (L.fd_grid_elems(C.byref(g)) * 4 + 255) // 256 * 256
+    assert fp >= 4 * vol + 4 * 500 * 256 and fp % 256 == 0
+    d.nt = 0
+    assert L.fd_shot_footprint(C.byref(d)) == -1
+    h = C.c_void_p()
+    EINVAL = _lib.FD_EINVAL
+    assert L.fd_server_create(C.byref(h), None, 1 << 30, 4, None, None) == EINVAL
+    assert L.fd_server_create(C.byref(h), FAKE + 8, 1 << 30, 4, None, None) == EINVAL  # unaligned
+    assert L.fd_server_create(C.byref(h), FAKE, 1 << 30, 0, None, None) == EINVAL
+    assert L.fd_server_create(C.byref(h), FAKE, 1 << 30, 65, None, None) == EINVAL
+    assert L.fd_server_create(C.byref(h), FAKE, 4096, 4, None, None) == _lib.FD_ENOMEM
+    assert L.shot_submit(None, C.byref(d), C.byref(C.c_int64())) == EINVAL
+    assert L.shot_poll(None, 1, None, 0, None) == EINVAL
