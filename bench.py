@@ -211,6 +211,85 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
     }
 
 
+def large_bench(steps=500, warmup=5):
+    """1024 x 1024 x 512 subdomain, sponge 16, Dirichlet halo, receivers on a 1024-point
+    line at z = 4: the same per-step path without the exchange."""
+    import numpy as np
+    import torch
+
+    from paper_2506_02486_amd import api
+    from workloads import center_source, receivers_xline, smooth_velocity
+
+    nx, ny, nz = 1024, 1024, 512
+    log("large: generating the 1024x1024x512 model")
+    v = smooth_velocity(nx, ny, nz, seed=2)
+    src = center_source(nx, ny, nz)
+    sim = api.Simulation(v, sponge_width=16,
+                         geom=api.Geometry(src=src, rec=receivers_xline(nx, 512, 4)))
+    del v
+    sim.run(warmup)
+    g = sim.grid
+    w = api.ricker(steps, sim.dt, n0=sim.n)
+    tr = torch.zeros((steps, sim.nrec), dtype=torch.float32, device="cuda")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[s][0].record()
+        api.step_fused(g, sim.u_prev, sim.u, sim.u_next, sim.vdt2, sim.sponge,
+                       (src, float(w[s])), None)
+        ev[s][1].record()
+        api.record_receivers(g, sim.u_next, sim.rec_off, tr[s])
+        sim.u_prev, sim.u, sim.u_next = sim.u, sim.u_next, sim.u_prev
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    pts = nx * ny * nz
+    out = {"workload": "1024x1024x512 + radius-4 halo, smooth model, sponge 16, Dirichlet, "
+                       "1024 receivers at z=4", "steps": steps,
+           "Gpts_per_s": round(pts * steps / el / 1e9, 2),
+           "ms_per_step": round(el * 1e3 / steps, 4),
+           "stencil_ms": round(k_ms, 4),
+           "stencil_frac_of_8TBps": round(16.0 * pts / (k_ms / 1e3) / 8e12, 4)}
+    del sim, tr
+    torch.cuda.empty_cache()
+    return out
+
+
+def fwi_bench(n=256, nt=1000, every=32):
+    """FWI gradient w.r.t. squared slowness: n^3, nt steps, checkpoints every `every`
+    steps, observed data from a +5% Gaussian blob."""
+    import numpy as np
+    import torch
+
+    from paper_2506_02486_amd import fwi
+    from workloads import blob_perturbed, receivers_plane, smooth_velocity
+
+    log(f"fwi: {n}^3, {nt} steps")
+    v0 = smooth_velocity(n, n, n, seed=2)
+    vt = blob_perturbed(v0)
+    dt = 0.4 * 10.0 / float(v0.max())
+    prob = fwi.FWIProblem((n, n, n), dt, (n // 2, n // 2, 20), receivers_plane(n, n, 20), nt,
+                          sponge_width=16, sponge_vmax=float(v0.max()), checkpoint_every=every)
+    m0 = torch.from_numpy((1.0 / v0.astype(np.float64) ** 2).astype(np.float32)).cuda()
+    mt = torch.from_numpy((1.0 / vt.astype(np.float64) ** 2).astype(np.float32)).cuda()
+    obs = prob.forward(mt, checkpoints=False)
+    fwi.misfit_gradient(prob, m0, obs)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g = fwi.misfit_gradient(prob, m0, obs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pts = n ** 3
+    # forward 16 B/pt/step, recompute 16, adjoint 16 + gradient 16
+    algo = (16.0 + 16.0 + 32.0) * pts * nt
+    return {"workload": f"FWI gradient {n}^3, {nt} steps, checkpoints every {every}, sponge 16",
+            "seconds_per_gradient": round(el, 4), "misfit": J,
+            "effective_GBps": round(algo / el / 1e9, 1),
+            "finite": bool(torch.isfinite(g).all().item())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +302,8 @@ def main():
                     help="after the timed region, run a plain 1 GiB device copy (for counters)")
     ap.add_argument("--kchunk", type=int, default=0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--large", action="store_true", help="also time the 1024x1024x512 subdomain")
+    ap.add_argument("--fwi", action="store_true", help="also time the 256^3 FWI gradient")
     ap.add_argument("--shots", type=int, default=256, help="shots in the serving stream")
     ap.add_argument("--vcache", default=None,
                     help="optional .npy path to cache the generated velocity model")
@@ -354,6 +435,10 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_serving:
         out["serving"] = serving_bench(nshots=args.shots)
+    if args.large:
+        out["large"] = large_bench()
+    if args.fwi:
+        out["fwi"] = fwi_bench()
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline ({args.cpu_steps} steps of {n}^3)")
         out["cpu_baseline"] = cpu_baseline(v, out["_dt"], src, args.cpu_steps)

@@ -186,6 +186,34 @@ int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* 
                   const float* vdt2, const fd_sponge* sp, const fd_source* src,
                   float* const face_out[6], void* stream);
 
+/* S1-S7 for nt steps, the host loop in native code: per step n,
+ *   (send given) halo_unpack(u, receive = the opposite face of send),
+ *   fd_step_fused(u_prev, u -> u_next, source w[n] at src if wavelet non-NULL),
+ *   (send given) halo_pack(u_next -> send),
+ *   (nrec > 0) record_receivers(u_next -> traces + n*nrec),
+ *   rotate (u_prev, u, u_next) <- (u, u_next, u_prev).
+ * With send set the exchange is the single-device loopback (periodic
+ * subdomain); on entry send must hold the faces of u (zeros for a zero
+ * start, or what the previous run left).  On return the struct's three
+ * pointers are rotated so u_prev, u hold the last two states.  wavelet is a
+ * host array of nt floats, read before the call returns; traces is a device
+ * array of nt*nrec floats; rec_off device int64 offsets. */
+typedef struct fd_run {
+  float* u_prev;
+  float* u;
+  float* u_next;
+  const float* vdt2;
+  fd_sponge sponge;              /* all NULL: no sponge */
+  int32_t nt;
+  int32_t src[3];
+  const float* wavelet;          /* host, nt values; NULL: no source */
+  int32_t nrec;
+  const int64_t* rec_off;        /* device */
+  float* traces;                 /* device, nt*nrec */
+  float* send[6];                /* device face buffers, or all NULL (no exchange) */
+} fd_run;
+int fd_forward_run(const fd_grid* g, fd_run* run, void* stream);
+
 /* S5: u_next[s] += vdt2[s] * w / (1+eta[s]) at interior point s = (i,j,k). */
 int inject_source(const fd_grid* g, float* u_next, const float* vdt2,
                   const fd_sponge* sp, int32_t i, int32_t j, int32_t k, float w,

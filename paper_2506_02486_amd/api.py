@@ -315,8 +315,9 @@ class Simulation:
         ``fused`` (default) runs per step: halo_unpack of the faces packed during the
         previous step, then one fd_step_fused (update + source + pack of the new
         field), then record_receivers.  ``fused=False`` issues the separate calls
-        halo_pack, halo_unpack, fd_step, inject_source, record_receivers.  Both give
-        the same bits."""
+        halo_pack, halo_unpack, fd_step, inject_source, record_receivers;
+        ``fused="native"`` runs the fused sequence in the library's own loop
+        (fd_forward_run).  All give the same bits."""
         g = self.grid
         if traces is None:
             traces = torch.zeros((nt, max(self.nrec, 1)), dtype=torch.float32, device=self.device)
@@ -326,6 +327,8 @@ class Simulation:
             w = ricker(nt, self.dt, geom.f0, geom.t0, n0=self.n)
         if fused and self.exchange and not self._faces_current:
             halo_pack(g, self.u, self.send, stream)
+        if fused == "native":
+            return self._run_native(nt, w, traces, stream)
         for s in range(nt):
             if fused:
                 if self.exchange:
@@ -348,6 +351,34 @@ class Simulation:
         # after a fused step the send buffers hold the faces of the current u
         self._faces_current = bool(fused and self.exchange and nt > 0) or (
             self._faces_current and nt == 0)
+        return traces[:, :self.nrec]
+
+    def _run_native(self, nt, w, traces, stream):
+        """The same per-step sequence as the fused path, looped in native code
+        (fd_forward_run)."""
+        r = _lib.fd_run()
+        bufs = {t.data_ptr(): t for t in (self.u_prev, self.u, self.u_next)}
+        r.u_prev, r.u, r.u_next = self.u_prev.data_ptr(), self.u.data_ptr(), self.u_next.data_ptr()
+        r.vdt2 = self.vdt2.data_ptr()
+        if self.sponge is not None:
+            r.sponge = self.sponge.c
+        r.nt = nt
+        wa = None
+        if w is not None:
+            wa = np.ascontiguousarray(w, dtype=np.float32)
+            r.wavelet = wa.ctypes.data
+            r.src[0], r.src[1], r.src[2] = (int(x) for x in self.geom.src)
+        if self.rec_off is not None:
+            r.nrec = self.nrec
+            r.rec_off = self.rec_off.data_ptr()
+            r.traces = traces.data_ptr()
+        if self.exchange:
+            for f in range(6):
+                r.send[f] = self.send[f].data_ptr()
+        check(lib().fd_forward_run(self.grid.ref, C.byref(r), _stream(stream)), "fd_forward_run")
+        self.u_prev, self.u, self.u_next = bufs[r.u_prev], bufs[r.u], bufs[r.u_next]
+        self.n += nt
+        self._faces_current = bool(self.exchange) or self._faces_current
         return traces[:, :self.nrec]
 
     def state(self):

@@ -333,6 +333,70 @@ int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* 
   return check_hip(launch_pack(geo, u_next, face_out, s), "fd_step_fused pack launch");
 }
 
+int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!run) return fail(FD_EINVAL, "fd_forward_run: run is NULL");
+  float *up = run->u_prev, *u = run->u, *un = run->u_next;
+  if (!up || !u || !un || !run->vdt2) return fail(FD_EINVAL, "fd_forward_run: NULL array");
+  if (overlaps(g, up, u) || overlaps(g, u, un) || overlaps(g, up, un))
+    return fail(FD_EINVAL, "fd_forward_run: the three wavefields must be distinct");
+  if (overlaps(g, run->vdt2, up) || overlaps(g, run->vdt2, u) || overlaps(g, run->vdt2, un))
+    return fail(FD_EINVAL, "fd_forward_run: vdt2 overlaps a wavefield");
+  if (run->nt < 0) return fail(FD_EINVAL, "fd_forward_run: nt < 0");
+  if (run->nrec < 0 || (run->nrec > 0 && (!run->rec_off || !run->traces)))
+    return fail(FD_EINVAL, "fd_forward_run: bad receivers");
+  if (run->wavelet && (run->src[0] < 0 || run->src[0] >= g->nx || run->src[1] < 0 ||
+                       run->src[1] >= g->ny || run->src[2] < 0 || run->src[2] >= g->nz))
+    return fail(FD_EINVAL, "fd_forward_run: source outside the interior");
+  int nsend = 0;
+  for (int f = 0; f < 6; ++f) nsend += run->send[f] != nullptr;
+  if (nsend != 0 && nsend != 6)
+    return fail(FD_EINVAL, "fd_forward_run: give all six face buffers or none");
+  if (nsend) {
+    rc = check_faces(g, (const void* const*)run->send, "fd_forward_run");
+    if (rc) return rc;
+  }
+  const float *ex, *ey, *ez;
+  rc = check_sponge(&run->sponge, &ex, &ey, &ez);
+  if (rc) return rc;
+  const Geo geo = make_geo(g);
+  const Coef c = make_coef(g);
+  hipStream_t s = as_stream(stream);
+  const float* recv[6] = {run->send[1], run->send[0], run->send[3],
+                          run->send[2], run->send[5], run->send[4]};
+  for (int32_t n = 0; n < run->nt; ++n) {
+    hipError_t e = hipSuccess;
+    if (nsend) e = launch_unpack(geo, u, recv, s);
+    fd_source src;
+    if (run->wavelet) {
+      src.i = run->src[0];
+      src.j = run->src[1];
+      src.k = run->src[2];
+      src.w = run->wavelet[n];
+    }
+    if (e == hipSuccess)
+      e = launch_step(geo, c, up, u, un, run->vdt2, ex, ey, ez, run->wavelet ? &src : nullptr, s);
+    if (e == hipSuccess && nsend) e = launch_pack(geo, un, run->send, s);
+    if (e == hipSuccess && run->nrec)
+      e = launch_record(un, run->rec_off, run->nrec, run->traces + (int64_t)n * run->nrec, s);
+    if (e != hipSuccess) {
+      run->u_prev = up;
+      run->u = u;
+      run->u_next = un;
+      return check_hip(e, "fd_forward_run launch");
+    }
+    float* t = up;
+    up = u;
+    u = un;
+    un = t;
+  }
+  run->u_prev = up;
+  run->u = u;
+  run->u_next = un;
+  return FD_OK;
+}
+
 int inject_source(const fd_grid* g, float* u_next, const float* vdt2, const fd_sponge* sp,
                   int32_t i, int32_t j, int32_t k, float w, void* stream) {
   int rc = check_grid(g);

@@ -17,7 +17,8 @@
 //     when the row is its own, else from LDS;
 //   * z neighbours come from a 9-deep register queue per row, so every plane of
 //     the field is read from global memory once per block (plus the 8-plane
-//     z halo of each chunk);
+//     z halo of each chunk); the queue is a ring renamed by unrolling the z loop
+//     nine times, so advancing a plane moves no registers;
 //   * the next plane of every operand is prefetched one iteration ahead;
 //   * pointwise operands (u_prev, vdt2, ...) are streamed with non-temporal
 //     loads and the result with non-temporal stores, leaving L2 to the field
@@ -30,6 +31,8 @@
 // with eta == 0 compute the same expression on both paths.
 // Blocks are renumbered so that each of the 8 XCDs (each with its own L2) gets
 // one contiguous run of tiles: hardware dispatches block b to XCD b % 8.
+#include <type_traits>
+
 #include "fd_internal.h"
 
 namespace fd {
@@ -168,6 +171,10 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
     }
   }
 
+  // block-uniform: the source point lies in this block's tile and z chunk
+  const bool src_tile = p.si >= x0 && p.si < x0 + TX && p.sj >= y0 && p.sj < y0 + TY &&
+                        p.sk >= kb && p.sk < ke;
+
   const long long org_c = p.g.org - 4LL * sy - 4;  // element offset of the padded corner
   const char* F0 = reinterpret_cast<const char*>(p.f + org_c);
   const char* Q0 = reinterpret_cast<const char*>(p.fq + org_c);
@@ -241,7 +248,12 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
     }
   }
 
-  for (int k = kb; k < ke; ++k) {
+  // One z-plane.  The 9-plane queue is a ring: with ring position P (the
+  // plane's index since kb, mod 9) slot (P + s) % 9 holds plane k - 4 + s, so
+  // advancing a plane renames registers instead of moving them (the loop below
+  // is unrolled 9 times with a compile-time P).
+  auto iter = [&](auto pos, const int k) {
+    constexpr int P = decltype(pos)::value;
     const int buf = (k - kb) & 1;
     // ---- prefetch for the next iteration
     float nzq[RY], ncq[RY], npa[RY], npb[RY], nhy[HPT];
@@ -294,7 +306,7 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
     // ---- stage plane k of the field in LDS
     float* s = sm[buf];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) s[(4 + w * RY + r) * LX + 4 + lane] = zq[4][r];
+    for (int r = 0; r < RY; ++r) s[(4 + w * RY + r) * LX + 4 + lane] = zq[(P + 4) % 9][r];
 #pragma unroll
     for (int h = 0; h < HPT; ++h) s[hy_lds[h]] = hy[h];
     if (hx_on) s[hx_lds] = hx;
@@ -304,36 +316,36 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
     const float ezk = SPONGE ? p.ez[k] : 0.f;
     // block-uniform: does any point of this tile-plane carry damping?
     const bool damped = SPONGE && (MODE == ADJ || tile_sponge || ezk != 0.f);
+    // block-uniform: the source point lies in this tile-plane
+    const bool src_plane = src_tile && k == p.sk;
     char* ok = O0 + (long long)k * szb;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const float* row = s + (4 + w * RY + r) * LX + 4 + lane;
-      const float uc = zq[4][r];
+      const float uc = zq[(P + 4) % 9][r];
       float lap = p.c.cc * uc;
 #pragma unroll
       for (int m = 1; m <= 4; ++m) lap += p.c.cx[m] * (row[m] + row[-m]);
 #pragma unroll
       for (int m = 1; m <= 4; ++m) {
-        const float up_ = (r + m < RY) ? zq[4][(r + m) % RY] : row[m * LX];
-        const float dn_ = (r - m >= 0) ? zq[4][(r - m + RY) % RY] : row[-m * LX];
+        const float up_ = (r + m < RY) ? zq[(P + 4) % 9][(r + m) % RY] : row[m * LX];
+        const float dn_ = (r - m >= 0) ? zq[(P + 4) % 9][(r - m + RY) % RY] : row[-m * LX];
         lap += p.c.cy[m] * (up_ + dn_);
       }
 #pragma unroll
-      for (int m = 1; m <= 4; ++m) lap += p.c.cz[m] * (zq[4 + m][r] + zq[4 - m][r]);
+      for (int m = 1; m <= 4; ++m) lap += p.c.cz[m] * (zq[(P + 4 + m) % 9][r] + zq[(P + 4 - m) % 9][r]);
 
       if (act[r]) {
         float eta = 0.f;
         if (damped) eta = ex_c + ey_r[r] + ezk;
         float* dst = reinterpret_cast<float*>(ok + cb[r]);
         if (MODE == FWD) {
-          float v;
-          if (damped && eta != 0.f)
-            v = (2.f * uc - (1.f - eta) * pa[r] + pb[r] * lap) * __builtin_amdgcn_rcpf(1.f + eta);
-          else
-            v = 2.f * uc - pa[r] + pb[r] * lap;
-          if (FUSE) {
-            const int yy = yr + r;
-            if (x == p.si && yy == p.sj && k == p.sk) v += pb[r] * p.sw / (1.f + eta);
+          // undamped update; the damped one, (2u - (1-eta) u_prev + q L u)/(1+eta),
+          // is that value plus eta u_prev over 1+eta, and keeps its bits where eta == 0
+          float v = 2.f * uc - pa[r] + pb[r] * lap;
+          if (damped) v = (v + eta * pa[r]) * __builtin_amdgcn_rcpf(1.f + eta);
+          if (FUSE && src_plane) {
+            if (x == p.si && yr + r == p.sj) v += pb[r] * p.sw / (1.f + eta);
           }
           __builtin_nontemporal_store(v, dst);
         } else if (MODE == ADJ) {
@@ -348,7 +360,7 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
           __builtin_nontemporal_store(v, dst);
         } else {
           float src = 0.f;
-          if (x == p.si && yr + r == p.sj && k == p.sk) src = p.sw;
+          if (src_plane && x == p.si && yr + r == p.sj) src = p.sw;
           float D = 1.f;
           if (damped && eta != 0.f) D = __builtin_amdgcn_rcpf(1.f + eta);
           *dst = pb[r] + D * pa[r] * (lap + src);
@@ -359,9 +371,7 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
     // ---- rotate queues
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) zq[t][r] = zq[t + 1][r];
-      zq[8][r] = nzq[r];
+      zq[P][r] = nzq[r];  // plane k + 5 replaces plane k - 4
       if (MODE == ADJ) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) cq[t][r] = cq[t + 1][r];
@@ -373,6 +383,39 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
 #pragma unroll
     for (int h = 0; h < HPT; ++h) hy[h] = nhy[h];
     hx = nhx;
+  };
+  using std::integral_constant;
+  if (MODE != FWD) {  // the adjoint kernels keep the queue in place (fewer scalar registers)
+    for (int k = kb; k < ke; ++k) {
+      iter(integral_constant<int, 0>{}, k);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {  // rotate: slot 0 now holds plane k + 5
+        const float t = zq[0][r];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) zq[s2][r] = zq[s2 + 1][r];
+        zq[8][r] = t;
+      }
+    }
+    return;
+  }
+  for (int k = kb; k < ke; k += 9) {
+    iter(integral_constant<int, 0>{}, k);
+    if (k + 1 >= ke) break;
+    iter(integral_constant<int, 1>{}, k + 1);
+    if (k + 2 >= ke) break;
+    iter(integral_constant<int, 2>{}, k + 2);
+    if (k + 3 >= ke) break;
+    iter(integral_constant<int, 3>{}, k + 3);
+    if (k + 4 >= ke) break;
+    iter(integral_constant<int, 4>{}, k + 4);
+    if (k + 5 >= ke) break;
+    iter(integral_constant<int, 5>{}, k + 5);
+    if (k + 6 >= ke) break;
+    iter(integral_constant<int, 6>{}, k + 6);
+    if (k + 7 >= ke) break;
+    iter(integral_constant<int, 7>{}, k + 7);
+    if (k + 8 >= ke) break;
+    iter(integral_constant<int, 8>{}, k + 8);
   }
 }
 
