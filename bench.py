@@ -86,22 +86,43 @@ def cpu_baseline(v, dt, src, steps):
     q = oracle.vdt2(v, dt)
     eta = oracle.sponge_tables(n, n, n, 16, float(v.max()), (10.0,) * 3, dt)
     w = oracle.ricker(steps + 1, dt)
-    t0 = time.perf_counter()
-    oracle.forward(None, 1, dt, src=src, w=w[:1], eta=eta, periodic=True, q=q)
-    t1 = time.perf_counter()
-    oracle.forward(None, steps + 1, dt, src=src, w=w, eta=eta, periodic=True, q=q)
-    t2 = time.perf_counter()
-    per_step = ((t2 - t1) - (t1 - t0)) / steps
+    def per_step_s(k):
+        t0 = time.perf_counter()
+        oracle.forward(None, 1, dt, src=src, w=w[:1], eta=eta, periodic=True, q=q)
+        t1 = time.perf_counter()
+        oracle.forward(None, k + 1, dt, src=src, w=w[:k + 1], eta=eta, periodic=True, q=q)
+        t2 = time.perf_counter()
+        return ((t2 - t1) - (t1 - t0)) / k
+
+    cores = oracle.threads()
+    per_step = per_step_s(steps)
+    oracle.set_threads(1)
+    per_step_1 = per_step_s(1)
+    oracle.set_threads(cores)
     del q
     return {
         "value": round(n ** 3 / per_step / 1e9, 5),
         "unit": "Gpts/s",
-        "cores": oracle.threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"FP64 oracle, same {n}^3 sponge-16 periodic workload, {steps} steps "
                   f"(time of {steps + 1} steps minus 1 step, set-up excluded); "
                   f"{per_step:.3f} s/step",
+        "one_core_Gpts_per_s": round(n ** 3 / per_step_1 / 1e9, 5),
+        "host_cpu": host_cpu(),
+        "host_nproc": os.cpu_count(),
     }
+
+
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.0,
@@ -211,6 +232,39 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
     }
 
 
+def small_bench(steps=100, repeats=5):
+    """64^3 plain forward: layered model (seed 1), Dirichlet halo, no sponge, Ricker at
+    the centre, 4096 receivers on the k = 0 plane, run by the library's native step
+    loop.  The arrays (1.2 MB each) stay in cache, so the rate is launch-bound and
+    its HBM fraction means nothing; reported as the median of `repeats` runs."""
+    import numpy as np
+    import torch
+
+    from paper_2506_02486_amd import api
+    from workloads import center_source, layered_velocity, receivers_plane
+
+    n = 64
+    v = layered_velocity(n, n, n, seed=1)
+    geom = api.Geometry(src=center_source(n, n, n), rec=receivers_plane(n, n, 0))
+    times = []
+    for r in range(repeats + 1):
+        sim = api.Simulation(v, geom=geom)
+        tr = torch.zeros((steps, sim.nrec), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(steps, tr, fused="native")
+        torch.cuda.synchronize()
+        if r:  # the first run warms the code paths
+            times.append(time.perf_counter() - t0)
+        del sim, tr
+    el = float(np.median(times))
+    return {"workload": "64^3 layered model, Dirichlet, no sponge, 4096 receivers at k=0, "
+                        f"{steps} steps (launch-bound; HBM fraction not meaningful)",
+            "steps": steps, "repeats": repeats,
+            "Gpts_per_s": round(n ** 3 * steps / el / 1e9, 2),
+            "us_per_step": round(el * 1e6 / steps, 2)}
+
+
 def large_bench(steps=500, warmup=5):
     """1024 x 1024 x 512 subdomain, sponge 16, Dirichlet halo, receivers on a 1024-point
     line at z = 4: the same per-step path without the exchange."""
@@ -304,6 +358,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--large", action="store_true", help="also time the 1024x1024x512 subdomain")
     ap.add_argument("--fwi", action="store_true", help="also time the 256^3 FWI gradient")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64^3 launch-bound leg")
     ap.add_argument("--shots", type=int, default=256, help="shots in the serving stream")
     ap.add_argument("--vcache", default=None,
                     help="optional .npy path to cache the generated velocity model")
@@ -411,7 +466,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "fd_step_fused stencil (stencil_kernel<64,8,4,FWD,sponge,source>)",
+            "kernel": "fd_step_fused stencil (stencil_kernel<64,8,4,FWD,sponge,source,early-halo>)",
             "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
@@ -435,6 +490,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_serving:
         out["serving"] = serving_bench(nshots=args.shots)
+    if not args.no_small:
+        out["small"] = small_bench()
     if args.large:
         out["large"] = large_bench()
     if args.fwi:

@@ -267,6 +267,38 @@ int fd_scatter_add(const fd_grid* g, float* a, const int64_t* off, const float* 
 int fd_grad_finalize(const fd_grid* g, const float* g_vdt2, const float* vdt2,
                      double dt, float* grad_m, void* stream);
 
+/* The same adjoint in the scaled variable b = Q D a.  Multiplying the
+ * fd_adjoint_step recurrence by Q D gives
+ *   b^n = D (2 b^{n+1} - E b^{n+2} + Q L b^{n+1}),
+ * the forward update run backward in time (L is symmetric, Q, D, E are
+ * diagonal), so the adjoint sweep runs the forward stencil kernel.  Since Q and
+ * D do not depend on n, g_vdt2 = g_b / Q with g_b = sum_n b^{n+1} (L u^n + f^n),
+ * and the derivative of the loss with respect to the source amplitude w[n] is
+ * b^{n+1} at the source point.
+ *
+ * S11 (scaled): b_out = D (2 b_n1 - E b_nn + Q L b_n1) on the interior, with
+ * b_n1's halo as given (zero for Dirichlet halos).  b_nn and b_n1 must be
+ * non-NULL; b_out may alias b_nn, never b_n1.  If g_b is non-NULL, also
+ * g_b += b_n1 (L u_n + f) with u_n's halo as given and f = src->w at src (src
+ * may be NULL); u_n must then be non-NULL.  Same error behaviour as
+ * fd_adjoint_step. */
+int fd_adjoint_step_scaled(const fd_grid* g, const float* b_nn, const float* b_n1,
+                           float* b_out, const float* vdt2, const fd_sponge* sp,
+                           const float* u_n, float* g_b, const fd_source* src,
+                           void* stream);
+
+/* The adjoint source in the scaled variable: b[off[r]] += vals[r] Q / (1+eta)
+ * at each offset (device arrays; offsets must be interior points of g, an
+ * offset outside the interior is taken with eta = 0; duplicates add). */
+int fd_scatter_add_scaled(const fd_grid* g, float* b, const int64_t* off,
+                          const float* vals, const float* vdt2, const fd_sponge* sp,
+                          int32_t n, void* stream);
+
+/* grad_m = -g_b * vdt2 / dt^2 on the interior, for the g_b accumulated by
+ * fd_adjoint_step_scaled (grad_m may alias g_b). */
+int fd_grad_finalize_scaled(const fd_grid* g, const float* g_b, const float* vdt2,
+                            double dt, float* grad_m, void* stream);
+
 /* ------------------------------------------------------- shot serving
  * S8/S9: a server that runs many independent forward-modelling shots of
  * different grid sizes at once.  Shots are admitted in submission order

@@ -104,6 +104,8 @@ def lib():
                                        _dp, _dpn, _dpn, _dpn, _dpn]
         L.ora_threads.restype = i32
         L.ora_threads.argtypes = []
+        L.ora_set_threads.restype = None
+        L.ora_set_threads.argtypes = [i32]
         _lib = L
     return _lib
 
@@ -111,6 +113,11 @@ def lib():
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return lib().ora_threads()
+
+
+def set_threads(n: int) -> None:
+    """Use ``n`` OpenMP threads in later oracle calls."""
+    lib().ora_set_threads(int(n))
 
 
 # ------------------------------------------------------------------ layout helpers

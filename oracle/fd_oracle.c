@@ -439,6 +439,11 @@ double ora_fwi_gradient(int nx, int ny, int nz, double dx, double dy, double dz,
   return J;
 }
 
+/* Sets the OpenMP threads of later parallel regions (n >= 1). */
+void ora_set_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+}
+
 /* Threads an OpenMP region of this library uses (for reporting only). */
 int ora_threads(void) {
   int n = 1;

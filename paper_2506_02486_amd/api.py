@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import check, fd_grid, fd_source, fd_sponge, lib
+from ._lib import FDError, check, fd_grid, fd_source, fd_sponge, lib  # noqa: F401
 
 COURANT = 0.4
 RICKER_F0 = 15.0
@@ -235,8 +235,16 @@ def adjoint_step(grid: Grid, a_nn, a_n1, a_out, vdt2, sponge=None, u_n=None, g_v
                                 sref, _stream(stream)), "fd_adjoint_step")
 
 
+def _check_points(where: str, off: torch.Tensor, vals: torch.Tensor):
+    if (off.dtype != torch.int64 or vals.dtype != torch.float32 or not off.is_contiguous()
+            or not vals.is_contiguous() or vals.numel() < off.numel()
+            or off.device.type != "cuda" or vals.device.type != "cuda"):
+        raise TypeError(f"{where}: device int64 offsets and float32 values (>= as many)")
+
+
 def scatter_add(grid: Grid, a, off: torch.Tensor, vals: torch.Tensor, stream=None):
     grid.check(a, "a")
+    _check_points("scatter_add", off, vals)
     check(lib().fd_scatter_add(grid.ref, a.data_ptr(), off.data_ptr(), vals.data_ptr(),
                                off.numel(), _stream(stream)), "fd_scatter_add")
 
@@ -248,11 +256,89 @@ def grad_finalize(grid: Grid, g_vdt2, vdt2, dt: float, grad_m, stream=None):
                                  grad_m.data_ptr(), _stream(stream)), "fd_grad_finalize")
 
 
+def adjoint_step_scaled(grid: Grid, b_nn, b_n1, b_out, vdt2, sponge=None, u_n=None, g_b=None,
+                        src=None, stream=None):
+    """b_out = D (2 b_n1 - E b_nn + Q L b_n1) (the adjoint in b = Q D lambda), and
+    optionally g_b += b_n1 (L u_n + f)."""
+    if b_nn is None or b_n1 is None or b_out is None:
+        raise ValueError("adjoint_step_scaled: b_nn, b_n1 and b_out are required")
+    for n, t in (("b_nn", b_nn), ("b_n1", b_n1), ("b_out", b_out), ("vdt2", vdt2),
+                 ("u_n", u_n), ("g_b", g_b)):
+        grid.check(t, n)
+    sref = None
+    if src is not None:
+        (i, j, k), w = src
+        sref = C.byref(fd_source(int(i), int(j), int(k), float(w)))
+    check(lib().fd_adjoint_step_scaled(grid.ref, b_nn.data_ptr(), b_n1.data_ptr(),
+                                       b_out.data_ptr(), vdt2.data_ptr(), sponge_ref(sponge),
+                                       _ptr(u_n), _ptr(g_b), sref, _stream(stream)),
+          "fd_adjoint_step_scaled")
+
+
+def scatter_add_scaled(grid: Grid, b, off: torch.Tensor, vals: torch.Tensor, vdt2,
+                       sponge=None, stream=None):
+    """b[off] += vals * vdt2 / (1 + eta) at each offset."""
+    grid.check(b, "b")
+    grid.check(vdt2, "vdt2")
+    _check_points("scatter_add_scaled", off, vals)
+    check(lib().fd_scatter_add_scaled(grid.ref, b.data_ptr(), off.data_ptr(), vals.data_ptr(),
+                                      vdt2.data_ptr(), sponge_ref(sponge), off.numel(),
+                                      _stream(stream)), "fd_scatter_add_scaled")
+
+
+def grad_finalize_scaled(grid: Grid, g_b, vdt2, dt: float, grad_m, stream=None):
+    for n, t in (("g_b", g_b), ("vdt2", vdt2), ("grad_m", grad_m)):
+        grid.check(t, n)
+    check(lib().fd_grad_finalize_scaled(grid.ref, g_b.data_ptr(), vdt2.data_ptr(), dt,
+                                        grad_m.data_ptr(), _stream(stream)),
+          "fd_grad_finalize_scaled")
+
+
 def set_kchunk(kchunk: int):
     check(lib().fd_set_kchunk(int(kchunk)), "fd_set_kchunk")
 
 
 # ----------------------------------------------------------------- forward model
+
+def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: int, src=None,
+                wavelet=None, rec_off: torch.Tensor | None = None,
+                traces: torch.Tensor | None = None, send=None, stream=None):
+    """``nt`` steps in the library's native loop (fd_forward_run): per step unpack of
+    ``send`` into the opposite halos (loopback; skipped when ``send`` is None), the
+    fused update with the source ``src`` at amplitude ``wavelet[s]``, pack into
+    ``send``, and the receiver row ``traces[s]``.  Returns the rotated
+    ``(u_prev, u, u_next)``: u^{n+nt-1}, u^{n+nt} and the spare array."""
+    for n, t in (("u_prev", u_prev), ("u", u), ("u_next", u_next), ("vdt2", vdt2)):
+        grid.check(t, n)
+    r = _lib.fd_run()
+    bufs = {t.data_ptr(): t for t in (u_prev, u, u_next)}
+    r.u_prev, r.u, r.u_next = u_prev.data_ptr(), u.data_ptr(), u_next.data_ptr()
+    r.vdt2 = vdt2.data_ptr()
+    if sponge is not None:
+        r.sponge = sponge.c
+    r.nt = int(nt)
+    wa = None
+    if src is not None:
+        wa = np.ascontiguousarray(wavelet, dtype=np.float32)
+        if wa.size < nt:
+            raise ValueError("forward_run: wavelet shorter than nt")
+        r.wavelet = wa.ctypes.data
+        r.src[0], r.src[1], r.src[2] = (int(x) for x in src)
+    if rec_off is not None and rec_off.numel():
+        if (rec_off.dtype != torch.int64 or traces is None or traces.dtype != torch.float32
+                or not traces.is_contiguous() or traces.dim() != 2
+                or traces.shape[0] < nt or traces.shape[1] != rec_off.numel()):
+            raise TypeError("forward_run: rec_off int64 and contiguous float32 traces "
+                            "(>= nt, nrec)")
+        r.nrec = rec_off.numel()
+        r.rec_off = rec_off.data_ptr()
+        r.traces = traces.data_ptr()
+    if send is not None:
+        for f in range(6):
+            r.send[f] = send[f].data_ptr()
+    check(lib().fd_forward_run(grid.ref, C.byref(r), _stream(stream)), "fd_forward_run")
+    return bufs[r.u_prev], bufs[r.u], bufs[r.u_next]
+
 
 @dataclass
 class Geometry:
@@ -356,27 +442,11 @@ class Simulation:
     def _run_native(self, nt, w, traces, stream):
         """The same per-step sequence as the fused path, looped in native code
         (fd_forward_run)."""
-        r = _lib.fd_run()
-        bufs = {t.data_ptr(): t for t in (self.u_prev, self.u, self.u_next)}
-        r.u_prev, r.u, r.u_next = self.u_prev.data_ptr(), self.u.data_ptr(), self.u_next.data_ptr()
-        r.vdt2 = self.vdt2.data_ptr()
-        if self.sponge is not None:
-            r.sponge = self.sponge.c
-        r.nt = nt
-        wa = None
-        if w is not None:
-            wa = np.ascontiguousarray(w, dtype=np.float32)
-            r.wavelet = wa.ctypes.data
-            r.src[0], r.src[1], r.src[2] = (int(x) for x in self.geom.src)
-        if self.rec_off is not None:
-            r.nrec = self.nrec
-            r.rec_off = self.rec_off.data_ptr()
-            r.traces = traces.data_ptr()
-        if self.exchange:
-            for f in range(6):
-                r.send[f] = self.send[f].data_ptr()
-        check(lib().fd_forward_run(self.grid.ref, C.byref(r), _stream(stream)), "fd_forward_run")
-        self.u_prev, self.u, self.u_next = bufs[r.u_prev], bufs[r.u], bufs[r.u_next]
+        self.u_prev, self.u, self.u_next = forward_run(
+            self.grid, self.u_prev, self.u, self.u_next, self.vdt2, self.sponge, nt,
+            src=self.geom.src if w is not None else None, wavelet=w, rec_off=self.rec_off,
+            traces=traces if self.rec_off is not None else None,
+            send=self.send if self.exchange else None, stream=stream)
         self.n += nt
         self._faces_current = bool(self.exchange) or self._faces_current
         return traces[:, :self.nrec]

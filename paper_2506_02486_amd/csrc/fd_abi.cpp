@@ -508,8 +508,78 @@ int fd_grad_finalize(const fd_grid* g, const float* g_vdt2, const float* vdt2, d
   if (!g_vdt2 || !vdt2 || !grad_m) return fail(FD_EINVAL, "fd_grad_finalize: NULL array");
   if (!finite_pos(dt)) return fail(FD_EINVAL, "fd_grad_finalize: dt must be > 0");
   if (overlaps(g, vdt2, grad_m)) return fail(FD_EINVAL, "fd_grad_finalize: grad_m overlaps vdt2");
-  return check_hip(launch_grad_finalize(make_geo(g), g_vdt2, vdt2, dt, grad_m, as_stream(stream)),
-                   "fd_grad_finalize launch");
+  return check_hip(
+      launch_grad_finalize(make_geo(g), g_vdt2, vdt2, dt, false, grad_m, as_stream(stream)),
+      "fd_grad_finalize launch");
+}
+
+int fd_adjoint_step_scaled(const fd_grid* g, const float* b_nn, const float* b_n1, float* b_out,
+                           const float* vdt2, const fd_sponge* sp, const float* u_n, float* g_b,
+                           const fd_source* src, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!b_nn || !b_n1 || !b_out || !vdt2)
+    return fail(FD_EINVAL, "fd_adjoint_step_scaled: NULL array");
+  if (overlaps(g, b_n1, b_out))
+    return fail(FD_EINVAL, "fd_adjoint_step_scaled: b_out overlaps b_n1");
+  if (overlaps(g, vdt2, b_out))
+    return fail(FD_EINVAL, "fd_adjoint_step_scaled: b_out overlaps vdt2");
+  if (b_out != b_nn && overlaps(g, b_nn, b_out))
+    return fail(FD_EINVAL, "fd_adjoint_step_scaled: b_out partially overlaps b_nn");
+  if (g_b) {
+    if (!u_n) return fail(FD_EINVAL, "fd_adjoint_step_scaled: gradient needs u_n");
+    if (overlaps(g, g_b, b_out) || overlaps(g, g_b, b_n1) || overlaps(g, g_b, u_n) ||
+        overlaps(g, g_b, vdt2) || overlaps(g, g_b, b_nn))
+      return fail(FD_EINVAL, "fd_adjoint_step_scaled: g_b overlaps another array");
+    if (src && (src->i < 0 || src->i >= g->nx || src->j < 0 || src->j >= g->ny || src->k < 0 ||
+                src->k >= g->nz))
+      return fail(FD_EINVAL, "fd_adjoint_step_scaled: source outside the interior");
+  }
+  const float *ex, *ey, *ez;
+  rc = check_sponge(sp, &ex, &ey, &ez);
+  if (rc) return rc;
+  const Geo geo = make_geo(g);
+  const Coef c = make_coef(g);
+  hipStream_t s = as_stream(stream);
+  // gradient first: it reads b_n1, which neither kernel writes; no damping
+  // factor (D is inside b)
+  if (g_b) {
+    rc = check_hip(launch_grad(geo, c, u_n, b_n1, g_b, nullptr, nullptr, nullptr, src, s),
+                   "gradient launch");
+    if (rc) return rc;
+  }
+  // the forward update run backward in time: b_out = D (2 b_n1 - E b_nn + Q L b_n1)
+  return check_hip(launch_step(geo, c, b_nn, b_n1, b_out, vdt2, ex, ey, ez, nullptr, s),
+                   "fd_adjoint_step_scaled launch");
+}
+
+int fd_scatter_add_scaled(const fd_grid* g, float* b, const int64_t* off, const float* vals,
+                          const float* vdt2, const fd_sponge* sp, int32_t n, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (n < 0) return fail(FD_EINVAL, "fd_scatter_add_scaled: n < 0");
+  if (n == 0) return FD_OK;
+  if (!b || !off || !vals || !vdt2) return fail(FD_EINVAL, "fd_scatter_add_scaled: NULL array");
+  if (overlaps(g, vdt2, b)) return fail(FD_EINVAL, "fd_scatter_add_scaled: b overlaps vdt2");
+  const float *ex, *ey, *ez;
+  rc = check_sponge(sp, &ex, &ey, &ez);
+  if (rc) return rc;
+  return check_hip(launch_scatter_add_scaled(make_geo(g), b, off, vals, vdt2, ex, ey, ez, n,
+                                             as_stream(stream)),
+                   "fd_scatter_add_scaled launch");
+}
+
+int fd_grad_finalize_scaled(const fd_grid* g, const float* g_b, const float* vdt2, double dt,
+                            float* grad_m, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!g_b || !vdt2 || !grad_m) return fail(FD_EINVAL, "fd_grad_finalize_scaled: NULL array");
+  if (!finite_pos(dt)) return fail(FD_EINVAL, "fd_grad_finalize_scaled: dt must be > 0");
+  if (overlaps(g, vdt2, grad_m))
+    return fail(FD_EINVAL, "fd_grad_finalize_scaled: grad_m overlaps vdt2");
+  return check_hip(
+      launch_grad_finalize(make_geo(g), g_b, vdt2, dt, true, grad_m, as_stream(stream)),
+      "fd_grad_finalize_scaled launch");
 }
 
 }  // extern "C"

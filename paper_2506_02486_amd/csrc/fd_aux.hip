@@ -89,6 +89,59 @@ __global__ void __launch_bounds__(BS) unpack_kernel(Geo g, float* __restrict__ u
   }
 }
 
+// 16-byte form of pack/unpack for the default layout (origin, strides and nx
+// multiples of 4 floats): each thread moves four consecutive x points.  Element
+// offset in u of the first of the four points that float4 e4 of `face` covers;
+// `halo` selects the unpack destination (the halo) instead of the pack source.
+__device__ __forceinline__ long long face4_at(const Geo& g, int face, unsigned e4, bool halo) {
+  const unsigned nx4 = (unsigned)g.nx >> 2;
+  int i, j, k;
+  if (face < 2) {  // [nz][ny][4]: one float4 per (j, k)
+    j = e4 % (unsigned)g.ny;
+    k = e4 / (unsigned)g.ny;
+    i = face == 0 ? (halo ? -4 : 0) : (halo ? g.nx : g.nx - 4);
+  } else if (face < 4) {  // [nz][4][nx]
+    const unsigned t = e4 / nx4;
+    const int q = t & 3u;
+    i = 4 * (int)(e4 % nx4);
+    k = t >> 2;
+    j = face == 2 ? (halo ? q - 4 : q) : (halo ? g.ny + q : g.ny - 4 + q);
+  } else {  // [4][ny][nx]
+    const unsigned t = e4 / nx4;
+    const int q = t / (unsigned)g.ny;
+    i = 4 * (int)(e4 % nx4);
+    j = t % (unsigned)g.ny;
+    k = face == 4 ? (halo ? q - 4 : q) : (halo ? g.nz + q : g.nz - 4 + q);
+  }
+  return at(g, i, j, k);
+}
+
+__global__ void __launch_bounds__(BS) pack4_kernel(Geo g, const float* __restrict__ u, Faces f) {
+  const int face = blockIdx.y;
+  float4* __restrict__ dst = reinterpret_cast<float4*>(f.p[face]);
+  if (!dst) return;
+  const unsigned n4 = (unsigned)(face_count(g, face) >> 2);
+  for (unsigned e = blockIdx.x * BS + threadIdx.x; e < n4; e += gridDim.x * BS)
+    dst[e] = *reinterpret_cast<const float4*>(u + face4_at(g, face, e, false));
+}
+
+__global__ void __launch_bounds__(BS) unpack4_kernel(Geo g, float* __restrict__ u, CFaces f) {
+  const int face = blockIdx.y;
+  const float4* __restrict__ src = reinterpret_cast<const float4*>(f.p[face]);
+  if (!src) return;
+  const unsigned n4 = (unsigned)(face_count(g, face) >> 2);
+  for (unsigned e = blockIdx.x * BS + threadIdx.x; e < n4; e += gridDim.x * BS)
+    *reinterpret_cast<float4*>(u + face4_at(g, face, e, true)) = src[e];
+}
+
+bool vec4_ok(const Geo& g, const void* u, const void* const* face) {
+  if ((g.org | g.sy | g.sz | g.nx) & 3) return false;
+  if (reinterpret_cast<uintptr_t>(u) & 15) return false;
+  for (int i = 0; i < 6; ++i)
+    if (reinterpret_cast<uintptr_t>(face[i]) & 15) return false;
+  return true;
+}
+
 __global__ void inject_kernel(float* un, const float* q, const float* ex, const float* ey,
                               const float* ez, long long o, int i, int j, int k, float w) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -102,6 +155,32 @@ __global__ void __launch_bounds__(BS) record_kernel(const float* __restrict__ u,
                                                     float* __restrict__ out) {
   const int r = blockIdx.x * BS + threadIdx.x;
   if (r < n) out[r] = u[off[r]];
+}
+
+// a[off[r]] += vals[r] * Q / (1 + eta) at the point, eta from its interior
+// coordinates (recovered from the offset; an offset outside the interior takes
+// eta = 0).
+__global__ void __launch_bounds__(BS) scatter_add_scaled_kernel(Geo g, float* a,
+                                                                const int64_t* __restrict__ off,
+                                                                const float* __restrict__ vals,
+                                                                const float* __restrict__ q,
+                                                                const float* ex, const float* ey,
+                                                                const float* ez, int n) {
+  const int r = blockIdx.x * BS + threadIdx.x;
+  if (r >= n) return;
+  const long long o = off[r];
+  float w = q[o];
+  if (ex) {
+    const long long t = o - g.org;
+    if (t >= 0) {
+      const long long k = t / g.sz;
+      const long long rem = t - k * g.sz;
+      const long long j = rem / g.sy;
+      const long long i = rem - j * g.sy;
+      if (k < g.nz && j < g.ny && i < g.nx) w = w / (1.f + (ex[i] + ey[j] + ez[k]));
+    }
+  }
+  atomicAdd(a + o, vals[r] * w);
 }
 
 __global__ void __launch_bounds__(BS) scatter_add_kernel(float* a, const int64_t* __restrict__ off,
@@ -187,15 +266,18 @@ __global__ void __launch_bounds__(BS) vmax_kernel(int nx, int ny, int nz,
   }
 }
 
+// scaled: the accumulator holds sum b (L u + f) with b = Q D lambda, so that
+// g_vdt2 = acc / Q and grad_m = -acc Q / dt^2; else acc = g_vdt2 and
+// grad_m = -acc Q^2 / dt^2.
 __global__ void __launch_bounds__(BS) grad_finalize_kernel(Geo g, const float* __restrict__ gq,
                                                            const float* __restrict__ q, float s,
-                                                           float* __restrict__ gm) {
+                                                           bool scaled, float* __restrict__ gm) {
   const int j = blockIdx.y;
   const int k = blockIdx.z;
   for (int i = blockIdx.x * BS + threadIdx.x; i < g.nx; i += gridDim.x * BS) {
     const long long o = at(g, i, j, k);
     const float qq = q[o];
-    gm[o] = -gq[o] * qq * qq * s;
+    gm[o] = scaled ? -gq[o] * qq * s : -gq[o] * qq * qq * s;
   }
 }
 
@@ -235,7 +317,10 @@ hipError_t launch_pack(const Geo& g, const float* u, float* const face[6], hipSt
     if (face[i] && c > mx) mx = c;
   }
   if (mx == 0) return hipSuccess;
-  hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(mx, 4096), 6), dim3(BS), 0, s, g, u, f);
+  if (vec4_ok(g, u, reinterpret_cast<const void* const*>(face)))
+    hipLaunchKernelGGL(pack4_kernel, dim3(blocks_for(mx / 4, 4096), 6), dim3(BS), 0, s, g, u, f);
+  else
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(mx, 4096), 6), dim3(BS), 0, s, g, u, f);
   return hipGetLastError();
 }
 
@@ -248,7 +333,11 @@ hipError_t launch_unpack(const Geo& g, float* u, const float* const face[6], hip
     if (face[i] && c > mx) mx = c;
   }
   if (mx == 0) return hipSuccess;
-  hipLaunchKernelGGL(unpack_kernel, dim3(blocks_for(mx, 4096), 6), dim3(BS), 0, s, g, u, f);
+  if (vec4_ok(g, u, reinterpret_cast<const void* const*>(face)))
+    hipLaunchKernelGGL(unpack4_kernel, dim3(blocks_for(mx / 4, 4096), 6), dim3(BS), 0, s, g, u,
+                       f);
+  else
+    hipLaunchKernelGGL(unpack_kernel, dim3(blocks_for(mx, 4096), 6), dim3(BS), 0, s, g, u, f);
   return hipGetLastError();
 }
 
@@ -318,10 +407,19 @@ hipError_t launch_vmax(const Geo& g, const float* v, int32_t* out, hipStream_t s
 }
 
 hipError_t launch_grad_finalize(const Geo& g, const float* gq, const float* q, double dt,
-                                float* gm, hipStream_t s) {
+                                bool scaled, float* gm, hipStream_t s) {
   const float sc = (float)(1.0 / (dt * dt));
   hipLaunchKernelGGL(grad_finalize_kernel, dim3(blocks_for(g.nx, 64), g.ny, g.nz), dim3(BS), 0,
-                     s, g, gq, q, sc, gm);
+                     s, g, gq, q, sc, scaled, gm);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_add_scaled(const Geo& g, float* a, const int64_t* off,
+                                     const float* vals, const float* q, const float* ex,
+                                     const float* ey, const float* ez, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_add_scaled_kernel, dim3((n + BS - 1) / BS), dim3(BS), 0, s, g, a,
+                     off, vals, q, ex, ey, ez, n);
   return hipGetLastError();
 }
 

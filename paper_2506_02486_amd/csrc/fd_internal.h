@@ -113,7 +113,13 @@ hipError_t launch_unpack(const Geo& g, float* u, const float* const face[6], hip
 hipError_t launch_prepare_vdt2(const Geo& g, const float* v, float* q, double dt, bool from_m,
                                hipStream_t s);
 hipError_t launch_vmax(const Geo& g, const float* v, int32_t* out, hipStream_t s);
+// scaled: gq accumulates b (L u + f) with b = Q D lambda (grad_m = -gq Q / dt^2);
+// else gq = g_vdt2 (grad_m = -gq Q^2 / dt^2)
 hipError_t launch_grad_finalize(const Geo& g, const float* gq, const float* q, double dt,
-                                float* gm, hipStream_t s);
+                                bool scaled, float* gm, hipStream_t s);
+// a[off[r]] += vals[r] * q / (1 + eta) at each (interior) offset
+hipError_t launch_scatter_add_scaled(const Geo& g, float* a, const int64_t* off,
+                                     const float* vals, const float* q, const float* ex,
+                                     const float* ey, const float* ez, int n, hipStream_t s);
 
 }  // namespace fd

@@ -79,7 +79,7 @@ __device__ __forceinline__ float ld_nt(const char* base, unsigned boff) {
 
 // The per-block work of every stencil kernel: tile (bx, by) of the x-y plane,
 // z-chunk bz, of the grid and operands described by p.
-template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE>
+template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY>
 __device__ __forceinline__ void stencil_block(const Params& p, const int bx, const int by,
                                               const int bz) {
   constexpr int TX = TXT;
@@ -89,6 +89,7 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
   constexpr int HPT = 8 / NY;  // y-halo rows each thread row loads per plane
   static_assert(NY == 1 || NY == 2 || NY == 4 || NY == 8, "NY must divide 8");
   static_assert(8 * RY <= TXT, "x-halo cells must fit in one thread row");
+  static_assert(!EARLY || MODE == FWD, "the halo ring needs the unrolled forward z loop");
   __shared__ float sm[2][LY * LX];
 
   const int lane = threadIdx.x;
@@ -216,8 +217,23 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
       if (MODE == ADJ && s >= 4) cq[s - 4][r] = cld[r] ? ld(fk, cb[r]) : 0.f;
     }
   }
+  // x-y halos of the field.  EARLY: a ring like the z queue (slot (P + s) % 9
+  // holds plane k - 4 + s; planes k .. k + 4 are live), filled in the same
+  // iteration as the centre column of the plane, so that a neighbouring tile's
+  // re-read of those cells follows its own load closely enough to hit in L2.
+  // Otherwise: the halos of plane k only, loaded one plane ahead.
   float hy[HPT], hx;
-  {
+  float hq[EARLY ? 9 : 1][HPT], xq[EARLY ? 9 : 1];
+  if (EARLY) {
+#pragma unroll
+    for (int s = 4; s < 9; ++s) {
+      const int k = kb - 4 + s;
+      const char* fk = F0 + (long long)k * szb;
+#pragma unroll
+      for (int h = 0; h < HPT; ++h) hq[s][h] = k < ke ? fld(fk, fk, hyb[h], hy_ld[h], 0.f, 0.f, 0.f) : 0.f;
+      xq[s] = k < ke ? fld(fk, fk, hxb, hx_ld, 0.f, 0.f, 0.f) : 0.f;
+    }
+  } else {
     const float ezv = ezw(kb);
     const char* fk = F0 + (long long)kb * szb;
     const char* qk = Q0 + (long long)kb * szb;
@@ -273,7 +289,15 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
       }
     }
     const bool more = k + 1 < ke;
-    if (more) {
+    if (EARLY) {
+      const int kn = k + 5;
+      if (kn < ke) {
+        const char* fk = F0 + (long long)kn * szb;
+#pragma unroll
+        for (int h = 0; h < HPT; ++h) nhy[h] = fld(fk, fk, hyb[h], hy_ld[h], 0.f, 0.f, 0.f);
+        nhx = fld(fk, fk, hxb, hx_ld, 0.f, 0.f, 0.f);
+      }
+    } else if (more) {
       const float ezv = ezw(k + 1);
       const char* fk = F0 + (long long)(k + 1) * szb;
       const char* qk = Q0 + (long long)(k + 1) * szb;
@@ -308,8 +332,8 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
 #pragma unroll
     for (int r = 0; r < RY; ++r) s[(4 + w * RY + r) * LX + 4 + lane] = zq[(P + 4) % 9][r];
 #pragma unroll
-    for (int h = 0; h < HPT; ++h) s[hy_lds[h]] = hy[h];
-    if (hx_on) s[hx_lds] = hx;
+    for (int h = 0; h < HPT; ++h) s[hy_lds[h]] = EARLY ? hq[(P + 4) % 9][h] : hy[h];
+    if (hx_on) s[hx_lds] = EARLY ? xq[(P + 4) % 9] : hx;
     __syncthreads();
 
     // ---- compute
@@ -381,8 +405,12 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
       pb[r] = npb[r];
     }
 #pragma unroll
-    for (int h = 0; h < HPT; ++h) hy[h] = nhy[h];
-    hx = nhx;
+    for (int h = 0; h < HPT; ++h) {
+      if (EARLY) hq[P][h] = nhy[h];  // plane k + 5
+      else hy[h] = nhy[h];
+    }
+    if (EARLY) xq[P] = nhx;
+    else hx = nhx;
   };
   using std::integral_constant;
   if (MODE != FWD) {  // the adjoint kernels keep the queue in place (fewer scalar registers)
@@ -419,12 +447,13 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
   }
 }
 
-template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE>
+template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY = (MODE == FWD)>
 __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
   const int logical = remap_block(blockIdx.x, gridDim.x);
   const int bx = logical % p.tiles_x;
   const int rest = logical / p.tiles_x;
-  stencil_block<TXT, NY, RY, MODE, SPONGE, FUSE>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
+  stencil_block<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY>(p, bx, rest % p.tiles_y,
+                                                        rest / p.tiles_y);
 }
 
 // Many grids in one launch: block b runs tile tiles[remap(b)] = (slot, bx, by, bz)
@@ -455,7 +484,7 @@ __global__ void __launch_bounds__(TXT * NY) batched_kernel(const BatchShot* __re
   p.sj = b.sj;
   p.sk = b.sk;
   p.sw = a.w[t.x];
-  stencil_block<TXT, NY, RY, FWD, true, true>(p, t.y, t.z, t.w);
+  stencil_block<TXT, NY, RY, FWD, true, true, true>(p, t.y, t.z, t.w);
 }
 
 struct LaunchShape {
@@ -474,12 +503,15 @@ LaunchShape shape_for(const Geo& g, int tx, int ty, int waves_per_block) {
     kc = g_kchunk_override;
   } else {
     // aim at about 4096 waves (16 per CU on 256 CUs) while keeping the z halo
-    // re-read (8 planes per chunk) small
+    // re-read (8 planes per chunk) small: chunks of at least 32 planes, unless the
+    // grid is so small that 32-plane chunks leave the chip mostly idle (its
+    // arrays then sit in cache, and the z-halo re-read costs no HBM traffic)
     const long long target = 4096 / waves_per_block;
     long long chunks = (target + tiles - 1) / tiles;
     if (chunks < 1) chunks = 1;
     kc = (int)((g.nz + chunks - 1) / chunks);
-    if (kc < 32) kc = 32;
+    const int kmin = tiles * ((g.nz + 31) / 32) >= 512 / waves_per_block ? 32 : 4;
+    if (kc < kmin) kc = kmin;
   }
   if (kc > g.nz) kc = g.nz;
   s.kchunk = kc;
@@ -487,7 +519,8 @@ LaunchShape shape_for(const Geo& g, int tx, int ty, int waves_per_block) {
   return s;
 }
 
-template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE = false>
+template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE = false,
+          bool EARLY = (MODE == FWD)>
 hipError_t launch_mode(Params p, hipStream_t st) {
   const LaunchShape sh = shape_for(p.g, TXT, NY * RY, (TXT * NY + 63) / 64);
   p.tiles_x = sh.tiles_x;
@@ -495,7 +528,7 @@ hipError_t launch_mode(Params p, hipStream_t st) {
   p.kchunk = sh.kchunk;
   const long long nb = (long long)sh.tiles_x * sh.tiles_y * sh.zchunks;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((stencil_kernel<TXT, NY, RY, MODE, SPONGE, FUSE>), dim3((unsigned)nb),
+  hipLaunchKernelGGL((stencil_kernel<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY>), dim3((unsigned)nb),
                      dim3(TXT, NY), 0, st, p);
   return hipGetLastError();
 }

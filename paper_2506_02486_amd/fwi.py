@@ -5,13 +5,22 @@ sponge), a Ricker source and receivers; the misfit is any function of the synthe
 traces.  ``FWIGrad.apply(m, problem)`` returns the traces and, on ``backward``, the
 gradient of the loss with respect to m, computed by
 
-* a forward sweep that keeps ``(u^{n-1}, u^n)`` every ``checkpoint_every`` steps,
+* a forward sweep that keeps ``(u^{n-1}, u^n)`` every ``checkpoint_every`` steps
+  (one native step loop, fd_forward_run, per checkpoint interval),
 * a reverse sweep over the segments, last first: each segment's wavefields are
-  recomputed from its checkpoint into a segment buffer, then for n descending
-  ``fd_adjoint_step`` forms lambda^n from lambda^{n+1}, lambda^{n+2} with the
-  gradient g += D lambda^{n+1} (L u^n + f^n) fused in, and ``fd_scatter_add`` adds
-  the trace residual of step n-1 at the receivers,
-* ``fd_grad_finalize``: grad_m = -g vdt2^2 / dt^2.
+  recomputed from its checkpoint into a segment buffer, then for n descending the
+  adjoint step forms the adjoint field at n from those at n+1 and n+2 with the
+  gradient accumulation fused in, and the trace residual of step n-1 is added at
+  the receivers,
+* the final scaling of the accumulated gradient to grad_m.
+
+The adjoint runs by default in the scaled variable b = vdt2 D lambda
+(``fd_adjoint_step_scaled``, ``fd_scatter_add_scaled``, ``fd_grad_finalize_scaled``):
+there it is the forward update run backward in time, on the forward kernel, and
+g_b = sum b^{n+1} (L u^n + f^n) gives grad_m = -g_b vdt2 / dt^2.  ``scaled=False``
+runs it in lambda (``fd_adjoint_step``: lambda^n = 2 D lambda^{n+1} +
+L(vdt2 D lambda^{n+1}) - E D lambda^{n+2}, g += D lambda^{n+1} (L u^n + f^n),
+``fd_scatter_add``, ``fd_grad_finalize``: grad_m = -g vdt2^2 / dt^2).
 
 dt and the sponge are fixed when the problem is built (they do not depend on m).
 All device work runs in libfd's kernels; torch allocates buffers and copies
@@ -69,20 +78,27 @@ class FWIProblem:
         up, u, un = g.zeros(self.device), g.zeros(self.device), g.zeros(self.device)
         traces = torch.zeros((self.nt, self.nrec), dtype=torch.float32, device=self.device)
         self.ckpt = []
-        for n in range(self.nt):
-            if checkpoints and n % self.C == 0:
+        for s in range(0, self.nt, self.C):  # one native loop per checkpoint interval
+            e = min(s + self.C, self.nt)
+            if checkpoints:
                 self.ckpt.append((up.clone(), u.clone()))
-            api.step(g, up, u, un, self.vdt2, self.sponge)
-            api.inject_source(g, un, self.vdt2, self.sponge, self.src, float(self.w[n]))
-            api.record_receivers(g, un, self.rec_off, traces[n])
-            up, u, un = u, un, up
+            up, u, un = api.forward_run(g, up, u, un, self.vdt2, self.sponge, e - s,
+                                        src=self.src, wavelet=self.w[s:e],
+                                        rec_off=self.rec_off, traces=traces[s:e])
         return traces
 
     # ------------------------------------------------------------ adjoint
-    def backward(self, res: torch.Tensor, want_lambda_src: bool = False):
+    def backward(self, res: torch.Tensor, want_grad_w: bool = False, scaled: bool = True,
+                 want_lambda_src: bool = False):
         """grad_m (interior, float32) for trace residual ``res`` (nt, nrec) = dLoss/dtraces.
-        With ``want_lambda_src`` also returns lambda^{n+1} at the source for each n
-        (the adjoint field that the source's own sensitivity is read from)."""
+
+        ``scaled`` (default) runs the adjoint in b = vdt2 D lambda, where it is the
+        forward update run backward in time (fd_adjoint_step_scaled); with
+        ``want_grad_w`` it also returns dLoss/dw[n] = b^{n+1} at the source.
+        ``scaled=False`` runs it in lambda itself (fd_adjoint_step); with
+        ``want_lambda_src`` it also returns lambda^{n+1} at the source."""
+        if scaled and want_lambda_src or not scaled and want_grad_w:
+            raise ValueError("want_grad_w goes with scaled=True, want_lambda_src with False")
         g = self.grid
         nt, C = self.nt, self.C
         if not self.ckpt:
@@ -90,6 +106,8 @@ class FWIProblem:
         res = res.to(device=self.device, dtype=torch.float32).contiguous()
         if res.shape != (nt, self.nrec):
             raise ValueError(f"residual must be ({nt}, {self.nrec})")
+        if scaled:
+            return self._backward_scaled(res, want_grad_w)
         A = g.zeros(self.device)  # lambda^{n+2}
         B = g.zeros(self.device)  # lambda^{n+1}
         api.scatter_add(g, B, self.rec_off, res[nt - 1])
@@ -97,16 +115,7 @@ class FWIProblem:
         seg = [g.zeros(self.device) for _ in range(min(C, nt))]
         lam_src = torch.zeros(nt, dtype=torch.float32, device=self.device) if want_lambda_src else None
         for j in range(len(self.ckpt) - 1, -1, -1):
-            s = j * C
-            e = min(s + C, nt)
-            prev, cur = self.ckpt[j]
-            seg[0].copy_(cur)
-            before = prev
-            for n in range(s, e - 1):  # recompute u^{s+1} .. u^{e-1}
-                i = n - s
-                api.step(g, before, seg[i], seg[i + 1], self.vdt2, self.sponge)
-                api.inject_source(g, seg[i + 1], self.vdt2, self.sponge, self.src, float(self.w[n]))
-                before = seg[i]
+            s, e = self._recompute(j, seg)
             for n in range(e - 1, s - 1, -1):
                 if lam_src is not None:
                     api.record_receivers(g, B, self.src_off, lam_src[n:n + 1])
@@ -120,6 +129,46 @@ class FWIProblem:
         out = g.interior(gm).clone()
         if want_lambda_src:
             return out, lam_src
+        return out
+
+    def _recompute(self, j: int, seg: list[torch.Tensor]) -> tuple[int, int]:
+        """u^s .. u^{e-1} of segment j into seg[0 .. e-s-1] from its checkpoint."""
+        g, C = self.grid, self.C
+        s = j * C
+        e = min(s + C, self.nt)
+        prev, cur = self.ckpt[j]
+        seg[0].copy_(cur)
+        before = prev
+        for n in range(s, e - 1):
+            i = n - s
+            api.step_fused(g, before, seg[i], seg[i + 1], self.vdt2, self.sponge,
+                           (self.src, float(self.w[n])))
+            before = seg[i]
+        return s, e
+
+    def _backward_scaled(self, res: torch.Tensor, want_grad_w: bool):
+        g, nt = self.grid, self.nt
+        A = g.zeros(self.device)  # b^{n+2}
+        B = g.zeros(self.device)  # b^{n+1}
+        api.scatter_add_scaled(g, B, self.rec_off, res[nt - 1], self.vdt2, self.sponge)
+        gb = g.zeros(self.device)
+        seg = [g.zeros(self.device) for _ in range(min(self.C, nt))]
+        grad_w = torch.zeros(nt, dtype=torch.float32, device=self.device) if want_grad_w else None
+        for j in range(len(self.ckpt) - 1, -1, -1):
+            s, e = self._recompute(j, seg)
+            for n in range(e - 1, s - 1, -1):
+                if grad_w is not None:
+                    api.record_receivers(g, B, self.src_off, grad_w[n:n + 1])
+                api.adjoint_step_scaled(g, A, B, A, self.vdt2, self.sponge, u_n=seg[n - s],
+                                        g_b=gb, src=(self.src, float(self.w[n])))
+                if n >= 1:
+                    api.scatter_add_scaled(g, A, self.rec_off, res[n - 1], self.vdt2,
+                                           self.sponge)
+                A, B = B, A
+        api.grad_finalize_scaled(g, gb, self.vdt2, self.dt, gb)
+        out = g.interior(gb).clone()
+        if want_grad_w:
+            return out, grad_w
         return out
 
 

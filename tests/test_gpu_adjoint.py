@@ -1,7 +1,9 @@
 """GPU parity of the adjoint path (S10, S11) against the FP64 oracle.
 
 fd_adjoint_step and the fused gradient are compared element by element with the
-oracle's transpose step (relative L2 <= 1e-6, as for the forward step); the transpose
+oracle's transpose step (relative L2 <= 1e-6, as for the forward step), and so is the
+scaled form (fd_adjoint_step_scaled on b = vdt2 D lambda, against vdt2 D times the
+oracle's step); the transpose
 identity is checked in FP32 with FP64 reductions (<= 1e-5 relative); the checkpointed
 FWI gradient is compared with the oracle's full-storage gradient driven by the same
 residual (relative L2 <= 1e-3), with the oracle's own end-to-end gradient and FP64
@@ -104,6 +106,52 @@ def test_one_step_dot_test_fp32():
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
+@pytest.mark.parametrize("periodic", [False, True])
+@pytest.mark.parametrize("shape", [(70, 37, 29), (64, 16, 33)])
+def test_scaled_adjoint_step_is_qd_times_the_lambda_step(shape, periodic):
+    """fd_adjoint_step_scaled on b = Q D lambda equals Q D times the oracle's transpose
+    step on lambda, and its gradient accumulation Q times the oracle's; the scaled
+    adjoint source and finalize match their definitions."""
+    nx, ny, nz = shape
+    v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
+    sim = api.Simulation(v, sponge_width=6)
+    g = sim.grid
+    q = ora.vdt2(v, sim.dt)
+    eta = ora.sponge_tables(nx, ny, nz, 6, float(v.max()), D10, sim.dt)
+    qd = q / (1.0 + eta[0][None, None, :] + eta[1][None, :, None] + eta[2][:, None, None])
+    b2, b1, u = _fields(g, (11, 12, 13), periodic)
+    I = lambda t: g.interior(t).cpu().numpy().astype(np.float64)
+    gb = g.zeros()
+    out = g.zeros()
+    src = (nx // 2, 3, nz - 2)
+    api.adjoint_step_scaled(g, b2, b1, out, sim.vdt2, sim.sponge, u_n=u, g_b=gb,
+                            src=(src, 5.0))
+    a_o, g_o = ora.adjoint_step(I(b2) / qd, I(b1) / qd, q, D10, eta, periodic, u_n=I(u),
+                                g=np.zeros((nz, ny, nx)), w=5.0, src=src)
+    assert rel_l2(I(out), qd * a_o) <= 1e-6
+    assert rel_l2(I(gb), q * g_o) <= 1e-6
+    # in place (b_out aliases b_nn) gives the same bits; b_out may not alias b_n1
+    api.adjoint_step_scaled(g, b2, b1, b2, sim.vdt2, sim.sponge)
+    assert torch.equal(b2, out)
+    with pytest.raises(api.FDError):
+        api.adjoint_step_scaled(g, b2, b1, b1, sim.vdt2, sim.sponge)
+    # adjoint source: b[off] += vals Q / (1 + eta)
+    pts = np.array([[0, 0, 0], [nx - 1, 2, 5], [3, ny - 1, nz - 1], [0, 0, 0]], np.int32)
+    off = torch.from_numpy(g.offsets(pts)).cuda()
+    vals = torch.tensor([1.0, -2.0, 0.5, 0.25], device="cuda")
+    z = g.zeros()
+    api.scatter_add_scaled(g, z, off, vals, sim.vdt2, sim.sponge)
+    Z = I(z)
+    want = np.zeros_like(Z)
+    for (i, j, k), val in zip(pts, [1.0, -2.0, 0.5, 0.25]):
+        want[k, j, i] += val * qd[k, j, i]
+    assert np.allclose(Z, want, rtol=1e-6, atol=0)
+    # finalize: grad_m = -g_b Q / dt^2
+    gm = g.zeros()
+    api.grad_finalize_scaled(g, gb, sim.vdt2, sim.dt, gm)
+    assert rel_l2(I(gm), -I(gb) * I(sim.vdt2) / sim.dt ** 2) <= 1e-6
+
+
 def test_scatter_add_and_finalize():
     g = api.Grid(20, 10, 12)
     a = g.zeros()
@@ -160,6 +208,11 @@ def test_fwi_gradient_matches_oracle_and_central_differences():
     obs_same = ref["traces"] - (tr_gpu - obs.astype(np.float32).astype(np.float64))
     ref_same = ora.fwi_gradient(None, nt, dt, obs_same, src, w, rec, D10, eta, q=dt * dt / m0)
     assert rel_l2(gm, ref_same["grad_m"]) <= 1e-3
+    # the adjoint in lambda itself (fd_adjoint_step) gives the same gradient
+    tr = prob.forward(m)
+    gm_a = prob.backward(tr - obs_t, scaled=False).cpu().numpy()
+    assert rel_l2(gm_a, ref_same["grad_m"]) <= 1e-3
+    assert rel_l2(gm_a, gm) <= 5e-4
     vox = fd_voxels(ref["grad_m"], count=16, seed=5)
 
     def Jo(mm):
@@ -208,17 +261,22 @@ def test_fwi_full_size_source_dot_test():
     m = torch.from_numpy((1.0 / v0.astype(np.float64) ** 2).astype(np.float32)).cuda()
     prob.forward(m)
     r = torch.from_numpy(random_field((nt, rec.shape[0]), 8, scale=1e-3)).cuda()
-    _, lam = prob.backward(r, want_lambda_src=True)
+    # scaled adjoint: dLoss/dw[n] = b^{n+1} at the source
+    _, grad_w = prob.backward(r, want_grad_w=True)
+    grad_w = grad_w.double().cpu().numpy()
+    # adjoint in lambda: dLoss/dw[n] = lambda^{n+1} vdt2 / (1 + eta) at the source
+    _, lam = prob.backward(r, scaled=False, want_lambda_src=True)
     g = prob.grid
     s_off = g.offsets(np.array([src], np.int32))[0]
     qs = float(prob.vdt2.cpu()[s_off])
     eta_s = float(prob.sponge.eta_x.cpu()[src[0]] + prob.sponge.eta_y.cpu()[src[1]]
                   + prob.sponge.eta_z.cpu()[src[2]])
-    grad_w = lam.double().cpu().numpy() * qs / (1.0 + eta_s)
+    grad_w_a = lam.double().cpu().numpy() * qs / (1.0 + eta_s)
     # F w' for an independent wavelet w' (same kernels, source term scaled)
     w2 = random_field((nt,), 9).astype(np.float32)
     prob.w = w2
     tr2 = prob.forward(m, checkpoints=False)
     lhs = float((tr2.double() * r.double()).sum())
-    rhs = float(np.dot(w2.astype(np.float64), grad_w))
-    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    for gw in (grad_w, grad_w_a):
+        rhs = float(np.dot(w2.astype(np.float64), gw))
+        assert abs(lhs - rhs) <= 1e-5 * abs(lhs)

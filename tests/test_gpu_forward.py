@@ -190,8 +190,9 @@ def test_resume_is_bitwise():
     assert torch.equal(a.state()[1], b.state()[1])
 
 
-def test_pack_unpack_bit_exact():
-    nx, ny, nz = 70, 9, 13
+@pytest.mark.parametrize("nx,ny,nz", [(70, 9, 13), (72, 9, 13), (8, 5, 4)])
+def test_pack_unpack_bit_exact(nx, ny, nz):
+    """nx = 70 takes the scalar kernels; nx a multiple of 4 the 16-byte ones."""
     g = api.Grid(nx, ny, nz)
     u = torch.from_numpy(random_field((g.elems,), 5)).cuda()
     faces = api.face_buffers(g)
@@ -252,6 +253,75 @@ def test_full_size_512_sampled_per_step_parity():
     assert np.abs(want).max() > 0
     assert rel_l2(gv, want) <= 1e-6
     assert np.abs(gv - want).max() <= 1e-5 * np.abs(want).max()
+
+
+def test_full_size_512_random_state_one_step():
+    """512^3, sponge 16, loopback, the launch configuration of the benchmark, from a
+    random state (nonzero on every face, edge and corner): one fused step against the
+    oracle at sampled points, so the halo exchange and the tile/chunk boundaries are
+    exercised at full size."""
+    n = 512
+    v = smooth_velocity(n, n, n, seed=2)
+    src = center_source(n, n, n)
+    sim = api.Simulation(v, sponge_width=16, exchange="loopback", geom=api.Geometry(src=src))
+    up = random_field((n, n, n), 21)
+    u = random_field((n, n, n), 22)
+    sim.grid.interior(sim.u_prev).copy_(torch.from_numpy(up))
+    sim.grid.interior(sim.u).copy_(torch.from_numpy(u))
+    sim._faces_current = False  # the faces of the new u^n are packed by the next run
+    w_src = float(ora.ricker(1, sim.dt, n0=0)[0])
+    sim.run(1)
+    got = sim.state()[1].cpu().numpy()
+    rng = np.random.default_rng(11)
+    edge = np.array([0, 1, 2, 3, 4, 5, 31, 32, 63, 64, 127, 128, 255, 256, 383, 384, 447, 448,
+                     506, 507, 508, 509, 510, 511])
+    pts = [np.stack(np.meshgrid(edge, edge, edge, indexing="ij"), -1).reshape(-1, 3)]
+    pts.append(rng.integers(0, n, size=(6000, 3)))
+    pts.append(np.array([src]))
+    pts = np.ascontiguousarray(np.concatenate(pts), dtype=np.int32)
+    q = ora.vdt2(v, sim.dt)
+    eta = ora.sponge_tables(n, n, n, 16, float(v.max()), D10, sim.dt)
+    want = ora.step_points(up, u, q, pts, eta=eta, periodic=True, src=src, w_src=w_src)
+    gv = got[pts[:, 2], pts[:, 1], pts[:, 0]]
+    assert rel_l2(gv, want) <= 1e-6
+    assert np.abs(gv - want).max() <= 1e-5 * np.abs(want).max()
+
+
+def test_full_size_512_energy_is_conserved_across_the_periodic_wrap():
+    """Property at full size: with no sponge and no source, the leapfrog conserves
+    I^n = sum (u^n^2 - u^{n+1} u^{n-1}) / vdt2 (the discrete energy, written with
+    L u^n = (u^{n+1} - 2u^n + u^{n-1}) / vdt2).  A Gaussian pulse centred on a corner
+    of the 512^3 periodic (loopback) box crosses every face, edge and corner halo."""
+    n = 512
+    v = smooth_velocity(n, n, n, seed=2)
+    sim = api.Simulation(v, exchange="loopback")
+    g = sim.grid
+    ax = torch.arange(n, dtype=torch.float64, device="cuda")
+    d1 = torch.minimum(ax, n - ax)  # periodic distance to index 0
+    e = torch.exp(-(d1 / 3.0) ** 2 / 2)
+    pulse = (e[:, None, None] * e[None, :, None] * e[None, None, :]).float()
+    g.interior(sim.u_prev).copy_(pulse)
+    g.interior(sim.u).copy_(pulse)
+    sim._faces_current = False
+    del pulse
+    q = g.interior(sim.vdt2).double()
+
+    def energy(a, b, c):
+        return float(((b.double() ** 2 - c.double() * a.double()) / q).sum())
+
+    hist = [g.interior(sim.u).clone()]
+    I = []
+    for _ in range(40):
+        sim.run(1)
+        hist.append(g.interior(sim.u).clone())
+        if len(hist) == 3:
+            I.append(energy(*hist))
+            hist.pop(0)
+    I = np.array(I)
+    assert I[0] > 0
+    assert np.abs(I - I[0]).max() <= 1e-4 * I[0]
+    # nothing reached the centre of the box (the support grows 4 cells per step)
+    assert float(g.interior(sim.u)[n // 2, n // 2, n // 2]) == 0.0
 
 
 @pytest.mark.parametrize("shape,width", [((100, 37, 45), 6), ((64, 64, 64), 16), ((9, 70, 5), 2)])
