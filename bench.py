@@ -7,14 +7,16 @@ centre, receivers on the centre x-line, the six faces packed and unpacked into
 contiguous buffers every step (loopback exchange) -- after W untimed warm-up steps,
 and prints one JSON line.
 
-A step is one pass of the per-step path: halo_unpack of the faces packed by the
-previous step, fd_step_fused (leapfrog update with the source term in the same
-kernel), halo_pack of the new field, record_receivers, pointer rotation.  ``value``
-is interior points x steps / wall time in Gpts/s with every array resident in HBM.
-``roofline`` rates the dominant kernel (the stencil of fd_step_fused) by its
-algorithmic bytes (16 B per interior point: u^n, u^{n-1} and vdt2 read once, u^{n+1}
-written once) over its average launch time from HIP events on its own stream.  ``cpu_baseline`` times the FP64 CPU oracle on
-a bounded sample of the same workload.
+A step is one pass of the per-step path: one fd_step_exchange -- the face halos of
+u^n read from the receive buffers (the loopback of the faces the previous step
+packed), the leapfrog update with the source term, and the six faces of u^{n+1}
+packed into the other face set, all in one kernel -- then record_receivers and the
+pointer rotation.  ``value`` is interior points x steps / wall time in Gpts/s with
+every array resident in HBM.  ``roofline`` rates that kernel by its algorithmic
+bytes (16 B per interior point: u^n, u^{n-1} and vdt2 read once, u^{n+1} written
+once; plus 4 B per face point read and 4 B per face point written) over its average
+launch time from HIP events on its own stream.  ``cpu_baseline`` times the FP64 CPU
+oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -252,7 +254,7 @@ def small_bench(steps=100, repeats=5):
         tr = torch.zeros((steps, sim.nrec), dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sim.run(steps, tr, fused="native")
+        sim.run(steps, tr, mode="native")
         torch.cuda.synchronize()
         if r:  # the first run warms the code paths
             times.append(time.perf_counter() - t0)
@@ -404,17 +406,34 @@ def main():
     log(f"bench: timing {K} steps")
     assert sim._faces_current  # the warm-up left the faces of u^n in the send buffers
     torch.cuda.synchronize()
+    # face sets: `cur` holds the faces of u^n (its loopback is this step's receive
+    # side), `nxt` receives the faces of u^{n+1}.  fd_step_exchange of the full
+    # sets runs unpack(y, z faces), the stencil (x faces inside), pack(y, z faces);
+    # the same three kernels are issued here through the split calls so that the
+    # events bracket the stencil kernel alone.
+    cur, nxt = sim.send, sim.send2
+
+    def split(F):
+        lb = api.loopback(F)
+        return ([None, None] + lb[2:], lb[:2] + [None] * 4, [None, None] + list(F[2:]),
+                list(F[:2]) + [None] * 4)
+
+    parts = {id(cur): split(cur), id(nxt): split(nxt)}
     t0 = time.perf_counter()
     for s in range(K):
-        api.halo_unpack(g, sim.u, sim.recv)
+        in_yz, in_x = parts[id(cur)][:2]
+        out_yz, out_x = parts[id(nxt)][2:]
+        api.halo_unpack(g, sim.u, in_yz)
         ev[s][0].record()
-        api.step_fused(g, sim.u_prev, sim.u, sim.u_next, sim.vdt2, sim.sponge,
-                       (src, float(w[s])), None)
+        api.step_exchange(g, sim.u_prev, sim.u, sim.u_next, sim.vdt2, sim.sponge,
+                          (src, float(w[s])), in_x, out_x)
         ev[s][1].record()
-        api.halo_pack(g, sim.u_next, sim.send)
+        api.halo_pack(g, sim.u_next, out_yz)
         api.record_receivers(g, sim.u_next, sim.rec_off, traces[s])
         sim.u_prev, sim.u, sim.u_next = sim.u, sim.u_next, sim.u_prev
+        cur, nxt = nxt, cur
         sim.n += 1
+    sim.send, sim.send2 = cur, nxt
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -423,7 +442,9 @@ def main():
     pts = n ** 3
     gpts = pts * K / elapsed / 1e9
     face_pts = 6 * 4 * n * n
-    algo_bytes = 16.0 * pts
+    # the stencil kernel reads u^n, u^{n-1}, vdt2 and the two received x faces once
+    # and writes u^{n+1} and the two sent x faces once
+    algo_bytes = 16.0 * pts + 8.0 * (2 * 4 * n * n)
     achieved = algo_bytes / (avg_ms / 1e3) / 1e9
     path_bytes = 16.0 * pts + 8.0 * face_pts
     finite = bool(torch.isfinite(g.interior(sim.u)).all().item())
@@ -466,7 +487,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "fd_step_fused stencil (stencil_kernel<64,8,4,FWD,sponge,source,early-halo>)",
+            "kernel": "stencil of fd_step_exchange: stencil_kernel<64,8,4,FWD,sponge,source,"
+                      "early-halo,x-exchange> (update + source, x faces received and sent "
+                      "in the same kernel)",
             "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",

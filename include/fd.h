@@ -186,6 +186,26 @@ int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* 
                   const float* vdt2, const fd_sponge* sp, const fd_source* src,
                   float* const face_out[6], void* stream);
 
+/* S3+S4+S5+S1, the whole per-step exchange path (the paper's subdomain step
+ * between two halo exchanges, Sec. 4 and Listing 1): the face halos of u are
+ * read from the receive buffers face_in (halo_unpack layouts; NULL array or
+ * NULL entry: u's own halo on that face), u_next is updated as by fd_step with
+ * the source term of src (may be NULL), and the faces of u_next are written to
+ * face_out (halo_pack layouts; NULL array or entry: skipped).  Bitwise the same
+ * u_next and faces as halo_unpack(u, face_in) + fd_step_fused.  When nx is a
+ * multiple of 64 and all four x-face buffers are given, the x faces are
+ * exchanged inside the stencil kernel (their 16-byte row pieces would otherwise
+ * cost whole cache lines in a separate pack and unpack); the y and z faces,
+ * whole rows and planes, go through the unpack and pack kernels.  On return u's
+ * face halos are unspecified (they may hold the face_in values).  face_in
+ * buffers must not overlap face_out buffers or any volume array (a real
+ * exchange double-buffers them: the loopback passes the faces of the previous
+ * call's face_out); FD_EINVAL otherwise. */
+int fd_step_exchange(const fd_grid* g, const float* u_prev, float* u, float* u_next,
+                     const float* vdt2, const fd_sponge* sp, const fd_source* src,
+                     const float* const face_in[6], float* const face_out[6],
+                     void* stream);
+
 /* S1-S7 for nt steps, the host loop in native code: per step n,
  *   (send given) halo_unpack(u, receive = the opposite face of send),
  *   fd_step_fused(u_prev, u -> u_next, source w[n] at src if wavelet non-NULL),
@@ -194,7 +214,12 @@ int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* 
  *   rotate (u_prev, u, u_next) <- (u, u_next, u_prev).
  * With send set the exchange is the single-device loopback (periodic
  * subdomain); on entry send must hold the faces of u (zeros for a zero
- * start, or what the previous run left).  On return the struct's three
+ * start, or what the previous run left).  With send2 set as well (a second,
+ * distinct set of six buffers) each step is one fd_step_exchange reading the
+ * loopback of send and writing the faces of u_next to send2, and the two sets
+ * swap roles; on return send holds the faces of u (the struct's send and send2
+ * pointers are swapped after an odd number of steps).  Same bits either way.
+ * On return the struct's three
  * pointers are rotated so u_prev, u hold the last two states.  wavelet is a
  * host array of nt floats, read before the call returns; traces is a device
  * array of nt*nrec floats; rec_off device int64 offsets. */
@@ -211,6 +236,7 @@ typedef struct fd_run {
   const int64_t* rec_off;        /* device */
   float* traces;                 /* device, nt*nrec */
   float* send[6];                /* device face buffers, or all NULL (no exchange) */
+  float* send2[6];               /* second face set (one-kernel steps), or all NULL */
 } fd_run;
 int fd_forward_run(const fd_grid* g, fd_run* run, void* stream);
 

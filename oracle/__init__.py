@@ -62,10 +62,16 @@ _ipn = _nullable(_ip)
 
 
 def lib():
+    """The compiled oracle.  ``ORACLE_LIB`` in the environment names another build
+    of it to load instead (the mutation test loads deliberately broken copies)."""
     global _lib
     if _lib is None:
-        build(force=False)
-        L = C.CDLL(_LIB)
+        alt = os.environ.get("ORACLE_LIB")
+        if alt:
+            L = C.CDLL(alt)
+        else:
+            build(force=False)
+            L = C.CDLL(_LIB)
         i32, i64, f64 = C.c_int, C.c_int64, C.c_double
         L.ora_elems.restype = i64
         L.ora_elems.argtypes = [i32, i32, i32]

@@ -48,7 +48,8 @@ class fd_run(C.Structure):
     _fields_ = [("u_prev", C.c_void_p), ("u", C.c_void_p), ("u_next", C.c_void_p),
                 ("vdt2", C.c_void_p), ("sponge", fd_sponge), ("nt", C.c_int32),
                 ("src", C.c_int32 * 3), ("wavelet", C.c_void_p), ("nrec", C.c_int32),
-                ("rec_off", C.c_void_p), ("traces", C.c_void_p), ("send", C.c_void_p * 6)]
+                ("rec_off", C.c_void_p), ("traces", C.c_void_p), ("send", C.c_void_p * 6),
+                ("send2", C.c_void_p * 6)]
 
 
 class FDError(RuntimeError):
@@ -83,6 +84,8 @@ SIGNATURES = {
     "fd_step": (C.c_int, [_G, _P, _P, _P, _P, _S, _P]),
     "fd_step_fused": (C.c_int, [_G, _P, _P, _P, _P, _S, C.POINTER(fd_source), C.POINTER(_P),
                                 _P]),
+    "fd_step_exchange": (C.c_int, [_G, _P, _P, _P, _P, _S, C.POINTER(fd_source),
+                                   C.POINTER(_P), C.POINTER(_P), _P]),
     "fd_forward_run": (C.c_int, [_G, C.POINTER(fd_run), _P]),
     "inject_source": (C.c_int, [_G, _P, _P, _S, _i32, _i32, _i32, _f32, _P]),
     "record_receivers": (C.c_int, [_G, _P, _P, _i32, _P, _P]),

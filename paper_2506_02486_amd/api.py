@@ -167,8 +167,27 @@ def step_fused(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None = None
         sref = C.byref(fd_source(int(i), int(j), int(k), float(w)))
     check(lib().fd_step_fused(grid.ref, u_prev.data_ptr(), u.data_ptr(), u_next.data_ptr(),
                               vdt2.data_ptr(), sponge_ref(sponge), sref,
-                              None if faces is None else _faces(faces), _stream(stream)),
+                              None if faces is None else _faces(faces, grid), _stream(stream)),
           "fd_step_fused")
+
+
+def step_exchange(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None = None, src=None,
+                  face_in=None, face_out=None, stream=None):
+    """The per-step exchange path as one kernel: u's face halos read from the receive
+    buffers ``face_in``, fd_step + source ``src`` = ((i,j,k), w), the faces of u_next
+    written to ``face_out`` (fd_step_exchange)."""
+    for n, t in (("u_prev", u_prev), ("u", u), ("u_next", u_next), ("vdt2", vdt2)):
+        grid.check(t, n)
+    sref = None
+    if src is not None:
+        (i, j, k), w = src
+        sref = C.byref(fd_source(int(i), int(j), int(k), float(w)))
+    check(lib().fd_step_exchange(grid.ref, u_prev.data_ptr(), u.data_ptr(), u_next.data_ptr(),
+                                 vdt2.data_ptr(), sponge_ref(sponge), sref,
+                                 None if face_in is None else _faces(face_in, grid),
+                                 None if face_out is None else _faces(face_out, grid),
+                                 _stream(stream)),
+          "fd_step_exchange")
 
 
 def inject_source(grid: Grid, u_next, vdt2, sponge, ijk, w: float, stream=None):
@@ -189,22 +208,32 @@ def record_receivers(grid: Grid, u, rec_off: torch.Tensor, trace_row: torch.Tens
                                  trace_row.data_ptr(), _stream(stream)), "record_receivers")
 
 
-def _faces(faces):
+def _faces(faces, grid: Grid):
+    """ctypes array of six face pointers; each given face must be a contiguous
+    float32 device tensor of at least that face's element count."""
+    if len(faces) != 6:
+        raise ValueError("expected six face buffers (-x, +x, -y, +y, -z, +z)")
     arr = _lib._FACES()
     for i in range(6):
         f = faces[i]
+        if f is not None:
+            if (not isinstance(f, torch.Tensor) or f.dtype != torch.float32 or not f.is_cuda
+                    or not f.is_contiguous() or f.numel() < grid.face_elems(i)):
+                raise TypeError(f"face {i}: expected a contiguous float32 ROCm tensor of "
+                                f">= {grid.face_elems(i)} elements")
         arr[i] = None if f is None else f.data_ptr()
     return arr
 
 
 def halo_pack(grid: Grid, u, faces, stream=None):
     grid.check(u, "u")
-    check(lib().halo_pack(grid.ref, u.data_ptr(), _faces(faces), _stream(stream)), "halo_pack")
+    check(lib().halo_pack(grid.ref, u.data_ptr(), _faces(faces, grid), _stream(stream)),
+          "halo_pack")
 
 
 def halo_unpack(grid: Grid, u, faces, stream=None):
     grid.check(u, "u")
-    check(lib().halo_unpack(grid.ref, u.data_ptr(), _faces(faces), _stream(stream)),
+    check(lib().halo_unpack(grid.ref, u.data_ptr(), _faces(faces, grid), _stream(stream)),
           "halo_unpack")
 
 
@@ -302,12 +331,15 @@ def set_kchunk(kchunk: int):
 
 def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: int, src=None,
                 wavelet=None, rec_off: torch.Tensor | None = None,
-                traces: torch.Tensor | None = None, send=None, stream=None):
+                traces: torch.Tensor | None = None, send=None, send2=None, stream=None):
     """``nt`` steps in the library's native loop (fd_forward_run): per step unpack of
     ``send`` into the opposite halos (loopback; skipped when ``send`` is None), the
     fused update with the source ``src`` at amplitude ``wavelet[s]``, pack into
-    ``send``, and the receiver row ``traces[s]``.  Returns the rotated
-    ``(u_prev, u, u_next)``: u^{n+nt-1}, u^{n+nt} and the spare array."""
+    ``send``, and the receiver row ``traces[s]``; with ``send2`` (a second face set)
+    each step is one fd_step_exchange and the sets alternate.  Returns the rotated
+    ``(u_prev, u, u_next)``: u^{n+nt-1}, u^{n+nt} and the spare array; with
+    ``send2`` it returns ``(u_prev, u, u_next, send, send2)``, ``send`` holding the
+    faces of the new u."""
     for n, t in (("u_prev", u_prev), ("u", u), ("u_next", u_next), ("vdt2", vdt2)):
         grid.check(t, n)
     r = _lib.fd_run()
@@ -334,10 +366,22 @@ def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: 
         r.rec_off = rec_off.data_ptr()
         r.traces = traces.data_ptr()
     if send is not None:
+        fs = _faces(send, grid)
         for f in range(6):
-            r.send[f] = send[f].data_ptr()
+            r.send[f] = fs[f]
+    if send2 is not None:
+        if send is None:
+            raise ValueError("forward_run: send2 needs send")
+        fs = _faces(send2, grid)
+        for f in range(6):
+            r.send2[f] = fs[f]
     check(lib().fd_forward_run(grid.ref, C.byref(r), _stream(stream)), "fd_forward_run")
-    return bufs[r.u_prev], bufs[r.u], bufs[r.u_next]
+    if send2 is None:
+        return bufs[r.u_prev], bufs[r.u], bufs[r.u_next]
+    swapped = r.send[0] != send[0].data_ptr()
+    if swapped:
+        send, send2 = send2, send
+    return bufs[r.u_prev], bufs[r.u], bufs[r.u_next], send, send2
 
 
 @dataclass
@@ -381,8 +425,10 @@ class Simulation:
         self.exchange = exchange
         if exchange not in (None, "loopback"):
             raise ValueError("exchange must be None or 'loopback'")
+        # two face sets: ``send`` holds the faces of u, ``send2`` receives those of
+        # u_next in the one-kernel step (a real exchange double-buffers likewise)
         self.send = face_buffers(g, device) if exchange else None
-        self.recv = loopback(self.send) if exchange else None
+        self.send2 = face_buffers(g, device) if exchange else None
         self._faces_current = True  # zero state, zero face buffers
         rec = self.geom.rec
         if rec is not None and len(rec):
@@ -394,16 +440,25 @@ class Simulation:
     def nrec(self) -> int:
         return 0 if self.rec_off is None else self.rec_off.numel()
 
+    MODES = ("exchange", "fused", "separate", "native", "native-fused")
+
     def run(self, nt: int, traces: torch.Tensor | None = None, stream=None,
-            fused: bool = True) -> torch.Tensor:
+            mode: str = "exchange") -> torch.Tensor:
         """Advance ``nt`` steps; returns (nt, nrec) device traces (u^{n+1} at receivers).
 
-        ``fused`` (default) runs per step: halo_unpack of the faces packed during the
-        previous step, then one fd_step_fused (update + source + pack of the new
-        field), then record_receivers.  ``fused=False`` issues the separate calls
-        halo_pack, halo_unpack, fd_step, inject_source, record_receivers;
-        ``fused="native"`` runs the fused sequence in the library's own loop
-        (fd_forward_run).  All give the same bits."""
+        Per step, by ``mode``:
+        * ``"exchange"`` (default): one fd_step_exchange (u's face halos read from the
+          loopback of the faces packed by the previous step, update + source, faces
+          of the new field packed into the other face set), then record_receivers;
+        * ``"fused"``: halo_unpack of the faces packed by the previous step, then
+          fd_step_fused (update + source + pack), then record_receivers;
+        * ``"separate"``: halo_pack, halo_unpack, fd_step, inject_source,
+          record_receivers as separate calls;
+        * ``"native"`` / ``"native-fused"``: the exchange / fused sequence looped in
+          the library (fd_forward_run).
+        All give the same bits."""
+        if mode not in self.MODES:
+            raise ValueError(f"mode must be one of {self.MODES}")
         g = self.grid
         if traces is None:
             traces = torch.zeros((nt, max(self.nrec, 1)), dtype=torch.float32, device=self.device)
@@ -411,21 +466,27 @@ class Simulation:
         w = None
         if geom.src is not None:
             w = ricker(nt, self.dt, geom.f0, geom.t0, n0=self.n)
-        if fused and self.exchange and not self._faces_current:
+        if mode != "separate" and self.exchange and not self._faces_current:
             halo_pack(g, self.u, self.send, stream)
-        if fused == "native":
-            return self._run_native(nt, w, traces, stream)
+        if mode.startswith("native"):
+            return self._run_native(nt, w, traces, stream, mode == "native")
         for s in range(nt):
-            if fused:
+            src = None if w is None else (geom.src, float(w[s]))
+            if mode == "exchange":
+                face_in = loopback(self.send) if self.exchange else None
+                step_exchange(g, self.u_prev, self.u, self.u_next, self.vdt2, self.sponge, src,
+                              face_in, self.send2 if self.exchange else None, stream)
                 if self.exchange:
-                    halo_unpack(g, self.u, self.recv, stream)
-                src = None if w is None else (geom.src, float(w[s]))
+                    self.send, self.send2 = self.send2, self.send
+            elif mode == "fused":
+                if self.exchange:
+                    halo_unpack(g, self.u, loopback(self.send), stream)
                 step_fused(g, self.u_prev, self.u, self.u_next, self.vdt2, self.sponge, src,
                            self.send if self.exchange else None, stream)
             else:
                 if self.exchange:
                     halo_pack(g, self.u, self.send, stream)
-                    halo_unpack(g, self.u, self.recv, stream)
+                    halo_unpack(g, self.u, loopback(self.send), stream)
                 step(g, self.u_prev, self.u, self.u_next, self.vdt2, self.sponge, stream)
                 if w is not None:
                     inject_source(g, self.u_next, self.vdt2, self.sponge, geom.src, float(w[s]),
@@ -434,19 +495,23 @@ class Simulation:
                 record_receivers(g, self.u_next, self.rec_off, traces[s], stream)
             self.u_prev, self.u, self.u_next = self.u, self.u_next, self.u_prev
             self.n += 1
-        # after a fused step the send buffers hold the faces of the current u
-        self._faces_current = bool(fused and self.exchange and nt > 0) or (
+        # after a packing step the send buffers hold the faces of the current u
+        self._faces_current = bool(mode != "separate" and self.exchange and nt > 0) or (
             self._faces_current and nt == 0)
         return traces[:, :self.nrec]
 
-    def _run_native(self, nt, w, traces, stream):
-        """The same per-step sequence as the fused path, looped in native code
-        (fd_forward_run)."""
-        self.u_prev, self.u, self.u_next = forward_run(
+    def _run_native(self, nt, w, traces, stream, one_kernel: bool):
+        """The exchange (``one_kernel``) or fused per-step sequence, looped in native
+        code (fd_forward_run)."""
+        out = forward_run(
             self.grid, self.u_prev, self.u, self.u_next, self.vdt2, self.sponge, nt,
             src=self.geom.src if w is not None else None, wavelet=w, rec_off=self.rec_off,
             traces=traces if self.rec_off is not None else None,
-            send=self.send if self.exchange else None, stream=stream)
+            send=self.send if self.exchange else None,
+            send2=self.send2 if self.exchange and one_kernel else None, stream=stream)
+        self.u_prev, self.u, self.u_next = out[:3]
+        if len(out) == 5:
+            self.send, self.send2 = out[3], out[4]
         self.n += nt
         self._faces_current = bool(self.exchange) or self._faces_current
         return traces[:, :self.nrec]

@@ -333,6 +333,98 @@ int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* 
   return check_hip(launch_pack(geo, u_next, face_out, s), "fd_step_fused pack launch");
 }
 
+// Overlap checks of six face buffers against the volume arrays of one call.
+static int faces_clear_of(const fd_grid* g, const float* const face[6], const float* const* vols,
+                          int nvol, const char* who) {
+  for (int f = 0; f < 6; ++f) {
+    const float* fp = face[f];
+    if (!fp) continue;
+    const int64_t n = fd_face_elems(g, f);
+    for (int v = 0; v < nvol; ++v) {
+      const float* a = vols[v];
+      if (a && fp < a + last_elem(g) + 1 && a < fp + n)
+        return fail(FD_EINVAL, "%s: face %d overlaps a volume array", who, f);
+    }
+  }
+  return FD_OK;
+}
+
+static bool face_sets_overlap(const fd_grid* g, const float* const a[6], const float* const b[6]) {
+  for (int f = 0; f < 6; ++f) {
+    if (!a[f]) continue;
+    const int64_t na = fd_face_elems(g, f);
+    for (int h = 0; h < 6; ++h) {
+      if (!b[h]) continue;
+      const int64_t nb = fd_face_elems(g, h);
+      if (a[f] < b[h] + nb && b[h] < a[f] + na) return true;
+    }
+  }
+  return false;
+}
+
+// One step of the exchange form; arguments already checked.
+static hipError_t step_exchange(const Geo& geo, const Coef& c, const float* up, float* u,
+                                float* un, const float* q, const float* ex, const float* ey,
+                                const float* ez, const fd_source* src,
+                                const float* const face_in[6], float* const face_out[6],
+                                hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (exchange_fits(geo) && face_in && face_out && face_in[0] && face_in[1] && face_out[0] &&
+      face_out[1]) {
+    // x faces inside the stencil kernel; y and z faces (whole rows and planes)
+    // by the unpack/pack kernels
+    const float* in_yz[6] = {nullptr, nullptr, face_in[2], face_in[3], face_in[4], face_in[5]};
+    float* out_yz[6] = {nullptr, nullptr, face_out[2], face_out[3], face_out[4], face_out[5]};
+    const float* in_x[2] = {face_in[0], face_in[1]};
+    float* out_x[2] = {face_out[0], face_out[1]};
+    e = launch_unpack(geo, u, in_yz, s);
+    if (e == hipSuccess)
+      e = launch_step_exchange(geo, c, up, u, un, q, ex, ey, ez, src, in_x, out_x, s);
+    if (e == hipSuccess) e = launch_pack(geo, un, out_yz, s);
+    return e;
+  }
+  if (face_in) e = launch_unpack(geo, u, face_in, s);
+  if (e == hipSuccess) e = launch_step(geo, c, up, u, un, q, ex, ey, ez, src, s);
+  if (e == hipSuccess && face_out) e = launch_pack(geo, un, face_out, s);
+  return e;
+}
+
+int fd_step_exchange(const fd_grid* g, const float* u_prev, float* u, float* u_next,
+                     const float* vdt2, const fd_sponge* sp, const fd_source* src,
+                     const float* const face_in[6], float* const face_out[6], void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!u_prev || !u || !u_next || !vdt2) return fail(FD_EINVAL, "fd_step_exchange: NULL array");
+  if (overlaps(g, u, u_next)) return fail(FD_EINVAL, "fd_step_exchange: u_next overlaps u");
+  if (overlaps(g, vdt2, u_next)) return fail(FD_EINVAL, "fd_step_exchange: u_next overlaps vdt2");
+  if (u_next != u_prev && overlaps(g, u_prev, u_next))
+    return fail(FD_EINVAL, "fd_step_exchange: u_next partially overlaps u_prev");
+  if (src && (src->i < 0 || src->i >= g->nx || src->j < 0 || src->j >= g->ny || src->k < 0 ||
+              src->k >= g->nz))
+    return fail(FD_EINVAL, "fd_step_exchange: source outside the interior");
+  const float* vols[4] = {u_prev, u, u_next, vdt2};
+  if (face_in) {
+    rc = check_faces(g, (const void* const*)face_in, "fd_step_exchange");
+    if (rc) return rc;
+    rc = faces_clear_of(g, face_in, vols, 4, "fd_step_exchange (face_in)");
+    if (rc) return rc;
+  }
+  if (face_out) {
+    rc = check_faces(g, (const void* const*)face_out, "fd_step_exchange");
+    if (rc) return rc;
+    rc = faces_clear_of(g, face_out, vols, 4, "fd_step_exchange (face_out)");
+    if (rc) return rc;
+  }
+  if (face_in && face_out && face_sets_overlap(g, face_in, face_out))
+    return fail(FD_EINVAL, "fd_step_exchange: a face_in buffer overlaps a face_out buffer");
+  const float *ex, *ey, *ez;
+  rc = check_sponge(sp, &ex, &ey, &ez);
+  if (rc) return rc;
+  return check_hip(step_exchange(make_geo(g), make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez,
+                                 src, face_in, face_out, as_stream(stream)),
+                   "fd_step_exchange launch");
+}
+
 int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
   int rc = check_grid(g);
   if (rc) return rc;
@@ -349,13 +441,28 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
   if (run->wavelet && (run->src[0] < 0 || run->src[0] >= g->nx || run->src[1] < 0 ||
                        run->src[1] >= g->ny || run->src[2] < 0 || run->src[2] >= g->nz))
     return fail(FD_EINVAL, "fd_forward_run: source outside the interior");
-  int nsend = 0;
-  for (int f = 0; f < 6; ++f) nsend += run->send[f] != nullptr;
-  if (nsend != 0 && nsend != 6)
+  int nsend = 0, nsend2 = 0;
+  for (int f = 0; f < 6; ++f) {
+    nsend += run->send[f] != nullptr;
+    nsend2 += run->send2[f] != nullptr;
+  }
+  if ((nsend != 0 && nsend != 6) || (nsend2 != 0 && nsend2 != 6))
     return fail(FD_EINVAL, "fd_forward_run: give all six face buffers or none");
+  if (nsend2 && !nsend) return fail(FD_EINVAL, "fd_forward_run: send2 needs send");
+  const float* vols[4] = {up, u, un, run->vdt2};
   if (nsend) {
     rc = check_faces(g, (const void* const*)run->send, "fd_forward_run");
     if (rc) return rc;
+    rc = faces_clear_of(g, run->send, vols, 4, "fd_forward_run (send)");
+    if (rc) return rc;
+  }
+  if (nsend2) {
+    rc = check_faces(g, (const void* const*)run->send2, "fd_forward_run");
+    if (rc) return rc;
+    rc = faces_clear_of(g, run->send2, vols, 4, "fd_forward_run (send2)");
+    if (rc) return rc;
+    if (face_sets_overlap(g, run->send, run->send2))
+      return fail(FD_EINVAL, "fd_forward_run: send and send2 overlap");
   }
   const float *ex, *ey, *ez;
   rc = check_sponge(&run->sponge, &ex, &ey, &ez);
@@ -363,11 +470,11 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
   const Geo geo = make_geo(g);
   const Coef c = make_coef(g);
   hipStream_t s = as_stream(stream);
-  const float* recv[6] = {run->send[1], run->send[0], run->send[3],
-                          run->send[2], run->send[5], run->send[4]};
+  float** cur = run->send;   // faces of u
+  float** nxt = run->send2;  // ping-pong: faces of u_next
   for (int32_t n = 0; n < run->nt; ++n) {
     hipError_t e = hipSuccess;
-    if (nsend) e = launch_unpack(geo, u, recv, s);
+    const float* recv[6] = {cur[1], cur[0], cur[3], cur[2], cur[5], cur[4]};
     fd_source src;
     if (run->wavelet) {
       src.i = run->src[0];
@@ -375,9 +482,17 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
       src.k = run->src[2];
       src.w = run->wavelet[n];
     }
-    if (e == hipSuccess)
-      e = launch_step(geo, c, up, u, un, run->vdt2, ex, ey, ez, run->wavelet ? &src : nullptr, s);
-    if (e == hipSuccess && nsend) e = launch_pack(geo, un, run->send, s);
+    const fd_source* sp_src = run->wavelet ? &src : nullptr;
+    if (nsend2) {
+      e = step_exchange(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, recv, nxt, s);
+      float** t = cur;
+      cur = nxt;
+      nxt = t;
+    } else {
+      if (nsend) e = launch_unpack(geo, u, recv, s);
+      if (e == hipSuccess) e = launch_step(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, s);
+      if (e == hipSuccess && nsend) e = launch_pack(geo, un, cur, s);
+    }
     if (e == hipSuccess && run->nrec)
       e = launch_record(un, run->rec_off, run->nrec, run->traces + (int64_t)n * run->nrec, s);
     if (e != hipSuccess) {
@@ -394,6 +509,8 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
   run->u_prev = up;
   run->u = u;
   run->u_next = un;
+  if (cur != run->send)  // ping-pong: run->send holds the faces of the final u
+    for (int f = 0; f < 6; ++f) std::swap(run->send[f], run->send2[f]);
   return FD_OK;
 }
 
@@ -428,6 +545,8 @@ static int check_faces(const fd_grid* g, const void* const* face, const char* wh
   const int n3[3] = {g->nx, g->ny, g->nz};
   for (int f = 0; f < 6; ++f) {
     if (!face[f]) continue;
+    if (reinterpret_cast<uintptr_t>(face[f]) & 3)
+      return fail(FD_EINVAL, "%s: face %d is not 4-byte aligned", who, f);
     if (n3[f / 2] < 4)
       return fail(FD_EINVAL, "%s: face %d needs at least 4 interior planes on its axis", who, f);
     if (fd_face_elems(g, f) > (int64_t)std::numeric_limits<int32_t>::max())

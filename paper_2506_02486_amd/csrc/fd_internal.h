@@ -93,6 +93,16 @@ hipError_t launch_vmax_view(int nx, int ny, int nz, const float* v, long long vs
 // dst[i] = 0 for i < n
 hipError_t launch_zero(float* dst, long long n, hipStream_t s);
 
+// The forward step with the x faces exchanged inside the stencil kernel: u's
+// x-face halos are read from rin[0] (-x) and rin[1] (+x) (halo_unpack layout
+// [nz][ny][4]), the x faces of un are written to sout[0], sout[1] (halo_pack
+// layout), the source is added when src is given.  All four buffers non-NULL;
+// only where exchange_fits (nx a multiple of the tile width).
+bool exchange_fits(const Geo& g);
+hipError_t launch_step_exchange(const Geo& g, const Coef& c, const float* up, const float* u,
+                                float* un, const float* q, const float* ex, const float* ey,
+                                const float* ez, const fd_source* src, const float* const rin[2],
+                                float* const sout[2], hipStream_t s);
 hipError_t launch_adjoint(const Geo& g, const Coef& c, const float* ann, const float* an1,
                           float* aout, const float* q, const float* ex, const float* ey,
                           const float* ez, hipStream_t s);

@@ -56,6 +56,11 @@ struct Params {
   int tiles_x, tiles_y, kchunk;
   int si, sj, sk;   // source point (si < 0: none): FWD adds its term, GRAD its f
   float sw;         // source amplitude
+  // exchange form (XCH): the x-face halos of f are read from rin[0], rin[1]
+  // instead of f's own halo, and the x faces of out are written to sout[0],
+  // sout[1] (halo_unpack / halo_pack layouts [nz][ny][4]; all four non-NULL)
+  const float* rin[2];
+  float* sout[2];
 };
 
 __device__ __forceinline__ int remap_block(int bid, int nb) {
@@ -79,7 +84,7 @@ __device__ __forceinline__ float ld_nt(const char* base, unsigned boff) {
 
 // The per-block work of every stencil kernel: tile (bx, by) of the x-y plane,
 // z-chunk bz, of the grid and operands described by p.
-template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY>
+template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY, bool XCH>
 __device__ __forceinline__ void stencil_block(const Params& p, const int bx, const int by,
                                               const int bz) {
   constexpr int TX = TXT;
@@ -90,10 +95,13 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
   static_assert(NY == 1 || NY == 2 || NY == 4 || NY == 8, "NY must divide 8");
   static_assert(8 * RY <= TXT, "x-halo cells must fit in one thread row");
   static_assert(!EARLY || MODE == FWD, "the halo ring needs the unrolled forward z loop");
+  static_assert(!XCH || EARLY, "the exchange form is a forward kernel");
+
   __shared__ float sm[2][LY * LX];
 
   const int lane = threadIdx.x;
-  const int w = threadIdx.y;
+  // a wave is one thread row when TXT is a multiple of 64: w is wave-uniform
+  const int w = TXT % 64 == 0 ? __builtin_amdgcn_readfirstlane((int)threadIdx.y) : (int)threadIdx.y;
   const int nx = p.g.nx, ny = p.g.ny, nz = p.g.nz;
   const int sy = p.g.sy;
   const long long szb = 4LL * p.g.sz;  // plane stride in bytes
@@ -196,6 +204,36 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
       return ld(fk, b);
     }
   };
+  // XCH: the x-face halos come from the receive buffers and the x faces of the
+  // result go to the send buffers.  Both are 16-byte pieces of rows whose cache
+  // lines otherwise hold interior points, so a separate pack/unpack, and the
+  // stencil's own x-halo loads, fetch and write whole lines for them; here each
+  // lane keeps a pointer and a per-plane step for its x-halo cell (interior
+  // tiles: u itself) and edge lanes a pointer into the x face they own.  nx is a
+  // multiple of TX, so only lanes hx_c < 4 of the first tile column and hx_c >= 4
+  // of the last read x halos; rows hx_y >= ny of a ragged last tile row are
+  // corner cells no point uses, left on u's halo (in bounds).
+  const char* hxp = F0 + hxb;
+  unsigned hxs = (unsigned)szb;
+  float* sx_ptr = nullptr;
+  bool xedge = false;  // block-uniform: the tile holds x-face points
+  if (XCH) {
+    if (hx_on && hx_y < ny && hx_c < 4 && bx == 0) {
+      hxp = reinterpret_cast<const char*>(p.rin[0]) + 4ull * ((unsigned)hx_y * 4u + (unsigned)hx_c);
+      hxs = 16u * (unsigned)ny;
+    } else if (hx_on && hx_y < ny && hx_c >= 4 && x0 + TX == nx) {
+      hxp = reinterpret_cast<const char*>(p.rin[1]) +
+            4ull * ((unsigned)hx_y * 4u + (unsigned)(hx_c - 4));
+      hxs = 16u * (unsigned)ny;
+    }
+    if (x < 4) sx_ptr = p.sout[0] + x;
+    else if (x >= nx - 4) sx_ptr = p.sout[1] + (x - (nx - 4));
+    xedge = bx == 0 || x0 + TX == nx;
+  }
+  auto xload = [&](int k) -> float {
+    return hx_ld ? *reinterpret_cast<const float*>(hxp + (unsigned long long)k * hxs) : 0.f;
+  };
+
   auto ezw = [&](int k) -> float {
     if (!SPONGE) return 0.f;
     if (MODE == ADJ) return p.ez[wrapi(k, nz)];
@@ -230,8 +268,9 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
       const int k = kb - 4 + s;
       const char* fk = F0 + (long long)k * szb;
 #pragma unroll
-      for (int h = 0; h < HPT; ++h) hq[s][h] = k < ke ? fld(fk, fk, hyb[h], hy_ld[h], 0.f, 0.f, 0.f) : 0.f;
-      xq[s] = k < ke ? fld(fk, fk, hxb, hx_ld, 0.f, 0.f, 0.f) : 0.f;
+      for (int h = 0; h < HPT; ++h)
+        hq[s][h] = k < ke ? fld(fk, fk, hyb[h], hy_ld[h], 0.f, 0.f, 0.f) : 0.f;
+      xq[s] = k < ke ? (XCH ? xload(k) : fld(fk, fk, hxb, hx_ld, 0.f, 0.f, 0.f)) : 0.f;
     }
   } else {
     const float ezv = ezw(kb);
@@ -294,8 +333,9 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
       if (kn < ke) {
         const char* fk = F0 + (long long)kn * szb;
 #pragma unroll
-        for (int h = 0; h < HPT; ++h) nhy[h] = fld(fk, fk, hyb[h], hy_ld[h], 0.f, 0.f, 0.f);
-        nhx = fld(fk, fk, hxb, hx_ld, 0.f, 0.f, 0.f);
+        for (int h = 0; h < HPT; ++h)
+          nhy[h] = fld(fk, fk, hyb[h], hy_ld[h], 0.f, 0.f, 0.f);
+        nhx = XCH ? xload(kn) : fld(fk, fk, hxb, hx_ld, 0.f, 0.f, 0.f);
       }
     } else if (more) {
       const float ezv = ezw(k + 1);
@@ -372,6 +412,7 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
             if (x == p.si && yr + r == p.sj) v += pb[r] * p.sw / (1.f + eta);
           }
           __builtin_nontemporal_store(v, dst);
+          if (XCH && xedge && sx_ptr) sx_ptr[((unsigned)k * (unsigned)ny + (unsigned)(yr + r)) * 4u] = v;
         } else if (MODE == ADJ) {
           const float c = cq[0][r];
           float v;
@@ -447,13 +488,14 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
   }
 }
 
-template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY = (MODE == FWD)>
+template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY = (MODE == FWD),
+          bool XCH = false>
 __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
   const int logical = remap_block(blockIdx.x, gridDim.x);
   const int bx = logical % p.tiles_x;
   const int rest = logical / p.tiles_x;
-  stencil_block<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY>(p, bx, rest % p.tiles_y,
-                                                        rest / p.tiles_y);
+  stencil_block<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY, XCH>(p, bx, rest % p.tiles_y,
+                                                             rest / p.tiles_y);
 }
 
 // Many grids in one launch: block b runs tile tiles[remap(b)] = (slot, bx, by, bz)
@@ -484,7 +526,7 @@ __global__ void __launch_bounds__(TXT * NY) batched_kernel(const BatchShot* __re
   p.sj = b.sj;
   p.sk = b.sk;
   p.sw = a.w[t.x];
-  stencil_block<TXT, NY, RY, FWD, true, true, true>(p, t.y, t.z, t.w);
+  stencil_block<TXT, NY, RY, FWD, true, true, true, false>(p, t.y, t.z, t.w);
 }
 
 struct LaunchShape {
@@ -502,16 +544,14 @@ LaunchShape shape_for(const Geo& g, int tx, int ty, int waves_per_block) {
   if (g_kchunk_override > 0) {
     kc = g_kchunk_override;
   } else {
-    // aim at about 4096 waves (16 per CU on 256 CUs) while keeping the z halo
-    // re-read (8 planes per chunk) small: chunks of at least 32 planes, unless the
-    // grid is so small that 32-plane chunks leave the chip mostly idle (its
-    // arrays then sit in cache, and the z-halo re-read costs no HBM traffic)
+    // aim at about 4096 waves (16 per CU on 256 CUs: every block resident at
+    // once) with chunks as long as that allows, so the z-halo re-read (8 planes
+    // per chunk) stays small; chunks of at least 4 planes
     const long long target = 4096 / waves_per_block;
     long long chunks = (target + tiles - 1) / tiles;
     if (chunks < 1) chunks = 1;
     kc = (int)((g.nz + chunks - 1) / chunks);
-    const int kmin = tiles * ((g.nz + 31) / 32) >= 512 / waves_per_block ? 32 : 4;
-    if (kc < kmin) kc = kmin;
+    if (kc < 4) kc = 4;
   }
   if (kc > g.nz) kc = g.nz;
   s.kchunk = kc;
@@ -520,7 +560,7 @@ LaunchShape shape_for(const Geo& g, int tx, int ty, int waves_per_block) {
 }
 
 template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE = false,
-          bool EARLY = (MODE == FWD)>
+          bool EARLY = (MODE == FWD), bool XCH = false>
 hipError_t launch_mode(Params p, hipStream_t st) {
   const LaunchShape sh = shape_for(p.g, TXT, NY * RY, (TXT * NY + 63) / 64);
   p.tiles_x = sh.tiles_x;
@@ -528,7 +568,7 @@ hipError_t launch_mode(Params p, hipStream_t st) {
   p.kchunk = sh.kchunk;
   const long long nb = (long long)sh.tiles_x * sh.tiles_y * sh.zchunks;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((stencil_kernel<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY>), dim3((unsigned)nb),
+  hipLaunchKernelGGL((stencil_kernel<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY, XCH>), dim3((unsigned)nb),
                      dim3(TXT, NY), 0, st, p);
   return hipGetLastError();
 }
@@ -593,6 +633,34 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
   }
   if (ex) return launch_mode<FWD_SHAPE, FWD, true>(p, s);
   return launch_mode<FWD_SHAPE, FWD, false>(p, s);
+}
+
+bool exchange_fits(const Geo& g) { return g.nx % BATCH_TX == 0; }
+
+hipError_t launch_step_exchange(const Geo& g, const Coef& c, const float* up, const float* u,
+                                float* un, const float* q, const float* ex, const float* ey,
+                                const float* ez, const fd_source* src, const float* const rin[2],
+                                float* const sout[2], hipStream_t s) {
+  if (!exchange_fits(g)) return hipErrorInvalidValue;
+  Params p = base_params(g, c, ex, ey, ez);
+  p.f = u;
+  p.fq = u;
+  p.pa = up;
+  p.pb = q;
+  p.out = un;
+  if (src) {
+    p.si = src->i;
+    p.sj = src->j;
+    p.sk = src->k;
+    p.sw = src->w;
+  }
+  if (!rin[0] || !rin[1] || !sout[0] || !sout[1]) return hipErrorInvalidValue;
+  for (int f = 0; f < 2; ++f) {
+    p.rin[f] = rin[f];
+    p.sout[f] = sout[f];
+  }
+  if (ex) return launch_mode<FWD_SHAPE, FWD, true, true, true, true>(p, s);
+  return launch_mode<FWD_SHAPE, FWD, false, true, true, true>(p, s);
 }
 
 hipError_t launch_adjoint(const Geo& g, const Coef& c, const float* ann, const float* an1,

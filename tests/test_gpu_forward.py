@@ -18,6 +18,16 @@ api = pytest.importorskip("paper_2506_02486_amd.api")
 D10 = (10.0, 10.0, 10.0)
 
 
+def _random_state(g, seed):
+    """(u_prev, u) padded device arrays with random interiors and zero halos."""
+    out = []
+    for s in (seed, seed + 1):
+        t = g.zeros()
+        g.interior(t).copy_(torch.from_numpy(random_field((g.nz, g.ny, g.nx), s)))
+        out.append(t)
+    return out
+
+
 def rel_l2(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -324,30 +334,71 @@ def test_full_size_512_energy_is_conserved_across_the_periodic_wrap():
     assert float(g.interior(sim.u)[n // 2, n // 2, n // 2]) == 0.0
 
 
-@pytest.mark.parametrize("shape,width", [((100, 37, 45), 6), ((64, 64, 64), 16), ((9, 70, 5), 2)])
-def test_fused_step_matches_separate_calls_bitwise(shape, width):
-    """fd_step_fused (update + source + face pack) against halo_pack, halo_unpack,
-    fd_step and inject_source issued separately, and against the native loop
-    fd_forward_run: same traces, fields and faces."""
+@pytest.mark.parametrize("shape,width", [((100, 37, 45), 6), ((64, 64, 64), 16), ((9, 70, 5), 2),
+                                         ((64, 32, 37), 5), ((128, 96, 4), 3), ((192, 64, 9), 4),
+                                         ((64, 37, 11), 4), ((128, 5, 4), 1)])
+def test_step_modes_match_bitwise(shape, width):
+    """fd_step_exchange (x faces inside the stencil kernel where nx % 64 == 0, else
+    unpack, step and pack launches), fd_step_fused after halo_unpack, the separate
+    calls halo_pack, halo_unpack, fd_step, inject_source, and the native loops of the
+    exchange and fused forms: the same traces, fields and faces, bit for bit."""
     nx, ny, nz = shape
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
     src = (1, ny // 2, nz // 2)  # inside the x sponge
     geom = api.Geometry(src=src, rec=receivers_xline(nx, ny // 3, nz // 2))
     runs = []
-    for fused in (True, False, "native"):
+    for mode in api.Simulation.MODES:
         sim = api.Simulation(v, sponge_width=width, exchange="loopback", geom=geom)
-        tr = sim.run(37, fused=fused)
-        tr2 = sim.run(4, fused=fused)
+        tr = sim.run(37, mode=mode)
+        tr2 = sim.run(4, mode=mode)
         runs.append((torch.cat([tr, tr2]), sim.state()[0].clone(), sim.state()[1].clone()))
-        if fused is True:
-            faces = [f.clone() for f in sim.send]
+        if mode != "separate":  # the send buffers hold the faces of the current u
             ref = api.face_buffers(sim.grid)
             api.halo_pack(sim.grid, sim.u, ref)
-            for a, b in zip(faces, ref):
-                assert torch.equal(a, b)
-    for other in runs[1:]:
+            for a, b in zip(sim.send, ref):
+                assert torch.equal(a, b), mode
+    for mode, other in zip(api.Simulation.MODES[1:], runs[1:]):
         for a, b in zip(runs[0], other):
-            assert torch.equal(a, b)
+            assert torch.equal(a, b), mode
+
+
+def test_exchange_step_reads_only_the_receive_buffers():
+    """With face_in given, the one-kernel step does not read u's face halos: garbage
+    there changes nothing; and a NULL face_in entry falls back to u's own halo."""
+    nx, ny, nz = 64, 32, 20
+    v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
+    sim = api.Simulation(v, sponge_width=3, exchange="loopback")
+    g = sim.grid
+    up, u = _random_state(g, 31)
+    faces = api.face_buffers(g)
+    api.halo_pack(g, u, faces)
+    recv = api.loopback(faces)
+    out1, out2 = g.zeros(), g.zeros()
+    api.step_exchange(g, up, u, out1, sim.vdt2, sim.sponge, None, recv, None)
+    ref = g.zeros()
+    u_ref = u.clone()
+    api.halo_unpack(g, u_ref, recv)
+    api.step(g, up, u_ref, ref, sim.vdt2, sim.sponge)
+    assert torch.equal(g.interior(out1), g.interior(ref))
+    # poison u's halo (interior kept): the result does not change
+    P = g.padded(u)
+    keep = g.interior(u).clone()
+    P.fill_(float("nan"))
+    g.interior(u).copy_(keep)
+    api.step_exchange(g, up, u, out2, sim.vdt2, sim.sponge, None, recv, None)
+    assert torch.equal(g.interior(out2), g.interior(ref))
+    # a NULL entry reads u's own halo on that face: with u's halo poisoned (again:
+    # the call above may have left the received values in it) the -z
+    # neighbourhood (k < 4) turns NaN and nothing else does
+    P.fill_(float("nan"))
+    g.interior(u).copy_(keep)
+    recv_nz = list(recv)
+    recv_nz[4] = None
+    out3 = g.zeros()
+    api.step_exchange(g, up, u, out3, sim.vdt2, sim.sponge, None, recv_nz, None)
+    I3 = g.interior(out3)
+    assert torch.isnan(I3[:4]).all()
+    assert torch.equal(I3[4:], g.interior(ref)[4:])
 
 
 def test_large_subdomain_sampled_parity():

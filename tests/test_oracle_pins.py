@@ -385,19 +385,21 @@ def test_sponge_profile_closed_form(ora):
 @pytest.mark.parametrize("periodic", [False, True])
 def test_step_points_equals_one_full_step(ora, periodic):
     """The point-sampled step (used for full-size sampled parity) reproduces a whole
-    oracle step exactly, including wrapped or zero neighbours and the source."""
+    oracle step exactly, including wrapped or zero neighbours and the source, on a
+    grid with three different spacings."""
     nx, ny, nz = 15, 11, 9
+    d = (10.0, 12.5, 8.0)
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=2.0)
-    dt = ora.cfl_dt(v, 10.0)
-    eta = ora.sponge_tables(nx, ny, nz, 3, float(v.max()), (10.0,) * 3, dt)
+    dt = ora.cfl_dt(v, min(d))
+    eta = ora.sponge_tables(nx, ny, nz, 3, float(v.max()), d, dt)
     up = random_field((nz, ny, nx), 1)
     u = random_field((nz, ny, nx), 2)
     src = (3, 4, 5)
     w = np.array([0.7])
-    _, _, full = ora.forward(v, 1, dt, src=src, w=w, eta=eta, periodic=periodic,
+    _, _, full = ora.forward(v, 1, dt, d=d, src=src, w=w, eta=eta, periodic=periodic,
                              state=(up.astype(np.float64), u.astype(np.float64)))
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     pts = np.stack([i.ravel(), j.ravel(), k.ravel()], 1).astype(np.int32)
-    got = ora.step_points(up, u, ora.vdt2(v, dt), pts, eta=eta, periodic=periodic,
+    got = ora.step_points(up, u, ora.vdt2(v, dt), pts, d=d, eta=eta, periodic=periodic,
                           src=src, w_src=0.7).reshape(full.shape)
     assert np.array_equal(got, full)
