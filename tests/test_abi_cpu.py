@@ -117,6 +117,54 @@ def test_step_argument_checks(L):
     assert L.fd_cfl_dt(C.byref(g), a, 0.4, None, None, None, None) == EINVAL
 
 
+def test_exchange_and_scaled_adjoint_argument_checks(L):
+    EINVAL = _lib.FD_EINVAL
+    g = grid(L)
+    n = L.fd_grid_elems(C.byref(g)) * 4
+    a, b, c, q, u, gg = (FAKE + i * 4 * n for i in range(6))
+    base = FAKE + 8 * 4 * n
+    fe = [L.fd_face_elems(C.byref(g), f) * 4 for f in range(6)]
+    offs = np.concatenate([[0], np.cumsum(fe)])
+    fin = (C.c_void_p * 6)(*[int(base + o) for o in offs[:6]])
+    fout = (C.c_void_p * 6)(*[int(base + offs[6] + o) for o in offs[:6]])
+    step = L.fd_step_exchange
+    assert step(C.byref(g), a, b, None, q, None, None, fin, fout, None) == EINVAL   # NULL u_next
+    assert step(C.byref(g), a, b, b, q, None, None, fin, fout, None) == EINVAL      # u_next == u
+    src = _lib.fd_source(64, 0, 0, 1.0)
+    assert step(C.byref(g), a, b, c, q, None, C.byref(src), fin, fout, None) == EINVAL
+    # a face buffer inside a volume array
+    bad = (C.c_void_p * 6)(*fin)
+    bad[2] = b + 64
+    assert step(C.byref(g), a, b, c, q, None, None, bad, fout, None) == EINVAL
+    # receive and send sets overlapping
+    assert step(C.byref(g), a, b, c, q, None, None, fin, fin, None) == EINVAL
+    # a misaligned face pointer
+    bad = (C.c_void_p * 6)(*fout)
+    bad[0] = int(bad[0]) + 2
+    assert step(C.byref(g), a, b, c, q, None, None, fin, bad, None) == EINVAL
+    assert b"aligned" in L.fd_last_error()
+    # native loop: a second face set needs the first, and must be distinct from it
+    r = _lib.fd_run()
+    r.u_prev, r.u, r.u_next, r.vdt2, r.nt = a, b, c, q, 1
+    for f in range(6):
+        r.send2[f] = fout[f]
+    assert L.fd_forward_run(C.byref(g), C.byref(r), None) == EINVAL
+    for f in range(6):
+        r.send[f] = fout[f]
+    assert L.fd_forward_run(C.byref(g), C.byref(r), None) == EINVAL
+    # scaled adjoint
+    sa = L.fd_adjoint_step_scaled
+    assert sa(C.byref(g), None, b, c, q, None, None, None, None, None) == EINVAL    # b_nn required
+    assert sa(C.byref(g), a, b, b, q, None, None, None, None, None) == EINVAL       # b_out == b_n1
+    assert sa(C.byref(g), a, b, c, q, None, None, gg, None, None) == EINVAL         # no u_n
+    assert sa(C.byref(g), a, b, c, q, None, u, q, None, None) == EINVAL            # g_b == vdt2
+    assert L.fd_scatter_add_scaled(C.byref(g), a, FAKE, FAKE, None, None, 3, None) == EINVAL
+    assert L.fd_scatter_add_scaled(C.byref(g), a, FAKE, FAKE, q, None, -1, None) == EINVAL
+    assert L.fd_scatter_add_scaled(C.byref(g), a, FAKE, FAKE, q, None, 0, None) == 0
+    assert L.fd_grad_finalize_scaled(C.byref(g), a, b, 0.0, c, None) == EINVAL
+    assert L.fd_grad_finalize_scaled(C.byref(g), a, b, 1e-3, b, None) == EINVAL  # grad_m == vdt2
+
+
 def test_halo_and_adjoint_argument_checks(L):
     EINVAL = _lib.FD_EINVAL
     small = grid(L, 3, 8, 8)
