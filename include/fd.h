@@ -354,8 +354,10 @@ typedef struct fd_shot_desc {
   double sponge_vmax;        /* velocity the sponge is designed for; <= 0: the
                                 shot's own max(v)                                  */
   const float* v_dev;        /* caller-owned device velocity view: point (i,j,k)
-                                at v_dev[k*v_zstride + j*v_ystride + i]; must stay
-                                valid and unchanged until the shot is done        */
+                                at v_dev[k*v_zstride + j*v_ystride + i]; fully
+                                written before shot_submit (the server reads it
+                                on a stream of its own) and unchanged until the
+                                shot is done                                       */
   int64_t v_ystride, v_zstride;
   int32_t nrec;              /* receivers, >= 0                                    */
   const int32_t* rec_ijk_host; /* 3*nrec (i,j,k) triples, copied at submit        */
@@ -369,7 +371,10 @@ int64_t fd_shot_footprint(const fd_shot_desc* d);
  * arena_dev + arena_bytes) (256-byte aligned; about 1.1 MB of it holds the
  * server's tables), running at most max_slots (1..64) shots at once.
  * compute_stream / copy_stream are hipStream_t (NULL: the server creates
- * its own).  The arena must outlive the server.  Starts the progress thread. */
+ * its own); the server also creates one stream of its own for admission work
+ * (zeroing, model preparation, sponge and receiver uploads), so admitting a shot never waits
+ * for the steps queued on the compute stream.  The arena must outlive the
+ * server.  Starts the progress thread. */
 int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t max_slots,
                      void* compute_stream, void* copy_stream);
 /* Queue a shot.  FD_EINVAL for a bad descriptor (sizes, source or receiver

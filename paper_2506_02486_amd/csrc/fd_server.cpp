@@ -4,9 +4,10 @@
 //   admit   : strict FIFO; the head shot enters when a slot is free and a
 //             first-fit search of the arena finds its footprint.  Admission
 //             zeroes its wavefields, reduces max(v) (checking stability),
-//             builds vdt2 from the caller's velocity view, uploads sponge
-//             tables and receiver offsets, and writes the shot's entry of
-//             the device slot table.
+//             builds vdt2 from the caller's velocity view and uploads sponge
+//             tables and receiver offsets, all on the server's own admission
+//             stream (its host waits never drain the steps queued on the
+//             compute stream), then writes the shot's entry of the slot table.
 //   step    : one batched stencil launch over the tile table of all active
 //             shots (each at its own step n, its source amplitude w[n] passed
 //             by value), then one batched receiver launch.
@@ -145,20 +146,25 @@ struct Server {
   int max_slots = 0;
   int device = 0;
   hipStream_t cs = nullptr, xs = nullptr;
+  hipStream_t as = nullptr;  // admission work (always the server's own)
   bool own_cs = false, own_xs = false;
   std::unique_ptr<Arena> arena;
-  // device tables (head of the arena) and pinned staging copies
+  // device tables (head of the arena), the host master slot table and two
+  // pinned staging sets used in turn, so that rebuilding the tables never waits
+  // for the copy of the previous upload
   BatchShot* d_shots = nullptr;
   int4* d_tiles = nullptr;
   int* d_slots = nullptr;
   int32_t* d_scratch = nullptr;
-  BatchShot* h_shots = nullptr;
-  int4* h_tiles = nullptr;
-  int* h_slots = nullptr;
+  std::vector<BatchShot> shots_host;
+  BatchShot* h_shots[2] = {};
+  int4* h_tiles[2] = {};
+  int* h_slots[2] = {};
+  hipEvent_t table_ev[2] = {};
+  int stage = 0;
   int32_t* h_scratch = nullptr;
   float* h_stage = nullptr;   // sponge and receiver upload staging
   size_t h_stage_cap = 0;
-  hipEvent_t table_ev = nullptr;
   hipEvent_t step_ev[kInflight] = {};
   int ntiles = 0, nactive = 0, max_nrec = 0;
   bool table_dirty = false;
@@ -215,12 +221,12 @@ int admit_device(Server* S, Shot* s, int slot) {
   float* tr = reinterpret_cast<float*>(blk + L.traces);
   const Geo geo = make_geo(&L.g);
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_zero(vol[i], L.elems, S->cs);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_zero(vol[i], L.elems, S->as);
   if (e == hipSuccess)
-    e = launch_vmax_view(d.nx, d.ny, d.nz, d.v_dev, d.v_ystride, d.v_zstride, S->d_scratch, S->cs);
+    e = launch_vmax_view(d.nx, d.ny, d.nz, d.v_dev, d.v_ystride, d.v_zstride, S->d_scratch, S->as);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(S->h_scratch, S->d_scratch, 8, hipMemcpyDeviceToHost, S->cs);
-  if (e == hipSuccess) e = hipStreamSynchronize(S->cs);
+    e = hipMemcpyAsync(S->h_scratch, S->d_scratch, 8, hipMemcpyDeviceToHost, S->as);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->as);
   if (e != hipSuccess) return check_hip(e, "shot admission");
   float vmax, vmin;
   memcpy(&vmax, &S->h_scratch[0], 4);
@@ -231,7 +237,7 @@ int admit_device(Server* S, Shot* s, int slot) {
   if ((double)vmax * d.dt * sqrt(symbol_at_nyquist() * inv2) > 2.0)
     return fail(FD_EINVAL, "shot %lld: dt %g is unstable for max(v) %g", (long long)s->id, d.dt,
                 (double)vmax);
-  e = launch_prepare_vdt2_view(geo, d.v_dev, d.v_ystride, d.v_zstride, vol[3], d.dt, S->cs);
+  e = launch_prepare_vdt2_view(geo, d.v_dev, d.v_ystride, d.v_zstride, vol[3], d.dt, S->as);
   if (e != hipSuccess) return check_hip(e, "shot vdt2");
   // sponge tables and receiver offsets through the pinned staging buffer
   const size_t need = (size_t)(d.nx + d.ny + d.nz) + 2 + 2 * (size_t)std::max(d.nrec, 1);
@@ -254,15 +260,14 @@ int admit_device(Server* S, Shot* s, int slot) {
   int64_t* hrec = reinterpret_cast<int64_t*>(S->h_stage + (d.nx + d.ny + d.nz + 1) / 2 * 2);
   if (d.nrec > 0) fd_receiver_offsets(&L.g, s->rec.data(), d.nrec, hrec);
   e = hipMemcpyAsync(sp, S->h_stage, 4 * (size_t)(d.nx + d.ny + d.nz), hipMemcpyHostToDevice,
-                     S->cs);
+                     S->as);
   if (e == hipSuccess && d.nrec > 0)
-    e = hipMemcpyAsync(rec, hrec, 8 * (size_t)d.nrec, hipMemcpyHostToDevice, S->cs);
-  if (e == hipSuccess) e = hipStreamSynchronize(S->cs);  // the staging buffer is reused
+    e = hipMemcpyAsync(rec, hrec, 8 * (size_t)d.nrec, hipMemcpyHostToDevice, S->as);
+  // the staging buffer is reused, and the compute stream may use the shot from
+  // its next step on: all of the shot's admission work has finished after this
+  if (e == hipSuccess) e = hipStreamSynchronize(S->as);
   if (e != hipSuccess) return check_hip(e, "shot upload");
-  // slot-table entry (the staging copy of the last table upload must have landed)
-  e = hipEventSynchronize(S->table_ev);
-  if (e != hipSuccess) return check_hip(e, "shot table");
-  BatchShot& b = S->h_shots[slot];
+  BatchShot& b = S->shots_host[slot];
   b.g = geo;
   b.c = make_coef(&L.g);
   for (int i = 0; i < 3; ++i) b.arr[i] = vol[i];
@@ -285,32 +290,37 @@ int admit_device(Server* S, Shot* s, int slot) {
 
 // Rebuild and upload the tile table, slot list and slot table.
 hipError_t upload_tables(Server* S) {
-  hipError_t e = hipEventSynchronize(S->table_ev);  // previous upload consumed the staging
+  const int st = S->stage ^= 1;
+  // the upload before the previous one used this staging set; it has landed
+  hipError_t e = hipEventSynchronize(S->table_ev[st]);
   if (e != hipSuccess) return e;
+  int4* h_tiles = S->h_tiles[st];
+  int* h_slots = S->h_slots[st];
+  memcpy(S->h_shots[st], S->shots_host.data(), sizeof(BatchShot) * S->max_slots);
   int nt = 0, na = 0, mr = 0;
   int tx, ty;
   batch_tile_shape(&tx, &ty);
   for (int slot = 0; slot < S->max_slots; ++slot) {
     Shot* s = S->slots[slot];
     if (!s) continue;
-    S->h_slots[na++] = slot;
+    h_slots[na++] = slot;
     mr = std::max(mr, s->d.nrec);
     const int bxn = (s->d.nx + tx - 1) / tx, byn = (s->d.ny + ty - 1) / ty;
     const int bzn = (s->d.nz + kServeKchunk - 1) / kServeKchunk;
     for (int bz = 0; bz < bzn; ++bz)
       for (int by = 0; by < byn; ++by)
-        for (int bx = 0; bx < bxn; ++bx) S->h_tiles[nt++] = make_int4(slot, bx, by, bz);
+        for (int bx = 0; bx < bxn; ++bx) h_tiles[nt++] = make_int4(slot, bx, by, bz);
   }
   S->ntiles = nt;
   S->nactive = na;
   S->max_nrec = mr;
-  e = hipMemcpyAsync(S->d_shots, S->h_shots, sizeof(BatchShot) * S->max_slots,
+  e = hipMemcpyAsync(S->d_shots, S->h_shots[st], sizeof(BatchShot) * S->max_slots,
                      hipMemcpyHostToDevice, S->cs);
   if (e == hipSuccess && nt)
-    e = hipMemcpyAsync(S->d_tiles, S->h_tiles, sizeof(int4) * nt, hipMemcpyHostToDevice, S->cs);
+    e = hipMemcpyAsync(S->d_tiles, h_tiles, sizeof(int4) * nt, hipMemcpyHostToDevice, S->cs);
   if (e == hipSuccess && na)
-    e = hipMemcpyAsync(S->d_slots, S->h_slots, sizeof(int) * na, hipMemcpyHostToDevice, S->cs);
-  if (e == hipSuccess) e = hipEventRecord(S->table_ev, S->cs);
+    e = hipMemcpyAsync(S->d_slots, h_slots, sizeof(int) * na, hipMemcpyHostToDevice, S->cs);
+  if (e == hipSuccess) e = hipEventRecord(S->table_ev[st], S->cs);
   S->table_dirty = false;
   return e;
 }
@@ -553,17 +563,21 @@ int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t ma
     e = hipStreamCreateWithFlags(&S->xs, hipStreamNonBlocking);
     S->own_xs = e == hipSuccess;
   }
-  if (e == hipSuccess)
-    e = hipHostMalloc((void**)&S->h_shots, sizeof(BatchShot) * MAX_BATCH_SLOTS, hipHostMallocDefault);
-  if (e == hipSuccess)
-    e = hipHostMalloc((void**)&S->h_tiles, sizeof(int4) * kTileCap, hipHostMallocDefault);
-  if (e == hipSuccess)
-    e = hipHostMalloc((void**)&S->h_slots, sizeof(int) * MAX_BATCH_SLOTS, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->as, hipStreamNonBlocking);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipHostMalloc((void**)&S->h_shots[i], sizeof(BatchShot) * MAX_BATCH_SLOTS,
+                      hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&S->h_tiles[i], sizeof(int4) * kTileCap, hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&S->h_slots[i], sizeof(int) * MAX_BATCH_SLOTS,
+                        hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->table_ev[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(S->table_ev[i], S->cs);
+  }
   if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_scratch, 8, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->table_ev, hipEventDisableTiming);
   for (int i = 0; i < kInflight && e == hipSuccess; ++i)
     e = hipEventCreateWithFlags(&S->step_ev[i], hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(S->table_ev, S->cs);
   if (e != hipSuccess) {
     rc = check_hip(e, "fd_server_create");
     Server* raw = S.release();
@@ -571,7 +585,7 @@ int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t ma
     fd_server_destroy(raw);
     return rc;
   }
-  memset(S->h_shots, 0, sizeof(BatchShot) * MAX_BATCH_SLOTS);
+  S->shots_host.assign(MAX_BATCH_SLOTS, BatchShot{});
   Server* raw = S.release();
   raw->th = std::thread(progress, raw);
   *srv = raw;
@@ -667,15 +681,18 @@ int fd_server_destroy(void* srv) {
   for (auto& kv : S->shots) give_pinned(S, kv.second->host, kv.second->host_cap);
   for (auto& pb : S->pinned_pool) hipHostFree(pb.second);
   if (S->h_stage) hipHostFree(S->h_stage);
-  if (S->h_shots) hipHostFree(S->h_shots);
-  if (S->h_tiles) hipHostFree(S->h_tiles);
-  if (S->h_slots) hipHostFree(S->h_slots);
+  for (int i = 0; i < 2; ++i) {
+    if (S->h_shots[i]) hipHostFree(S->h_shots[i]);
+    if (S->h_tiles[i]) hipHostFree(S->h_tiles[i]);
+    if (S->h_slots[i]) hipHostFree(S->h_slots[i]);
+    if (S->table_ev[i]) hipEventDestroy(S->table_ev[i]);
+  }
   if (S->h_scratch) hipHostFree(S->h_scratch);
-  if (S->table_ev) hipEventDestroy(S->table_ev);
   for (int i = 0; i < kInflight; ++i)
     if (S->step_ev[i]) hipEventDestroy(S->step_ev[i]);
   if (S->own_cs) hipStreamDestroy(S->cs);
   if (S->own_xs) hipStreamDestroy(S->xs);
+  if (S->as) hipStreamDestroy(S->as);
   delete S;
   return FD_OK;
 }
