@@ -338,12 +338,17 @@ def fwi_bench(n=256, nt=1000, every=32):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     pts = n ** 3
-    # forward 16 B/pt/step, recompute 16, adjoint 16 + gradient 16
-    algo = (16.0 + 16.0 + 32.0) * pts * nt
-    return {"workload": f"FWI gradient {n}^3, {nt} steps, checkpoints every {every}, sponge 16",
-            "seconds_per_gradient": round(el, 4), "misfit": J,
-            "effective_GBps": round(algo / el / 1e9, 1),
-            "finite": bool(torch.isfinite(g).all().item())}
+    # forward 16 B/pt/step, recompute 16 (none when every state is kept), adjoint 16 +
+    # gradient 16
+    algo = (16.0 + (16.0 if every else 0.0) + 32.0) * pts * nt
+    what = f"checkpoints every {every}" if every else "every state kept in HBM"
+    out = {"workload": f"FWI gradient {n}^3, {nt} steps, {what}, sponge 16",
+           "seconds_per_gradient": round(el, 4), "misfit": J,
+           "effective_GBps": round(algo / el / 1e9, 1),
+           "finite": bool(torch.isfinite(g).all().item())}
+    del prob, g, m0, mt, obs
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -519,6 +524,8 @@ def main():
         out["large"] = large_bench()
     if args.fwi:
         out["fwi"] = fwi_bench()
+        # the same gradient keeping all 1000 states in HBM (89 GB): no recompute
+        out["fwi_all_states"] = fwi_bench(every=0)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline ({args.cpu_steps} steps of {n}^3)")
         out["cpu_baseline"] = cpu_baseline(v, out["_dt"], src, args.cpu_steps)

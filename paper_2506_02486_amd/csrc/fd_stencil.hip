@@ -31,6 +31,9 @@
 // with eta == 0 compute the same expression on both paths.
 // Blocks are renumbered so that each of the 8 XCDs (each with its own L2) gets
 // one contiguous run of tiles: hardware dispatches block b to XCD b % 8.
+// Exchange form (XCH, fd_step_exchange): the -x/+x halos are read from receive
+// buffers and the x faces of the result written to send buffers by the lanes
+// that own them, instead of a separate unpack/pack over 16-byte row pieces.
 #include <type_traits>
 
 #include "fd_internal.h"

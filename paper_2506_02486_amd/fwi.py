@@ -47,9 +47,11 @@ class FWIProblem:
         self.nt = int(nt)
         self.src = tuple(int(x) for x in src)
         self.device = device
+        # checkpoint_every = 0 keeps every state u^0 .. u^{nt-1} (nt volumes: 89 GB
+        # at 256^3 and 1000 steps fits one MI355X's 288 GB) and skips the recompute
         self.C = int(checkpoint_every)
-        if self.C < 1:
-            raise ValueError("checkpoint_every must be >= 1")
+        if self.C < 0:
+            raise ValueError("checkpoint_every must be >= 0 (0: keep every state)")
         if sponge_width > 0:
             if sponge_vmax is None:
                 raise ValueError("a sponge needs the (fixed) vmax it is designed for")
@@ -63,6 +65,7 @@ class FWIProblem:
         self.m = g.zeros(device)
         self.vdt2 = g.zeros(device)
         self.ckpt: list[tuple[torch.Tensor, torch.Tensor]] = []
+        self.states: list[torch.Tensor] = []
 
     # ------------------------------------------------------------ forward
     def set_model(self, m_interior: torch.Tensor):
@@ -78,13 +81,36 @@ class FWIProblem:
         up, u, un = g.zeros(self.device), g.zeros(self.device), g.zeros(self.device)
         traces = torch.zeros((self.nt, self.nrec), dtype=torch.float32, device=self.device)
         self.ckpt = []
-        for s in range(0, self.nt, self.C):  # one native loop per checkpoint interval
-            e = min(s + self.C, self.nt)
+        if checkpoints and self.C == 0:
+            return self._forward_store_all(traces)
+        self.states = []
+        step = self.C if self.C > 0 else self.nt
+        for s in range(0, self.nt, step):  # one native loop per checkpoint interval
+            e = min(s + step, self.nt)
             if checkpoints:
                 self.ckpt.append((up.clone(), u.clone()))
             up, u, un = api.forward_run(g, up, u, un, self.vdt2, self.sponge, e - s,
                                         src=self.src, wavelet=self.w[s:e],
                                         rec_off=self.rec_off, traces=traces[s:e])
+        return traces
+
+    def _forward_store_all(self, traces: torch.Tensor) -> torch.Tensor:
+        """Forward sweep writing u^{n+1} of step n into its own buffer: states[n] is
+        u^n for n < nt (states[0] = u^0 = 0); u^{nt} lands in a spare buffer."""
+        g = self.grid
+        if len(self.states) != self.nt + 2:
+            self.states = []
+            torch.cuda.empty_cache()
+            self.states = [g.zeros(self.device) for _ in range(self.nt + 2)]
+        else:
+            self.states[0].zero_()
+            self.states[-1].zero_()
+        zero = self.states[-1]  # u^{-1}
+        for n in range(self.nt):
+            up = zero if n == 0 else self.states[n - 1]
+            api.step_fused(g, up, self.states[n], self.states[n + 1], self.vdt2, self.sponge,
+                           (self.src, float(self.w[n])))
+            api.record_receivers(g, self.states[n + 1], self.rec_off, traces[n])
         return traces
 
     # ------------------------------------------------------------ adjoint
@@ -101,7 +127,7 @@ class FWIProblem:
             raise ValueError("want_grad_w goes with scaled=True, want_lambda_src with False")
         g = self.grid
         nt, C = self.nt, self.C
-        if not self.ckpt:
+        if not self.ckpt and not (C == 0 and self.states):
             raise RuntimeError("backward needs a forward run with checkpoints")
         res = res.to(device=self.device, dtype=torch.float32).contiguous()
         if res.shape != (nt, self.nrec):
@@ -112,10 +138,10 @@ class FWIProblem:
         B = g.zeros(self.device)  # lambda^{n+1}
         api.scatter_add(g, B, self.rec_off, res[nt - 1])
         gq = g.zeros(self.device)
-        seg = [g.zeros(self.device) for _ in range(min(C, nt))]
+        seg = self._segment_buffers()
         lam_src = torch.zeros(nt, dtype=torch.float32, device=self.device) if want_lambda_src else None
-        for j in range(len(self.ckpt) - 1, -1, -1):
-            s, e = self._recompute(j, seg)
+        for j in range(self._segments() - 1, -1, -1):
+            s, e, seg = self._recompute(j, seg)
             for n in range(e - 1, s - 1, -1):
                 if lam_src is not None:
                     api.record_receivers(g, B, self.src_off, lam_src[n:n + 1])
@@ -131,8 +157,19 @@ class FWIProblem:
             return out, lam_src
         return out
 
-    def _recompute(self, j: int, seg: list[torch.Tensor]) -> tuple[int, int]:
-        """u^s .. u^{e-1} of segment j into seg[0 .. e-s-1] from its checkpoint."""
+    def _segments(self) -> int:
+        return 1 if self.C == 0 else len(self.ckpt)
+
+    def _segment_buffers(self) -> list[torch.Tensor]:
+        if self.C == 0:
+            return []
+        return [self.grid.zeros(self.device) for _ in range(min(self.C, self.nt))]
+
+    def _recompute(self, j: int, seg: list[torch.Tensor]):
+        """(s, e, buffers) with buffers[i] = u^{s+i} for segment j: the stored states,
+        or u^s .. u^{e-1} recomputed into ``seg`` from the segment's checkpoint."""
+        if self.C == 0:
+            return 0, self.nt, self.states
         g, C = self.grid, self.C
         s = j * C
         e = min(s + C, self.nt)
@@ -144,7 +181,7 @@ class FWIProblem:
             api.step_fused(g, before, seg[i], seg[i + 1], self.vdt2, self.sponge,
                            (self.src, float(self.w[n])))
             before = seg[i]
-        return s, e
+        return s, e, seg
 
     def _backward_scaled(self, res: torch.Tensor, want_grad_w: bool):
         g, nt = self.grid, self.nt
@@ -152,10 +189,10 @@ class FWIProblem:
         B = g.zeros(self.device)  # b^{n+1}
         api.scatter_add_scaled(g, B, self.rec_off, res[nt - 1], self.vdt2, self.sponge)
         gb = g.zeros(self.device)
-        seg = [g.zeros(self.device) for _ in range(min(self.C, nt))]
+        seg = self._segment_buffers()
         grad_w = torch.zeros(nt, dtype=torch.float32, device=self.device) if want_grad_w else None
-        for j in range(len(self.ckpt) - 1, -1, -1):
-            s, e = self._recompute(j, seg)
+        for j in range(self._segments() - 1, -1, -1):
+            s, e, seg = self._recompute(j, seg)
             for n in range(e - 1, s - 1, -1):
                 if grad_w is not None:
                     api.record_receivers(g, B, self.src_off, grad_w[n:n + 1])
