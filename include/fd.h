@@ -28,7 +28,8 @@
  * Conventions.
  *   - Pointers named *_dev or documented as "device" are device pointers
  *     owned by the caller; the library never frees or retains them.  The
- *     stepping calls (fd_step ... fd_grad_finalize) never allocate.
+ *     stepping calls (fd_step through fd_grad_finalize_scaled below) never
+ *     allocate.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls enqueue work on it and return without synchronising, except
  *     where a call says it synchronises.
@@ -222,7 +223,8 @@ int fd_step_exchange(const fd_grid* g, const float* u_prev, float* u, float* u_n
  * On return the struct's three
  * pointers are rotated so u_prev, u hold the last two states.  wavelet is a
  * host array of nt floats, read before the call returns; traces is a device
- * array of nt*nrec floats; rec_off device int64 offsets. */
+ * array of nt*nrec floats (may be NULL when nt == 0); rec_off device int64
+ * offsets. */
 typedef struct fd_run {
   float* u_prev;
   float* u;

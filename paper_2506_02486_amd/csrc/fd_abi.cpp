@@ -119,7 +119,7 @@ const char* fd_strerror(int code) {
 
 const char* fd_last_error(void) { return t_err; }
 
-int fd_version(void) { return 10000; }
+int fd_version(void) { return 10100; }
 
 int fd_grid_init(fd_grid* g, int32_t nx, int32_t ny, int32_t nz, double dx, double dy,
                  double dz) {
@@ -436,7 +436,7 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
   if (overlaps(g, run->vdt2, up) || overlaps(g, run->vdt2, u) || overlaps(g, run->vdt2, un))
     return fail(FD_EINVAL, "fd_forward_run: vdt2 overlaps a wavefield");
   if (run->nt < 0) return fail(FD_EINVAL, "fd_forward_run: nt < 0");
-  if (run->nrec < 0 || (run->nrec > 0 && (!run->rec_off || !run->traces)))
+  if (run->nrec < 0 || (run->nrec > 0 && run->nt > 0 && (!run->rec_off || !run->traces)))
     return fail(FD_EINVAL, "fd_forward_run: bad receivers");
   if (run->wavelet && (run->src[0] < 0 || run->src[0] >= g->nx || run->src[1] < 0 ||
                        run->src[1] >= g->ny || run->src[2] < 0 || run->src[2] >= g->nz))

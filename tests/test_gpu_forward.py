@@ -155,6 +155,28 @@ def test_degenerate_small_grids(shape):
     assert rel_l2(tr, tr_o) <= 1e-5
 
 
+@pytest.mark.parametrize("mode", ["exchange", "fused", "separate", "native", "native-fused"])
+def test_empty_runs_and_no_receivers(mode):
+    """nt = 0 changes nothing and returns no trace rows; a model without receivers
+    or source steps and returns an empty trace table."""
+    nx, ny, nz = 64, 32, 9
+    v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
+    src = (5, 6, 4)
+    sim = api.Simulation(v, sponge_width=3, exchange="loopback",
+                         geom=api.Geometry(src=src, rec=np.array([src], np.int32)))
+    sim.run(5, mode=mode)
+    before = [t.clone() for t in sim.state()]
+    tr = sim.run(0, mode=mode)
+    assert tr.shape[0] == 0
+    for a, b in zip(before, sim.state()):
+        assert torch.equal(a, b)
+    assert sim.n == 5
+    bare = api.Simulation(v, exchange="loopback")
+    tr = bare.run(3, mode=mode)
+    assert tr.shape == (3, 0)
+    assert not torch.any(bare.state()[1])  # no source: the zero state stays zero
+
+
 def test_in_place_two_array_stepping_matches_three_arrays():
     n = 40
     v = layered_velocity(n, n, n, seed=1)
