@@ -145,9 +145,12 @@ bool vec4_ok(const Geo& g, const void* u, const void* const* face) {
 __global__ void inject_kernel(float* un, const float* q, const float* ex, const float* ey,
                               const float* ez, long long o, int i, int j, int k, float w) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  float eta = 0.f;
-  if (ex) eta = ex[i] + ey[j] + ez[k];
-  un[o] += q[o] * w / (1.f + eta);
+  {
+#pragma clang fp contract(off)  // rounds as the source term fused into the stencil
+    float eta = 0.f;
+    if (ex) eta = ex[i] + ey[j] + ez[k];
+    un[o] += q[o] * w / (1.f + eta);
+  }
 }
 
 __global__ void __launch_bounds__(BS) record_kernel(const float* __restrict__ u,

@@ -412,6 +412,9 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
           float v = 2.f * uc - pa[r] + pb[r] * lap;
           if (damped) v = (v + eta * pa[r]) * __builtin_amdgcn_rcpf(1.f + eta);
           if (FUSE && src_plane) {
+            // no contraction: the product, quotient and sum round exactly as in
+            // inject_source, whether or not eta is known to be 0 here
+#pragma clang fp contract(off)
             if (x == p.si && yr + r == p.sj) v += pb[r] * p.sw / (1.f + eta);
           }
           __builtin_nontemporal_store(v, dst);

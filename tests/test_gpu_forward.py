@@ -358,7 +358,8 @@ def test_full_size_512_energy_is_conserved_across_the_periodic_wrap():
 
 @pytest.mark.parametrize("shape,width", [((100, 37, 45), 6), ((64, 64, 64), 16), ((9, 70, 5), 2),
                                          ((64, 32, 37), 5), ((128, 96, 4), 3), ((192, 64, 9), 4),
-                                         ((64, 37, 11), 4), ((128, 5, 4), 1)])
+                                         ((64, 37, 11), 4), ((128, 5, 4), 1), ((64, 32, 48), 0),
+                                         ((30, 20, 12), 0)])
 def test_step_modes_match_bitwise(shape, width):
     """fd_step_exchange (x faces inside the stencil kernel where nx % 64 == 0, else
     unpack, step and pack launches), fd_step_fused after halo_unpack, the separate
@@ -382,6 +383,47 @@ def test_step_modes_match_bitwise(shape, width):
     for mode, other in zip(api.Simulation.MODES[1:], runs[1:]):
         for a, b in zip(runs[0], other):
             assert torch.equal(a, b), mode
+
+
+@pytest.mark.parametrize("use_exchange_call", [False, True])
+def test_two_subdomains_exchanging_faces_equal_one_domain(use_exchange_call):
+    """Domain decomposition on one device: a periodic 64 x 32 x 48 domain split into
+    two z slabs of 24 planes, each slab exchanging its z faces with the other (the
+    -z halo of one receives the +z face of the other) and its x/y faces with itself,
+    reproduces the undivided domain bit for bit after 30 steps -- the exchange a
+    slab decomposition over several GPUs would run, with the puts replaced by
+    passing the other slab's send buffers."""
+    nx, ny, nz, nt = 64, 32, 48, 30
+    v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
+    src = (10, 11, 5)
+    whole = api.Simulation(v, exchange="loopback", geom=api.Geometry(src=src))
+    whole.run(nt, mode="separate")
+    dt = whole.dt
+    w = api.ricker(nt, dt)  # the wavelet the undivided run used
+    slabs = [api.Simulation(v[:24], dt=dt), api.Simulation(v[24:], dt=dt)]
+    g = slabs[0].grid
+    send = [[api.face_buffers(g) for _ in range(2)] for _ in range(2)]  # [slab][set]
+    for n in range(nt):
+        cur, nxt = n % 2, (n + 1) % 2
+        if n == 0:
+            for i in range(2):
+                api.halo_pack(g, slabs[i].u, send[i][cur])
+        recv = []
+        for i in range(2):
+            own, other = send[i][cur], send[1 - i][cur]
+            recv.append([own[1], own[0], own[3], own[2], other[5], other[4]])
+        for i, sl in enumerate(slabs):
+            s = (src, float(w[n])) if i == 0 else None
+            if use_exchange_call:
+                api.step_exchange(g, sl.u_prev, sl.u, sl.u_next, sl.vdt2, None, s, recv[i],
+                                  send[i][nxt])
+            else:
+                api.halo_unpack(g, sl.u, recv[i])
+                api.step_fused(g, sl.u_prev, sl.u, sl.u_next, sl.vdt2, None, s, send[i][nxt])
+            sl.u_prev, sl.u, sl.u_next = sl.u, sl.u_next, sl.u_prev
+    got = torch.cat([sl.state()[1] for sl in slabs], dim=0)
+    assert torch.equal(got, whole.state()[1])
+    assert float(got.abs().max()) > 0
 
 
 def test_exchange_step_reads_only_the_receive_buffers():
