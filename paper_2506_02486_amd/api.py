@@ -200,10 +200,10 @@ def inject_source(grid: Grid, u_next, vdt2, sponge, ijk, w: float, stream=None):
 
 def record_receivers(grid: Grid, u, rec_off: torch.Tensor, trace_row: torch.Tensor,
                      stream=None):
+    """trace_row[r] = u[rec_off[r]]: rec_off from ``Grid.offsets`` (interior points)."""
     grid.check(u, "u")
     n = rec_off.numel()
-    if rec_off.dtype != torch.int64 or trace_row.dtype != torch.float32 or trace_row.numel() < n:
-        raise TypeError("record_receivers: rec_off int64, trace_row float32 of >= nrec")
+    _check_points("record_receivers", rec_off, trace_row)
     check(lib().record_receivers(grid.ref, u.data_ptr(), rec_off.data_ptr(), n,
                                  trace_row.data_ptr(), _stream(stream)), "record_receivers")
 
