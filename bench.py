@@ -102,6 +102,14 @@ def cpu_baseline(v, dt, src, steps):
     per_step_1 = per_step_s(1)
     oracle.set_threads(cores)
     del q
+    # the 64^3 parity configuration (layered model, Dirichlet, 100 steps) in full
+    from workloads import center_source as _cs, layered_velocity, receivers_plane
+    v64 = layered_velocity(64, 64, 64, seed=1)
+    dt64 = oracle.cfl_dt(v64, 10.0)
+    t0 = time.perf_counter()
+    oracle.forward(v64, 100, dt64, src=_cs(64, 64, 64), w=oracle.ricker(100, dt64),
+                   rec=receivers_plane(64, 64, 0))
+    t64 = time.perf_counter() - t0
     return {
         "value": round(n ** 3 / per_step / 1e9, 5),
         "unit": "Gpts/s",
@@ -111,6 +119,7 @@ def cpu_baseline(v, dt, src, steps):
                   f"(time of {steps + 1} steps minus 1 step, set-up excluded); "
                   f"{per_step:.3f} s/step",
         "one_core_Gpts_per_s": round(n ** 3 / per_step_1 / 1e9, 5),
+        "config_64cubed_100_steps_Gpts_per_s": round(64 ** 3 * 100 / t64 / 1e9, 5),
         "host_cpu": host_cpu(),
         "host_nproc": os.cpu_count(),
     }
