@@ -381,7 +381,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this library runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding of the subdomain is not built.", file=sys.stderr)
         sys.exit(2)
 

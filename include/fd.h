@@ -3,10 +3,10 @@
  * (libfd.so, HIP for gfx950).
  *
  * What it computes.  The acoustic isotropic wave-propagation kernel that the
- * paper evaluates as its real-world application (Sec. 4.5, Minimod: a
- * finite-difference discretised wave equation with a high-order stencil, run
- * on 1200^3 grids for 1000 steps), on ONE device's subdomain, together with
- * the pack and unpack of the subdomain's boundary planes that the paper's
+ * paper evaluates as its real-world application (Sec. 4.5: the Minimod proxy
+ * application, seismic wave propagation by finite differences with a wide
+ * stencil, run on 1200^3 grids for 1000 steps), on ONE device's subdomain,
+ * together with the pack and unpack of the subdomain's boundary planes that the paper's
  * halo exchange moves between neighbouring ranks with one-sided puts and a
  * fence (Listing 1).  The paper does not state the stencil; this library uses
  *   - 8th order in space: per axis the 9-point central second difference

@@ -6,12 +6,12 @@
  * baseline leg of the benchmark may load this library.  It shares no code,
  * header, table or helper with the HIP path and includes nothing from it.
  *
- * The paper fixes only "high-order stencil computation" for the acoustic
- * isotropic kernel (Sec. 4.5) and a halo exchange over neighbouring ranks
- * (Listing 1).  Every numerical choice below is the reading stated in the
- * design notes: 8th-order central second differences in each axis (a 25-point
- * star), second-order leapfrog in time, an optional damping sponge, a Ricker
- * source added after the update and receivers sampling the updated field.
+ * For the acoustic isotropic kernel the paper gives only that its stencil is of
+ * high order (Sec. 4.5) and that halos are exchanged with neighbouring ranks
+ * (Listing 1).  Every numerical choice below is therefore a reading: 8th-order
+ * central second differences in each axis (a 25-point star), second-order
+ * leapfrog in time, an optional damping sponge, a Ricker source added after
+ * the update and receivers sampling the updated field.
  *
  * Layout of every volume here: FP64, halo H = 4 on each face, x fastest,
  * (nz+8) x (ny+8) x (nx+8) elements, interior point (i,j,k) at

@@ -117,7 +117,7 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build the HIP library first "
-                "(python -c 'import __graft_entry__ as g; g.build()')")
+                "(python paper_2506_02486_amd/build.py)")
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
