@@ -526,7 +526,9 @@ def main():
     del sim, traces
     torch.cuda.empty_cache()
     if not args.no_serving:
-        out["serving"] = serving_bench(nshots=args.shots)
+        out["serving"] = serving_bench(nshots=args.shots)  # throughput: arrivals at 2x
+        # latency: arrivals at half the plain loop's service rate, a quarter of the shots
+        out["serving_latency"] = serving_bench(nshots=max(16, args.shots // 4), load=0.5)
     if not args.no_small:
         out["small"] = small_bench()
     if args.large:
