@@ -137,7 +137,7 @@ def host_cpu() -> str:
 
 
 def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.0,
-                  warm=16, load=2.0):
+                  warm=16, load=2.0, caps=(16_000_000,)):
     """Poisson stream of shots of uneven size: the batching server against the plain
     per-shot loop (same kernels, one shot at a time, arrival order)."""
     import threading
@@ -190,57 +190,67 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
     del plain
     torch.cuda.empty_cache()
 
-    # --- batching server
-    log("serving: batching server")
-    srv = serving.ShotServer(int(arena_gb * (1 << 30)), max_slots=max_slots)
-    ids = [None] * nshots
-    t_arr = [0] * nshots
-
-    def submitter():
-        b = time.monotonic()
-        for i, s in enumerate(shots):
-            wait = b + arr[i] - time.monotonic()
-            if wait > 0:
-                time.sleep(wait)
-            t_arr[i] = time.monotonic_ns()
-            ids[i] = srv.submit(s)
-
-    th = threading.Thread(target=submitter)
-    th.start()
-    res = [None] * nshots
-    pending = set(range(nshots))
-    while pending:
-        for i in list(pending):
-            if ids[i] is None:
-                continue
-            r = srv.poll(ids[i])
-            if r is not None:
-                res[i] = r
-                pending.discard(i)
-        time.sleep(2e-4)
-    th.join()
-    steps = srv.stats()["steps"]
-    srv.close()
-    codes = [r[0] for r in res]
-    lat_s = [(r[2][2] - t_arr[i]) / 1e9 for i, r in enumerate(res)]
-    span_s = (max(r[2][2] for r in res) - min(t_arr)) / 1e9
-    same = all(np.array_equal(res[i][1], plain_tr[i]) for i in plain_tr)
+    # --- batching server, once per admission policy
     pct = lambda x, q: round(float(np.percentile(np.array(x), q)), 4)  # noqa: E731
-    return {
+
+    def run_server(cap):
+        log(f"serving: batching server (max_active_points {cap})")
+        srv = serving.ShotServer(int(arena_gb * (1 << 30)), max_slots=max_slots,
+                                 max_active_points=cap)
+        ids = [None] * nshots
+        t_arr = [0] * nshots
+
+        def submitter():
+            b = time.monotonic()
+            for i, s in enumerate(shots):
+                wait = b + arr[i] - time.monotonic()
+                if wait > 0:
+                    time.sleep(wait)
+                t_arr[i] = time.monotonic_ns()
+                ids[i] = srv.submit(s)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        res = [None] * nshots
+        pending = set(range(nshots))
+        while pending:
+            for i in list(pending):
+                if ids[i] is None:
+                    continue
+                r = srv.poll(ids[i])
+                if r is not None:
+                    res[i] = r
+                    pending.discard(i)
+            time.sleep(2e-4)
+        th.join()
+        steps = srv.stats()["steps"]
+        srv.close()
+        lat_s = [(r[2][2] - t_arr[i]) / 1e9 for i, r in enumerate(res)]
+        span_s = (max(r[2][2] for r in res) - min(t_arr)) / 1e9
+        return {"max_active_points": cap,
+                "shots_per_s": round(nshots / span_s, 3), "p50_s": pct(lat_s, 50),
+                "p99_s": pct(lat_s, 99), "Gpts_per_s": round(pts / span_s / 1e9, 2),
+                "speedup_shots_per_s": round(span_p / span_s, 3),
+                "batched_steps": steps, "all_ok": all(r[0] == 0 for r in res),
+                "traces_bitwise_equal_first8": all(np.array_equal(res[i][1], plain_tr[i])
+                                                   for i in plain_tr)}
+
+    out = {
         "workload": f"{nshots} shots, grids uniform in [{lo},{hi}]^3 (seed 3), {nt} steps, "
                     f"sponge 16, Ricker 15 Hz, x-line receivers, Poisson arrivals at "
                     f"{load:g}x the plain loop's service rate (seed 4)",
         "arrival_rate": round(lam, 3),
-        "server": {"shots_per_s": round(nshots / span_s, 3), "p50_s": pct(lat_s, 50),
-                   "p99_s": pct(lat_s, 99), "Gpts_per_s": round(pts / span_s / 1e9, 2),
-                   "batched_steps": steps, "all_ok": all(c == 0 for c in codes)},
         "plain_loop": {"shots_per_s": round(nshots / span_p, 3), "p50_s": pct(lat_p, 50),
                        "p99_s": pct(lat_p, 99), "Gpts_per_s": round(pts / span_p / 1e9, 2)},
-        "speedup_shots_per_s": round(span_p / span_s, 3),
-        "traces_bitwise_equal_first8": bool(same),
         "max_slots": max_slots,
         "arena_GB": arena_gb,
     }
+    # "server": admission by slots and memory only; "server_capped": also waits while
+    # the running shots hold `cap` points (about what fills the device alone)
+    out["server"] = run_server(0)
+    for cap in caps:
+        out["server_capped"] = run_server(cap)
+    return out
 
 
 def small_bench(steps=100, repeats=5):
@@ -529,6 +539,8 @@ def main():
         out["serving"] = serving_bench(nshots=args.shots)  # throughput: arrivals at 2x
         # latency: arrivals at half the plain loop's service rate, a quarter of the shots
         out["serving_latency"] = serving_bench(nshots=max(16, args.shots // 4), load=0.5)
+        # small shots, which leave the device part idle when run one at a time
+        out["serving_small"] = serving_bench(nshots=args.shots, lo=48, hi=128, caps=())
     if not args.no_small:
         out["small"] = small_bench()
     if args.large:

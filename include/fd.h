@@ -120,6 +120,13 @@ int64_t fd_offset(const fd_grid* g, int32_t i, int32_t j, int32_t k);
  * depend on it. */
 int fd_set_kchunk(int32_t kchunk);
 
+/* Launch shape of the forward stencil kernel (fd_step, fd_step_fused,
+ * fd_step_exchange) over g, as the next such call would use it: out[0..3] =
+ * x tiles, y tiles, z planes per block, z chunks (blocks = their product; a
+ * tile is 64 x 32 points).  Host only, no device call; FD_EINVAL for a bad
+ * grid or NULL out. */
+int fd_step_launch(const fd_grid* g, int32_t out[4]);
+
 /* ----------------------------------------------------------- model prep
  * (set-up, step S0; not on the per-step path) */
 
@@ -392,6 +399,13 @@ int shot_submit(void* srv, const fd_shot_desc* d, int64_t* shot_id);
  * FD_EDEVICE or FD_ECANCELED.  FD_ENOTFOUND for an unknown or already
  * collected id.  Thread-safe. */
 int shot_poll(void* srv, int64_t shot_id, float* traces_host, size_t cap, int64_t t_ns[3]);
+/* Admission control: the next queued shot (FIFO) is admitted only while the
+ * running shots hold fewer than max_active_points interior points (0, the
+ * default: no limit besides slots, arena and tile table).  A shot is always
+ * admitted when none runs.  Fewer shots at once finish each sooner once they
+ * fill the device; more keep small shots from leaving it idle.  FD_EINVAL for
+ * a NULL server or a negative limit.  Thread-safe. */
+int fd_server_set_admission(void* srv, int64_t max_active_points);
 /* Counts of queued, running, finished-but-uncollected shots, and batched
  * steps launched so far (4 int64).  Thread-safe. */
 int fd_server_stats(void* srv, int64_t out[4]);

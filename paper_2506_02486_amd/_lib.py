@@ -74,6 +74,7 @@ SIGNATURES = {
     "fd_face_elems": (_i64, [_G, _i32]),
     "fd_offset": (_i64, [_G, _i32, _i32, _i32]),
     "fd_set_kchunk": (C.c_int, [_i32]),
+    "fd_step_launch": (C.c_int, [_G, C.POINTER(C.c_int32)]),
     "fd_cfl_dt": (C.c_int, [_G, _P, _f64, _P, C.POINTER(_f64), C.POINTER(_f64), _P]),
     "fd_prepare_vdt2": (C.c_int, [_G, _P, _P, _f64, _P]),
     "fd_prepare_vdt2_m": (C.c_int, [_G, _P, _P, _f64, _P]),
@@ -102,6 +103,7 @@ SIGNATURES = {
     "fd_server_create": (C.c_int, [C.POINTER(_P), _P, C.c_size_t, _i32, _P, _P]),
     "shot_submit": (C.c_int, [_P, C.POINTER(fd_shot_desc), C.POINTER(_i64)]),
     "shot_poll": (C.c_int, [_P, _i64, _P, C.c_size_t, C.POINTER(_i64)]),
+    "fd_server_set_admission": (C.c_int, [_P, _i64]),
     "fd_server_stats": (C.c_int, [_P, C.POINTER(_i64)]),
     "fd_server_shutdown": (C.c_int, [_P]),
     "fd_server_destroy": (C.c_int, [_P]),

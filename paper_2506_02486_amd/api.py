@@ -327,6 +327,14 @@ def set_kchunk(kchunk: int):
     check(lib().fd_set_kchunk(int(kchunk)), "fd_set_kchunk")
 
 
+def step_launch(grid: Grid) -> dict:
+    """Launch shape of the forward stencil kernel over ``grid`` (fd_step_launch)."""
+    out = (C.c_int32 * 4)()
+    check(lib().fd_step_launch(grid.ref, out), "fd_step_launch")
+    tx, ty, kc, zc = out
+    return {"tiles_x": tx, "tiles_y": ty, "kchunk": kc, "zchunks": zc, "blocks": tx * ty * zc}
+
+
 # ----------------------------------------------------------------- forward model
 
 def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: int, src=None,

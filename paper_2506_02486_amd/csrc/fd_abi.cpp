@@ -174,6 +174,16 @@ int fd_set_kchunk(int32_t kchunk) {
   return FD_OK;
 }
 
+int fd_step_launch(const fd_grid* g, int32_t out[4]) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!out) return fail(FD_EINVAL, "fd_step_launch: out is NULL");
+  int o[4];
+  forward_launch_shape(make_geo(g), o);
+  for (int i = 0; i < 4; ++i) out[i] = o[i];
+  return FD_OK;
+}
+
 int fd_cfl_dt(const fd_grid* g, const float* v, double courant, int32_t* scratch_dev,
               double* vmax_host, double* dt_out, void* stream) {
   int rc = check_grid(g);

@@ -75,6 +75,13 @@ struct BatchStep {
 hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float* u,
                        float* un, const float* q, const float* ex, const float* ey,
                        const float* ez, const fd_source* src, hipStream_t s);
+// Planes per block (z chunk) for one launch over n grids, grid i with xy[i] x-y
+// tiles and nz[i] planes, with the least modelled time; at most kc_max planes
+// (0: no limit) and at most max_blocks blocks (the longest chunk is the fallback).
+int choose_kchunk(const long long* xy, const int* nz, int n, int waves_per_block, int kc_max,
+                  long long max_blocks);
+// tiles_x, tiles_y, kchunk, zchunks of the forward stencil launch over g
+void forward_launch_shape(const Geo& g, int out[4]);
 // Tile size (x, y) of the batched kernel; returns threads per block.
 int batch_tile_shape(int* tx, int* ty);
 // One time step of every shot listed in the tile table (entries: slot, bx, by, bz).

@@ -36,10 +36,17 @@ namespace fd {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kInflight = 4;
+// The progress thread runs at most kEventEvery * kInflight batched steps ahead of
+// the device.  It records a throttle event once per kEventEvery steps, not every
+// step: each default event between two launches left the device idle ~5.5 us
+// (kernel trace of lone 192^3 shots: 27 us steps)
+constexpr int kInflight = 2;
+constexpr int kEventEvery = 4;
 constexpr int kTileCap = 1 << 16;   // tile-table entries
-// z planes per tile-table entry: short chunks give fine-grained blocks that
-// balance shots of uneven size within one launch (measured best at 16-24)
+// z planes per tile-table entry counted against kTileCap at admission.  The table
+// itself uses the z chunk the stencil's launch model picks for the active shots
+// together (a lone 128^3 shot: 2 planes, 512 blocks; 32 shots of the 128..384^3
+// mix: tens of planes), within kTileCap entries.
 constexpr int kServeKchunk = 24;
 constexpr double kSpongeR = 1e-3;
 
@@ -180,6 +187,7 @@ struct Server {
   std::vector<std::pair<size_t, float*>> pinned_pool;
   int64_t next_id = 1;
   int64_t steps = 0;
+  int64_t max_points = 0;  // admission waits while the slots hold this many points
   int queued = 0, running = 0, finished = 0;
   bool stopping = false, stopped = false;
   std::thread th;
@@ -301,14 +309,26 @@ hipError_t upload_tables(Server* S) {
   memcpy(S->h_shots[st], S->shots_host.data(), sizeof(BatchShot) * S->max_slots);
   int nt = 0, na = 0, mr = 0;
   int tx, ty;
-  batch_tile_shape(&tx, &ty);
+  const int wpb = batch_tile_shape(&tx, &ty) / 64;  // waves per block
+  // one z chunk for all active shots, chosen by the stencil's launch-time model
+  // within kTileCap entries (a chunk of kServeKchunk planes always fits)
+  std::vector<long long> xy;
+  std::vector<int> nzs;
+  for (const Shot* s : S->slots)
+    if (s) {
+      xy.push_back((long long)((s->d.nx + tx - 1) / tx) * ((s->d.ny + ty - 1) / ty));
+      nzs.push_back(s->d.nz);
+    }
+  const int kc = xy.empty() ? kServeKchunk
+                            : choose_kchunk(xy.data(), nzs.data(), (int)xy.size(), wpb, 0, kTileCap);
   for (int slot = 0; slot < S->max_slots; ++slot) {
     Shot* s = S->slots[slot];
     if (!s) continue;
     h_slots[na++] = slot;
     mr = std::max(mr, s->d.nrec);
     const int bxn = (s->d.nx + tx - 1) / tx, byn = (s->d.ny + ty - 1) / ty;
-    const int bzn = (s->d.nz + kServeKchunk - 1) / kServeKchunk;
+    const int bzn = (s->d.nz + kc - 1) / kc;
+    S->h_shots[st][slot].kchunk = kc;
     for (int bz = 0; bz < bzn; ++bz)
       for (int by = 0; by < byn; ++by)
         for (int bx = 0; bx < bxn; ++bx) h_tiles[nt++] = make_int4(slot, bx, by, bz);
@@ -334,6 +354,13 @@ int tiles_in_use(Server* S) {
   return t;
 }
 
+long long points_in_use(Server* S) {
+  long long p = 0;
+  for (Shot* s : S->slots)
+    if (s) p += (long long)s->d.nx * s->d.ny * s->d.nz;
+  return p;
+}
+
 void progress(Server* S) {
   hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
@@ -347,6 +374,7 @@ void progress(Server* S) {
         if (!S->slots[i]) { slot = i; break; }
       if (slot < 0) break;
       if (tiles_in_use(S) + s->L.tiles > kTileCap) break;
+      if (S->max_points > 0 && points_in_use(S) >= S->max_points) break;
       size_t off;
       if (!S->arena->alloc(s->L.total, &off)) break;
       S->queue.pop_front();
@@ -421,13 +449,16 @@ void progress(Server* S) {
     const bool dirty = S->table_dirty;
     lk.unlock();
     hipError_t e = hipSuccess;
-    const int64_t step = S->steps;
-    if (step >= kInflight) e = hipEventSynchronize(S->step_ev[step % kInflight]);
+    const int64_t step = S->steps, grp = step / kEventEvery;
+    // the first step of group grp waits for the end of group grp - kInflight
+    if (step % kEventEvery == 0 && grp >= kInflight)
+      e = hipEventSynchronize(S->step_ev[grp % kInflight]);
     if (e == hipSuccess && dirty) e = upload_tables(S);
     if (e == hipSuccess) e = launch_batched(S->d_shots, S->d_tiles, S->ntiles, a, S->cs);
     if (e == hipSuccess)
       e = launch_batched_record(S->d_shots, S->d_slots, S->nactive, S->max_nrec, a, S->cs);
-    if (e == hipSuccess) e = hipEventRecord(S->step_ev[step % kInflight], S->cs);
+    if (e == hipSuccess && step % kEventEvery == kEventEvery - 1)
+      e = hipEventRecord(S->step_ev[grp % kInflight], S->cs);
     lk.lock();
     S->steps++;
     if (e != hipSuccess) {
@@ -578,8 +609,10 @@ int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t ma
     if (e == hipSuccess) e = hipEventRecord(S->table_ev[i], S->cs);
   }
   if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_scratch, 8, hipHostMallocDefault);
+  // throttle events only tell how far the device got; without the system-scope
+  // release (an L2 write-back) an event between two steps costs no idle time
   for (int i = 0; i < kInflight && e == hipSuccess; ++i)
-    e = hipEventCreateWithFlags(&S->step_ev[i], hipEventDisableTiming);
+    e = hipEventCreateWithFlags(&S->step_ev[i], hipEventDisableTiming | hipEventDisableSystemFence);
   if (e != hipSuccess) {
     rc = check_hip(e, "fd_server_create");
     Server* raw = S.release();
@@ -656,6 +689,18 @@ int shot_poll(void* srv, int64_t shot_id, float* traces_host, size_t cap, int64_
   S->shots.erase(it);
   if (code != FD_OK) fail(code, "shot %lld ended with %s", (long long)shot_id, fd_strerror(code));
   return code;
+}
+
+int fd_server_set_admission(void* srv, int64_t max_active_points) {
+  Server* S = static_cast<Server*>(srv);
+  if (!S) return fail(FD_EINVAL, "fd_server_set_admission: NULL server");
+  if (max_active_points < 0) return fail(FD_EINVAL, "max_active_points must be >= 0");
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->max_points = max_active_points;
+  }
+  S->cv.notify_all();
+  return FD_OK;
 }
 
 int fd_server_stats(void* srv, int64_t out[4]) {

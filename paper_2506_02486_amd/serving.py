@@ -68,7 +68,8 @@ class Shot:
 class ShotServer:
     """Submit shots from any thread; poll for (code, traces (nt, nrec), t_ns)."""
 
-    def __init__(self, arena_bytes: int, max_slots: int = 32, device="cuda"):
+    def __init__(self, arena_bytes: int, max_slots: int = 32, device="cuda",
+                 max_active_points: int = 0):
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         self.cs = torch.cuda.Stream(device=device)
         self.xs = torch.cuda.Stream(device=device)
@@ -78,6 +79,13 @@ class ShotServer:
               "fd_server_create")
         self.h = h
         self._shots: dict[int, Shot] = {}
+        if max_active_points:
+            self.set_admission(max_active_points)
+
+    def set_admission(self, max_active_points: int):
+        """Admit queued shots only while the running ones hold fewer points (0: no limit)."""
+        check(lib().fd_server_set_admission(self.h, int(max_active_points)),
+              "fd_server_set_admission")
 
     def submit(self, shot: Shot) -> int:
         # the server reads the velocity on its own stream: finish writes to it first

@@ -206,6 +206,42 @@ def test_host_helpers(L):
     assert L.fd_set_kchunk(0) == 0
 
 
+def launch(L, nx, ny, nz):
+    out = (C.c_int32 * 4)()
+    assert L.fd_step_launch(C.byref(grid(L, nx, ny, nz)), out) == 0
+    tx, ty, kc, zc = out
+    assert (tx, ty) == (-(-nx // 64), -(-ny // 32))
+    assert zc == -(-nz // kc) and 1 <= kc <= nz
+    return kc, tx * ty * zc
+
+
+def test_step_launch_shape(L):
+    """The forward stencil's z chunk: 512 resident blocks of 8 waves make one round
+    on 256 CUs; the choice fills one round where the x-y tiles allow it and never
+    leaves a small second round (a 576-block launch of 384^3 took 210 us against 164
+    at 432 blocks)."""
+    assert launch(L, 512, 512, 512) == (128, 512)
+    assert launch(L, 1024, 1024, 512) == (512, 512)
+    assert launch(L, 256, 256, 256) == (16, 512)
+    assert launch(L, 64, 64, 64) == (1, 128)  # small grids: one-plane chunks
+    for n in (128, 192, 320, 384, 448):
+        kc, blocks = launch(L, n, n, n)
+        assert 448 <= blocks <= 512, (n, kc, blocks)
+    kc, blocks = launch(L, 64, 32, 5000)  # one x-y tile, deep: split in z alone
+    assert 448 <= blocks <= 512 and kc == -(-5000 // blocks)
+    kc, blocks = launch(L, 64 * 20, 32 * 30, 64)  # 600 x-y tiles: never 1.17 rounds
+    assert blocks % 600 == 0 and blocks != 600
+    assert L.fd_set_kchunk(24) == 0
+    try:
+        assert launch(L, 512, 512, 512) == (24, 128 * 22)
+    finally:
+        assert L.fd_set_kchunk(0) == 0
+    assert launch(L, 512, 512, 512) == (128, 512)
+    out = (C.c_int32 * 4)()
+    assert L.fd_step_launch(C.byref(grid(L)), None) == _lib.FD_EINVAL
+    assert L.fd_step_launch(None, out) == _lib.FD_EINVAL
+
+
 def test_shot_footprint_and_server_argument_checks(L):
     d = _lib.fd_shot_desc()
     d.nx, d.ny, d.nz, d.nt = 256, 256, 256, 500
@@ -226,3 +262,4 @@ def test_shot_footprint_and_server_argument_checks(L):
     assert L.fd_server_create(C.byref(h), FAKE, 4096, 4, None, None) == _lib.FD_ENOMEM
     assert L.shot_submit(None, C.byref(d), C.byref(C.c_int64())) == EINVAL
     assert L.shot_poll(None, 1, None, 0, None) == EINVAL
+    assert L.fd_server_set_admission(None, 0) == EINVAL

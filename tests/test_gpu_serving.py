@@ -4,8 +4,8 @@ Every shot's traces from the batched server must be bitwise equal to the same sh
 alone through fd_step_fused + record_receivers (the batched kernel runs the same
 per-point code); the smallest shots are also checked against the FP64 oracle
 (relative L2 <= 1e-4).  Admission is checked under an arena that holds only a few
-shots, and the error paths (oversize, unknown id, unstable dt, shutdown) end as
-documented.
+shots and under a cap on the points running at once, and the error paths
+(oversize, unknown id, unstable dt, shutdown) end as documented.
 """
 import numpy as np
 import pytest
@@ -74,6 +74,27 @@ def test_mix_equals_solo_bitwise_and_overlaps(model):
     assert st["running"] == 0 and st["queued"] == 0
     # fewer launches than the plain loop would issue
     assert st["steps"] < sum(s.nt for s in shots)
+
+
+def test_admission_cap_runs_shots_in_turn(model):
+    """max_active_points = 1 admits a shot only when none runs: every batched step
+    then advances exactly one shot, so the steps launched are the sum of the nt."""
+    shots = make_shots(model, 4, nt=20, seed=5)
+    with serving.ShotServer(2 << 30, max_slots=8, max_active_points=1) as srv:
+        ids = [srv.submit(s) for s in shots]
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+        with pytest.raises(_lib.FDError) as e:
+            srv.set_admission(-1)
+        assert e.value.code == _lib.FD_EINVAL
+        srv.set_admission(0)  # no limit again: the next shot still runs
+        assert srv.wait(srv.submit(shots[0]))[0] == _lib.FD_OK
+    assert st["steps"] == sum(s.nt for s in shots)
+    admits = [r[2][1] for r in res]
+    assert admits == sorted(admits)
+    for shot, (code, tr, _) in zip(shots, res):
+        assert code == _lib.FD_OK
+        assert np.array_equal(tr, solo(shot))
 
 
 def test_small_shots_match_oracle(model):
