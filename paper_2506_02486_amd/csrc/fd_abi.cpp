@@ -44,8 +44,6 @@ Coef make_coef(const fd_grid* g) {
   return c;
 }
 
-void set_kchunk_override(int kc);
-
 }  // namespace fd
 
 using namespace fd;

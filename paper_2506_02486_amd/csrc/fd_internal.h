@@ -80,6 +80,14 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
 // (0: no limit) and at most max_blocks blocks (the longest chunk is the fallback).
 int choose_kchunk(const long long* xy, const int* nz, int n, int waves_per_block, int kc_max,
                   long long max_blocks);
+struct LaunchShape {
+  int tiles_x, tiles_y, kchunk, zchunks;
+};
+// Blocks of a stencil kernel with tx x ty tiles over g: the z chunk set by
+// set_kchunk_override (> 0), else choose_kchunk's.
+LaunchShape stencil_shape(const Geo& g, int tx, int ty, int waves_per_block);
+// Process-wide z chunk for every stencil launch (0: automatic).
+void set_kchunk_override(int kc);
 // tiles_x, tiles_y, kchunk, zchunks of the forward stencil launch over g
 void forward_launch_shape(const Geo& g, int out[4]);
 // Tile size (x, y) of the batched kernel; returns threads per block.

@@ -1,0 +1,88 @@
+// fd_launch.cpp -- launch shape of the z-marching stencil kernels (host only).
+//
+// A stencil block owns one x-y tile and marches through a chunk of kc z planes,
+// so a launch over a grid has tiles_x * tiles_y * ceil(nz / kc) blocks.  The
+// chunk trades blocks (bandwidth needs enough of them in flight, and a small
+// last round of blocks runs nearly alone) against the z halo each chunk reads
+// again.  choose_kchunk takes the chunk of least modelled time.
+#include <algorithm>
+#include <atomic>
+
+#include "fd_internal.h"
+
+namespace fd {
+namespace {
+
+std::atomic<int> g_kchunk_override{0};
+
+// Relative time of a launch of B blocks that each stream kc planes (+1 for the
+// z halo, which mostly hits L2), when R blocks fit on the chip at once.  Below one
+// round the blocks cannot pull the full bandwidth; a little above it the second
+// round runs nearly alone.  Fitted to stencil times of cubes 128..512 over z chunks
+// of 4..128 planes (e.g. 384^3: 576 blocks 210 us, 432 blocks 164 us).
+double launch_cost(long long B, int kc, long long R) {
+  const double x = (double)B / (double)R;
+  const double e = x <= 1.0 ? 0.55 + 0.3 * x : std::max(0.9 * x + 0.2, 1.4);
+  return (kc + 1.0) * e;
+}
+
+}  // namespace
+
+int choose_kchunk(const long long* xy, const int* nz, int n, int waves_per_block, int kc_max,
+                  long long max_blocks) {
+  // 4096 waves: 16 per CU on 256 CUs
+  const long long R = std::max(1, 4096 / std::max(1, waves_per_block));
+  int deep = 1;
+  for (int i = 0; i < n; ++i) deep = std::max(deep, nz[i]);
+  const int top = kc_max > 0 ? std::min(deep, kc_max) : deep;
+  // candidates: the shortest chunk that cuts the deepest grid into z pieces, for
+  // z = 1, 2, ... (exact for one grid: the time grows with kc at a fixed block
+  // count); past eight rounds of blocks shorter chunks only add blocks and halo
+  int best = top, prev = -1;
+  double best_cost = -1.0;
+  for (long long z = (deep + top - 1) / top;; ++z) {
+    const int kc = (int)((deep + z - 1) / z);
+    if (kc == prev) continue;
+    prev = kc;
+    long long B = 0;
+    for (int i = 0; i < n; ++i) B += xy[i] * ((nz[i] + kc - 1) / kc);
+    if (B > max_blocks) break;  // B only grows as kc shrinks
+    const double c = launch_cost(B, kc, R);
+    if (best_cost < 0.0 || c < best_cost) {  // ties go to the longer chunk
+      best_cost = c;
+      best = kc;
+    }
+    if (kc == 1 || B > 8 * R) break;
+  }
+  return best;
+}
+
+LaunchShape stencil_shape(const Geo& g, int tx, int ty, int waves_per_block) {
+  LaunchShape s;
+  s.tiles_x = (g.nx + tx - 1) / tx;
+  s.tiles_y = (g.ny + ty - 1) / ty;
+  const long long tiles = (long long)s.tiles_x * s.tiles_y;
+  int kc = g_kchunk_override.load(std::memory_order_relaxed);
+  if (kc <= 0) {
+    // one full round of resident blocks where the x-y tiles allow it (512^3: 128
+    // planes, 256^3: 16), several rounds otherwise, one plane for small grids whose
+    // arrays sit in cache (64^3: 4.8 us per step at 1 plane, 8.0 at 4).  The last
+    // choice is kept per thread.
+    thread_local struct { int nx = -1, ny = -1, nz = -1, tx = -1, ty = -1, w = -1, kc = 0; } last;
+    if (last.nx == g.nx && last.ny == g.ny && last.nz == g.nz && last.tx == tx && last.ty == ty &&
+        last.w == waves_per_block) {
+      kc = last.kc;
+    } else {
+      kc = choose_kchunk(&tiles, &g.nz, 1, waves_per_block, 0, 0x7fffffffLL);
+      last = {g.nx, g.ny, g.nz, tx, ty, waves_per_block, kc};
+    }
+  }
+  if (kc > g.nz) kc = g.nz;
+  s.kchunk = kc;
+  s.zchunks = (g.nz + kc - 1) / kc;
+  return s;
+}
+
+void set_kchunk_override(int kc) { g_kchunk_override.store(kc, std::memory_order_relaxed); }
+
+}  // namespace fd

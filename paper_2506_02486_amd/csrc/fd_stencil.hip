@@ -34,7 +34,6 @@
 // Exchange form (XCH, fd_step_exchange): the -x/+x halos are read from receive
 // buffers and the x faces of the result written to send buffers by the lanes
 // that own them, instead of a separate unpack/pack over 16-byte row pieces.
-#include <algorithm>
 #include <type_traits>
 
 #include "fd_internal.h"
@@ -536,80 +535,10 @@ __global__ void __launch_bounds__(TXT * NY) batched_kernel(const BatchShot* __re
   stencil_block<TXT, NY, RY, FWD, true, true, true, false>(p, t.y, t.z, t.w);
 }
 
-struct LaunchShape {
-  int tiles_x, tiles_y, kchunk, zchunks;
-};
-
-int g_kchunk_override = 0;
-
-// Relative time of a launch of B blocks that each stream kc planes (+1 for the
-// z halo, which mostly hits L2), when R blocks fit on the chip at once.  Below one
-// round the blocks cannot pull the full bandwidth; a little above it the second
-// round runs nearly alone.  Fitted to stencil times of cubes 128..512 over z chunks
-// of 4..128 planes (e.g. 384^3: 576 blocks 210 us, 432 blocks 164 us).
-double launch_cost(long long B, int kc, long long R) {
-  const double x = (double)B / (double)R;
-  const double e = x <= 1.0 ? 0.55 + 0.3 * x : std::max(0.9 * x + 0.2, 1.4);
-  return (kc + 1.0) * e;
-}
-
-}  // namespace
-
-int choose_kchunk(const long long* xy, const int* nz, int n, int waves_per_block, int kc_max,
-                  long long max_blocks) {
-  const long long R = std::max(1, 4096 / std::max(1, waves_per_block));
-  int top = 1;
-  for (int i = 0; i < n; ++i) top = std::max(top, nz[i]);
-  if (kc_max > 0) top = std::min(top, kc_max);
-  int best = top;
-  double best_cost = -1.0;
-  for (int kc = top; kc >= 1; --kc) {  // ties go to the longer chunk
-    long long B = 0;
-    for (int i = 0; i < n; ++i) B += xy[i] * ((nz[i] + kc - 1) / kc);
-    if (B > max_blocks) break;  // B only grows as kc shrinks
-    const double c = launch_cost(B, kc, R);
-    if (best_cost < 0.0 || c < best_cost) {
-      best_cost = c;
-      best = kc;
-    }
-  }
-  return best;
-}
-
-namespace {
-
-LaunchShape shape_for(const Geo& g, int tx, int ty, int waves_per_block) {
-  LaunchShape s;
-  s.tiles_x = (g.nx + tx - 1) / tx;
-  s.tiles_y = (g.ny + ty - 1) / ty;
-  const long long tiles = (long long)s.tiles_x * s.tiles_y;
-  int kc;
-  if (g_kchunk_override > 0) {
-    kc = g_kchunk_override;
-  } else {
-    // the chunk with the least modelled time: one full round of resident blocks
-    // when the x-y tiles allow it (512^3: 128 planes, 256^3: 16), several rounds
-    // otherwise, one plane for small grids whose arrays sit in cache (64^3: 4.8 us
-    // per step at 1 plane, 8.0 at 4).  The last choice is kept per thread.
-    thread_local struct { int nx = -1, ny = -1, nz = -1, tx = -1, ty = -1, w = -1, kc = 0; } last;
-    if (last.nx == g.nx && last.ny == g.ny && last.nz == g.nz && last.tx == tx && last.ty == ty &&
-        last.w == waves_per_block) {
-      kc = last.kc;
-    } else {
-      kc = choose_kchunk(&tiles, &g.nz, 1, waves_per_block, 0, 0x7fffffffLL);
-      last = {g.nx, g.ny, g.nz, tx, ty, waves_per_block, kc};
-    }
-  }
-  if (kc > g.nz) kc = g.nz;
-  s.kchunk = kc;
-  s.zchunks = (g.nz + kc - 1) / kc;
-  return s;
-}
-
 template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE = false,
           bool EARLY = (MODE == FWD), bool XCH = false>
 hipError_t launch_mode(Params p, hipStream_t st) {
-  const LaunchShape sh = shape_for(p.g, TXT, NY * RY, (TXT * NY + 63) / 64);
+  const LaunchShape sh = stencil_shape(p.g, TXT, NY * RY, (TXT * NY + 63) / 64);
   p.tiles_x = sh.tiles_x;
   p.tiles_y = sh.tiles_y;
   p.kchunk = sh.kchunk;
@@ -643,10 +572,8 @@ constexpr int BATCH_TY = 8 * 4;   // tile height of the batched kernel (FWD_SHAP
 
 }  // namespace
 
-void set_kchunk_override(int kc) { g_kchunk_override = kc; }
-
 void forward_launch_shape(const Geo& g, int out[4]) {
-  const LaunchShape sh = shape_for(g, 64, 8 * 4, 8);  // FWD_SHAPE: 64 x (8 x 4), 8 waves
+  const LaunchShape sh = stencil_shape(g, BATCH_TX, BATCH_TY, BATCH_TX * 8 / 64);  // FWD_SHAPE
   out[0] = sh.tiles_x;
   out[1] = sh.tiles_y;
   out[2] = sh.kchunk;
