@@ -252,7 +252,7 @@ int admit_device(Server* S, Shot* s, int slot) {
   // sponge tables and receiver offsets through the pinned staging buffer
   const size_t need = (size_t)(d.nx + d.ny + d.nz) + 2 + 2 * (size_t)std::max(d.nrec, 1);
   if (need > S->h_stage_cap) {
-    if (S->h_stage) hipHostFree(S->h_stage);
+    if (S->h_stage) (void)hipHostFree(S->h_stage);
     S->h_stage = nullptr;
     if (hipHostMalloc((void**)&S->h_stage, need * 4, hipHostMallocDefault) != hipSuccess)
       return fail(FD_ENOMEM, "shot: pinned staging allocation failed");
@@ -362,9 +362,10 @@ long long points_in_use(Server* S) {
 }
 
 void progress(Server* S) {
-  hipSetDevice(S->device);
+  const hipError_t dev = hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
-  int fatal = FD_OK;
+  // without its device the thread can run nothing: every shot fails with FD_EDEVICE
+  int fatal = dev == hipSuccess ? FD_OK : check_hip(dev, "server thread: hipSetDevice");
   while (!S->stopping) {
     // ---- admission (strict FIFO)
     while (!S->queue.empty() && fatal == FD_OK) {
@@ -412,7 +413,7 @@ void progress(Server* S) {
       if (q == hipErrorNotReady) { ++i; continue; }
       S->arena->release(s->off, s->L.total);
       s->has_block = false;
-      hipEventDestroy(s->copied);
+      (void)hipEventDestroy(s->copied);
       s->copied = nullptr;
       S->running--;
       finish_locked(S, s, q == hipSuccess ? FD_OK : FD_EDEVICE);
@@ -489,7 +490,7 @@ void progress(Server* S) {
         r = hipMemcpyAsync(s->host, reinterpret_cast<char*>(S->base) + s->off + s->L.traces,
                            4 * s->host_cap, hipMemcpyDeviceToHost, S->xs);
       if (r == hipSuccess) r = hipEventRecord(s->copied, S->xs);
-      if (stepped) hipEventDestroy(stepped);
+      if (stepped) (void)hipEventDestroy(stepped);
       if (r != hipSuccess) {
         check_hip(r, "trace copy");
         S->arena->release(s->off, s->L.total);
@@ -503,8 +504,8 @@ void progress(Server* S) {
   }
   lk.unlock();
   // let queued device work finish before the caller frees anything
-  hipStreamSynchronize(S->cs);
-  hipStreamSynchronize(S->xs);
+  (void)hipStreamSynchronize(S->cs);
+  (void)hipStreamSynchronize(S->xs);
 }
 
 void stop_server(Server* S) {
@@ -530,7 +531,7 @@ void stop_server(Server* S) {
       finish_locked(S, s, FD_ECANCELED);
     }
   for (Shot* s : S->draining) {  // copies completed in the final synchronisation
-    if (s->copied) hipEventDestroy(s->copied);
+    if (s->copied) (void)hipEventDestroy(s->copied);
     s->copied = nullptr;
     if (s->has_block) S->arena->release(s->off, s->L.total);
     s->has_block = false;
@@ -726,20 +727,20 @@ int fd_server_destroy(void* srv) {
   if (!S) return fail(FD_EINVAL, "fd_server_destroy: NULL server");
   stop_server(S);
   for (auto& kv : S->shots) give_pinned(S, kv.second->host, kv.second->host_cap);
-  for (auto& pb : S->pinned_pool) hipHostFree(pb.second);
-  if (S->h_stage) hipHostFree(S->h_stage);
+  for (auto& pb : S->pinned_pool) (void)hipHostFree(pb.second);
+  if (S->h_stage) (void)hipHostFree(S->h_stage);
   for (int i = 0; i < 2; ++i) {
-    if (S->h_shots[i]) hipHostFree(S->h_shots[i]);
-    if (S->h_tiles[i]) hipHostFree(S->h_tiles[i]);
-    if (S->h_slots[i]) hipHostFree(S->h_slots[i]);
-    if (S->table_ev[i]) hipEventDestroy(S->table_ev[i]);
+    if (S->h_shots[i]) (void)hipHostFree(S->h_shots[i]);
+    if (S->h_tiles[i]) (void)hipHostFree(S->h_tiles[i]);
+    if (S->h_slots[i]) (void)hipHostFree(S->h_slots[i]);
+    if (S->table_ev[i]) (void)hipEventDestroy(S->table_ev[i]);
   }
-  if (S->h_scratch) hipHostFree(S->h_scratch);
+  if (S->h_scratch) (void)hipHostFree(S->h_scratch);
   for (int i = 0; i < kInflight; ++i)
-    if (S->step_ev[i]) hipEventDestroy(S->step_ev[i]);
-  if (S->own_cs) hipStreamDestroy(S->cs);
-  if (S->own_xs) hipStreamDestroy(S->xs);
-  if (S->as) hipStreamDestroy(S->as);
+    if (S->step_ev[i]) (void)hipEventDestroy(S->step_ev[i]);
+  if (S->own_cs) (void)hipStreamDestroy(S->cs);
+  if (S->own_xs) (void)hipStreamDestroy(S->xs);
+  if (S->as) (void)hipStreamDestroy(S->as);
   delete S;
   return FD_OK;
 }

@@ -264,8 +264,8 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
   // re-read of those cells follows its own load closely enough to hit in L2.
   // Otherwise: the halos of plane k only, loaded one plane ahead.
   float hy[HPT], hx;
-  float hq[EARLY ? 9 : 1][HPT], xq[EARLY ? 9 : 1];
-  if (EARLY) {
+  float hq[9][HPT], xq[9];  // the early form's rings (unused, and removed, otherwise)
+  if constexpr (EARLY) {
 #pragma unroll
     for (int s = 4; s < 9; ++s) {
       const int k = kb - 4 + s;
@@ -453,10 +453,10 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
     }
 #pragma unroll
     for (int h = 0; h < HPT; ++h) {
-      if (EARLY) hq[P][h] = nhy[h];  // plane k + 5
+      if constexpr (EARLY) hq[P][h] = nhy[h];  // plane k + 5
       else hy[h] = nhy[h];
     }
-    if (EARLY) xq[P] = nhx;
+    if constexpr (EARLY) xq[P] = nhx;
     else hx = nhx;
   };
   using std::integral_constant;
