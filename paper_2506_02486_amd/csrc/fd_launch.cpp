@@ -19,7 +19,9 @@ std::atomic<int> g_kchunk_override{0};
 // z halo, which mostly hits L2), when R blocks fit on the chip at once.  Below one
 // round the blocks cannot pull the full bandwidth; a little above it the second
 // round runs nearly alone.  Fitted to stencil times of cubes 128..512 over z chunks
-// of 4..128 planes (e.g. 384^3: 576 blocks 210 us, 432 blocks 164 us).
+// of 4..128 planes; with the three wavefields rotating as in real stepping, its
+// choice was the fastest of 17 chunks tried at every one of those sizes (e.g.
+// 384^3: 576 blocks 235 us, 432 blocks 185 us, the chosen 504 blocks 175 us).
 double launch_cost(long long B, int kc, long long R) {
   const double x = (double)B / (double)R;
   const double e = x <= 1.0 ? 0.55 + 0.3 * x : std::max(0.9 * x + 0.2, 1.4);
