@@ -78,6 +78,32 @@ def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
     return 2 * nbytes / s / 1e9
 
 
+def stream_bandwidth(torch, n=140_000_000, reps=20):
+    """Bandwidth of torch's own elementwise kernel on the stencil's access mix: three
+    arrays read and one written per element (addcmul, 16 B/element), the three
+    working arrays rotating as the wavefields do (560 MB each, far above the 256 MB
+    last-level cache).  A reference for what plain streaming of that mix reaches."""
+    bufs = [torch.ones(n, dtype=torch.float32, device="cuda") for _ in range(3)]
+    q = torch.full((n,), 0.25, dtype=torch.float32, device="cuda")
+
+    def step(i):
+        torch.addcmul(bufs[i % 3], bufs[(i + 1) % 3], q, out=bufs[(i + 2) % 3])
+
+    for i in range(3):
+        step(i)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        step(i)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del bufs, q
+    return 16.0 * n / s / 1e9
+
+
 def cpu_baseline(v, dt, src, steps):
     """FP64 oracle on the same 512^3 workload: (time of 1+steps) - (time of 1 step)."""
     import numpy as np
@@ -476,6 +502,7 @@ def main():
         f"{gpts:.1f} Gpts/s, finite={finite}")
 
     copy_gbps = copy_bandwidth(torch)
+    stream_gbps = stream_bandwidth(torch)
     if args.copy_calibration:
         # a plain copy of exactly 1 GiB read + 1 GiB written, for the counter factor
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -528,6 +555,9 @@ def main():
             "frac": round(path_bytes / (elapsed / K) / 1e9 / PEAK_HBM_GBPS, 4),
         },
         "copy_GBps": round(copy_gbps, 1),
+        # torch addcmul over rotating 560 MB arrays: 3 reads + 1 write, the stencil's mix
+        "stream_3r1w_GBps": round(stream_gbps, 1),
+        "stencil_vs_stream_3r1w": round(achieved / stream_gbps, 3),
         "gpu": torch.cuda.get_device_name(0),
         "hip": torch.version.hip,
         "finite": finite,
