@@ -30,6 +30,7 @@
 #include <thread>
 #include <vector>
 
+#include "fd_arena.h"
 #include "fd_internal.h"
 
 namespace fd {
@@ -57,43 +58,6 @@ int64_t now_ns() {
              std::chrono::steady_clock::now().time_since_epoch())
       .count();
 }
-
-// First-fit allocator over [0, size) with coalescing of neighbouring holes.
-class Arena {
- public:
-  explicit Arena(size_t size) { if (size) free_[0] = size; }
-  bool alloc(size_t n, size_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        *off = it->first;
-        const size_t rest = it->second - n;
-        const size_t at = it->first + n;
-        free_.erase(it);
-        if (rest) free_[at] = rest;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-
- private:
-  std::map<size_t, size_t> free_;
-};
 
 // Layout of one shot's arena block.
 struct ShotLayout {

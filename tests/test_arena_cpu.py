@@ -1,0 +1,24 @@
+"""The shot server's arena allocator (csrc/fd_arena.h), built on the host with gcc under
+AddressSanitizer and UndefinedBehaviorSanitizer and checked against a brute-force
+first-fit model (tests/cpp/test_arena.cpp): same offsets, no overlap, holes equal to the
+free runs, everything merged back after the last release."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_arena_against_first_fit_model(tmp_path):
+    exe = tmp_path / "test_arena"
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-I", os.path.join(ROOT, "paper_2506_02486_amd", "csrc"),
+           os.path.join(ROOT, "tests", "cpp", "test_arena.cpp"), "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.strip() == "ok"
