@@ -120,11 +120,18 @@ int64_t fd_offset(const fd_grid* g, int32_t i, int32_t j, int32_t k);
  * depend on it. */
 int fd_set_kchunk(int32_t kchunk);
 
+/* Performance knob: tile shape of the forward stencil kernels (fd_step,
+ * fd_step_fused, fd_step_exchange, fd_forward_run, fd_adjoint_step_scaled):
+ * 0 = automatic (64 x 16 points for grids of at most 2^20 interior points,
+ * 64 x 32 above), 1 = always 64 x 32, 2 = always 64 x 16.  Process-wide;
+ * results do not depend on it.  FD_EINVAL for another mode. */
+int fd_set_tiles(int32_t mode);
+
 /* Launch shape of the forward stencil kernel (fd_step, fd_step_fused,
  * fd_step_exchange) over g, as the next such call would use it: out[0..3] =
  * x tiles, y tiles, z planes per block, z chunks (blocks = their product; a
- * tile is 64 x 32 points).  Host only, no device call; FD_EINVAL for a bad
- * grid or NULL out. */
+ * tile is 64 x 32 points, or 64 x 16, see fd_set_tiles).  Host only, no device
+ * call; FD_EINVAL for a bad grid or NULL out. */
 int fd_step_launch(const fd_grid* g, int32_t out[4]);
 
 /* ----------------------------------------------------------- model prep

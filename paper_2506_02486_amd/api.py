@@ -327,6 +327,11 @@ def set_kchunk(kchunk: int):
     check(lib().fd_set_kchunk(int(kchunk)), "fd_set_kchunk")
 
 
+def set_tiles(mode: int):
+    """Forward tile shape: 0 automatic, 1 = 64 x 32, 2 = 64 x 16 (fd_set_tiles)."""
+    check(lib().fd_set_tiles(int(mode)), "fd_set_tiles")
+
+
 def step_launch(grid: Grid) -> dict:
     """Launch shape of the forward stencil kernel over ``grid`` (fd_step_launch)."""
     out = (C.c_int32 * 4)()

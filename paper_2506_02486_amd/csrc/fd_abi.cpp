@@ -172,6 +172,13 @@ int fd_set_kchunk(int32_t kchunk) {
   return FD_OK;
 }
 
+int fd_set_tiles(int32_t mode) {
+  if (mode < 0 || mode > 2)
+    return fail(FD_EINVAL, "tile mode %d: 0 (automatic), 1 (64 x 32) or 2 (64 x 16)", mode);
+  set_tile_override(mode);
+  return FD_OK;
+}
+
 int fd_step_launch(const fd_grid* g, int32_t out[4]) {
   int rc = check_grid(g);
   if (rc) return rc;

@@ -88,6 +88,11 @@ struct LaunchShape {
 LaunchShape stencil_shape(const Geo& g, int tx, int ty, int waves_per_block);
 // Process-wide z chunk for every stencil launch (0: automatic).
 void set_kchunk_override(int kc);
+// Forward launches over g use 64 x 16 tiles instead of 64 x 32: small grids (at
+// most kSmallGridPoints interior points), or as forced by set_tile_override
+// (0: automatic, 1: always 64 x 32, 2: always 64 x 16).
+bool forward_small_tiles(const Geo& g);
+void set_tile_override(int mode);
 // tiles_x, tiles_y, kchunk, zchunks of the forward stencil launch over g
 void forward_launch_shape(const Geo& g, int out[4]);
 // Tile size (x, y) of the batched kernel; returns threads per block.

@@ -14,6 +14,12 @@ namespace fd {
 namespace {
 
 std::atomic<int> g_kchunk_override{0};
+std::atomic<int> g_tile_override{0};
+
+// Up to about 100^3 points the 64 x 32 tile leaves CUs idle even with one-plane
+// chunks (64^3: 128 blocks); 64 x 16 tiles double the blocks (64^3: 6.4 us per
+// step against 7.2, 96^3: 10.4 against 11.1, 128^3 the same).
+constexpr long long kSmallGridPoints = 1LL << 20;
 
 // Relative time of a launch of B blocks that each stream kc planes (+1 for the
 // z halo, which mostly hits L2), when R blocks fit on the chip at once.  Below one
@@ -86,5 +92,14 @@ LaunchShape stencil_shape(const Geo& g, int tx, int ty, int waves_per_block) {
 }
 
 void set_kchunk_override(int kc) { g_kchunk_override.store(kc, std::memory_order_relaxed); }
+
+bool forward_small_tiles(const Geo& g) {
+  const int mode = g_tile_override.load(std::memory_order_relaxed);
+  if (mode == 1) return false;
+  if (mode == 2) return true;
+  return (long long)g.nx * g.ny * g.nz <= kSmallGridPoints;
+}
+
+void set_tile_override(int mode) { g_tile_override.store(mode, std::memory_order_relaxed); }
 
 }  // namespace fd

@@ -408,9 +408,11 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
         float* dst = reinterpret_cast<float*>(ok + cb[r]);
         if (MODE == FWD) {
           // undamped update; the damped one, (2u - (1-eta) u_prev + q L u)/(1+eta),
-          // is that value plus eta u_prev over 1+eta, and keeps its bits where eta == 0
+          // is that value plus eta u_prev over 1+eta, taken only where eta != 0 (with
+          // eta == 0 it would still turn a -0 into +0), so a point's bits do not
+          // depend on whether its tile holds damped points
           float v = 2.f * uc - pa[r] + pb[r] * lap;
-          if (damped) v = (v + eta * pa[r]) * __builtin_amdgcn_rcpf(1.f + eta);
+          if (damped && eta != 0.f) v = (v + eta * pa[r]) * __builtin_amdgcn_rcpf(1.f + eta);
           if (FUSE && src_plane) {
             // no contraction: the product, quotient and sum round exactly as in
             // inject_source, whether or not eta is known to be 0 here
@@ -566,14 +568,39 @@ Params base_params(const Geo& g, const Coef& c, const float* ex, const float* ey
 
 // tile shapes (threads in x, thread rows, y rows per thread)
 #define FWD_SHAPE 64, 8, 4
+#define FWD_SMALL_SHAPE 64, 8, 2  // grids small enough to leave CUs idle with 64 x 32 tiles
 #define ADJ_SHAPE 64, 4, 2
 constexpr int BATCH_TX = 64;      // tile width of the batched kernel (FWD_SHAPE)
 constexpr int BATCH_TY = 8 * 4;   // tile height of the batched kernel (FWD_SHAPE)
 
+// The forward kernel in one tile shape: x faces exchanged inside (always with the
+// source epilogue, a negative source index meaning none), or the source fused, or
+// the plain update.
+template <int TXT, int NY, int RY>
+hipError_t launch_forward(const Params& p, bool sponge, bool fuse, bool xch, hipStream_t s) {
+  if (xch) {
+    if (sponge) return launch_mode<TXT, NY, RY, FWD, true, true, true, true>(p, s);
+    return launch_mode<TXT, NY, RY, FWD, false, true, true, true>(p, s);
+  }
+  if (fuse) {
+    if (sponge) return launch_mode<TXT, NY, RY, FWD, true, true>(p, s);
+    return launch_mode<TXT, NY, RY, FWD, false, true>(p, s);
+  }
+  if (sponge) return launch_mode<TXT, NY, RY, FWD, true>(p, s);
+  return launch_mode<TXT, NY, RY, FWD, false>(p, s);
+}
+
+hipError_t launch_forward(const Params& p, bool sponge, bool fuse, bool xch, hipStream_t s) {
+  if (forward_small_tiles(p.g)) return launch_forward<FWD_SMALL_SHAPE>(p, sponge, fuse, xch, s);
+  return launch_forward<FWD_SHAPE>(p, sponge, fuse, xch, s);
+}
+
 }  // namespace
 
 void forward_launch_shape(const Geo& g, int out[4]) {
-  const LaunchShape sh = stencil_shape(g, BATCH_TX, BATCH_TY, BATCH_TX * 8 / 64);  // FWD_SHAPE
+  // FWD_SHAPE or FWD_SMALL_SHAPE: 64-wide tiles of 8 waves, 4 or 2 rows per thread
+  const int ty = forward_small_tiles(g) ? 8 * 2 : 8 * 4;
+  const LaunchShape sh = stencil_shape(g, 64, ty, 8);
   out[0] = sh.tiles_x;
   out[1] = sh.tiles_y;
   out[2] = sh.kchunk;
@@ -609,12 +636,7 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
     p.sk = src->k;
     p.sw = src->w;
   }
-  if (src) {
-    if (ex) return launch_mode<FWD_SHAPE, FWD, true, true>(p, s);
-    return launch_mode<FWD_SHAPE, FWD, false, true>(p, s);
-  }
-  if (ex) return launch_mode<FWD_SHAPE, FWD, true>(p, s);
-  return launch_mode<FWD_SHAPE, FWD, false>(p, s);
+  return launch_forward(p, ex != nullptr, src != nullptr, false, s);
 }
 
 bool exchange_fits(const Geo& g) { return g.nx % BATCH_TX == 0; }
@@ -641,8 +663,7 @@ hipError_t launch_step_exchange(const Geo& g, const Coef& c, const float* up, co
     p.rin[f] = rin[f];
     p.sout[f] = sout[f];
   }
-  if (ex) return launch_mode<FWD_SHAPE, FWD, true, true, true, true>(p, s);
-  return launch_mode<FWD_SHAPE, FWD, false, true, true, true>(p, s);
+  return launch_forward(p, ex != nullptr, true, true, s);
 }
 
 hipError_t launch_adjoint(const Geo& g, const Coef& c, const float* ann, const float* an1,

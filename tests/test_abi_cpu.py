@@ -206,11 +206,12 @@ def test_host_helpers(L):
     assert L.fd_set_kchunk(0) == 0
 
 
-def launch(L, nx, ny, nz):
+def launch(L, nx, ny, nz, tile_rows=None):
     out = (C.c_int32 * 4)()
     assert L.fd_step_launch(C.byref(grid(L, nx, ny, nz)), out) == 0
     tx, ty, kc, zc = out
-    assert (tx, ty) == (-(-nx // 64), -(-ny // 32))
+    rows = tile_rows or (16 if nx * ny * nz <= 1 << 20 else 32)  # 64 x 16 tiles up to 2^20 points
+    assert (tx, ty) == (-(-nx // 64), -(-ny // rows))
     assert zc == -(-nz // kc) and 1 <= kc <= nz
     return kc, tx * ty * zc
 
@@ -223,10 +224,18 @@ def test_step_launch_shape(L):
     assert launch(L, 512, 512, 512) == (128, 512)
     assert launch(L, 1024, 1024, 512) == (512, 512)
     assert launch(L, 256, 256, 256) == (16, 512)
-    assert launch(L, 64, 64, 64) == (1, 128)  # small grids: one-plane chunks
-    for n in (128, 192, 320, 384, 448):
+    assert launch(L, 64, 64, 64) == (1, 256)  # small grids: 64 x 16 tiles, one-plane chunks
+    assert L.fd_set_tiles(1) == 0
+    try:
+        assert launch(L, 64, 64, 64, tile_rows=32) == (1, 128)
+        assert L.fd_set_tiles(2) == 0
+        assert launch(L, 512, 512, 512, tile_rows=16) == (256, 512)
+    finally:
+        assert L.fd_set_tiles(0) == 0
+    assert L.fd_set_tiles(3) == _lib.FD_EINVAL and L.fd_set_tiles(-1) == _lib.FD_EINVAL
+    for n in (102, 128, 192, 320, 384, 448):
         kc, blocks = launch(L, n, n, n)
-        assert 448 <= blocks <= 512, (n, kc, blocks)
+        assert 400 <= blocks <= 512, (n, kc, blocks)
     kc, blocks = launch(L, 64, 32, 5000)  # one x-y tile, deep: split in z alone
     assert 448 <= blocks <= 512 and kc == -(-5000 // blocks)
     kc, blocks = launch(L, 64 * 20, 32 * 30, 64)  # 600 x-y tiles: never 1.17 rounds

@@ -11,6 +11,7 @@ import torch
 import oracle as ora
 from workloads import (center_source, layered_velocity, random_field, receivers_plane,
                        receivers_xline, smooth_velocity)
+from bitwise import same_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -53,12 +54,12 @@ def test_setup_is_bit_exact_with_oracle():
     dt_o = ora.cfl_dt(v, 9.0)
     assert sim.dt == dt_o
     q = sim.grid.interior(sim.vdt2).cpu().numpy()
-    assert np.array_equal(q, ora.vdt2(v, dt_o).astype(np.float32))
+    assert same_bits(q, ora.vdt2(v, dt_o).astype(np.float32))
     # face halos of vdt2 carry the periodic image, edges stay zero
     P = sim.grid.padded(sim.vdt2).cpu().numpy()
-    assert np.array_equal(P[4:-4, 4:-4, :4], q[:, :, -4:])
-    assert np.array_equal(P[4:-4, -4:, 4:-4], q[:, :4, :])
-    assert np.array_equal(P[:4, 4:-4, 4:-4], q[-4:, :, :])
+    assert same_bits(P[4:-4, 4:-4, :4], q[:, :, -4:])
+    assert same_bits(P[4:-4, -4:, 4:-4], q[:, :4, :])
+    assert same_bits(P[:4, 4:-4, 4:-4], q[-4:, :, :])
     assert np.all(P[:4, :4, :] == 0)
     w = api.ricker(50, dt_o)
     assert np.allclose(w, ora.ricker(50, dt_o), rtol=0, atol=2e-7)
@@ -155,12 +156,13 @@ def test_degenerate_small_grids(shape):
     assert rel_l2(tr, tr_o) <= 1e-5
 
 
-@pytest.mark.parametrize("shape", [(128, 40, 45), (70, 33, 29)])
-def test_results_independent_of_z_chunk(shape):
-    """The z chunk (planes per block, fd_set_kchunk) changes the launch, never the
-    bits: forward runs in the exchange and fused forms and both adjoint steps give
-    the same traces, fields and gradient accumulators for chunks that end inside,
-    at and past the 9-plane unrolled loop, one plane and the whole depth."""
+@pytest.mark.parametrize("shape", [(128, 40, 45), (70, 33, 29), (192, 80, 64)])
+def test_results_independent_of_launch_shape(shape):
+    """The tile shape (fd_set_tiles: 64 x 32 or 64 x 16) and the z chunk (planes per
+    block, fd_set_kchunk) change the launch, never the bits: forward runs in the
+    exchange and fused forms and both adjoint steps give the same traces, fields and
+    gradient accumulators in both tile shapes, for chunks that end inside, at and past
+    the 9-plane unrolled loop, one plane and the whole depth."""
     nx, ny, nz = shape
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
     geom = api.Geometry(src=(nx // 3, ny // 2, nz // 2), rec=receivers_xline(nx, ny // 3, nz // 3))
@@ -187,18 +189,35 @@ def test_results_independent_of_z_chunk(shape):
             outs += [out, acc]
         return outs
 
+    def signed_zeros():
+        # a state of random values near the smallest subnormals: the update underflows
+        # to zeros of both signs, and a point with eta == 0 must keep its sign whether
+        # or not its tile holds damped points
+        sim = api.Simulation(v, sponge_width=6, geom=api.Geometry())
+        a, b = _random_state(sim.grid, 21)
+        sim.u_prev.copy_(a * 1e-43)
+        sim.u.copy_(b * 1e-43)
+        sim.run(2, mode="fused")
+        u = sim.state()[1]
+        assert bool(((u == 0) & torch.signbit(u)).any()), "no -0 produced"
+        return [sim.state()[0].clone(), u.clone()]
+
     def everything():
-        return forward("exchange") + forward("fused") + adjoint()
+        return forward("exchange") + forward("fused") + adjoint() + signed_zeros()
 
     api.set_kchunk(0)
+    api.set_tiles(0)
     ref = everything()
     try:
-        for kc in (1, 2, 5, 9, 10, 17, nz):
-            api.set_kchunk(kc)
-            for i, (a, b) in enumerate(zip(ref, everything())):
-                assert torch.equal(a, b), (kc, i)
+        for tiles in (1, 2):
+            api.set_tiles(tiles)
+            for kc in (0, 1, 2, 5, 9, 10, 17, nz):
+                api.set_kchunk(kc)
+                for i, (a, b) in enumerate(zip(ref, everything())):
+                    assert same_bits(a, b), (tiles, kc, i)
     finally:
         api.set_kchunk(0)
+        api.set_tiles(0)
 
 
 @pytest.mark.parametrize("mode", ["exchange", "fused", "separate", "native", "native-fused"])
@@ -215,7 +234,7 @@ def test_empty_runs_and_no_receivers(mode):
     tr = sim.run(0, mode=mode)
     assert tr.shape[0] == 0
     for a, b in zip(before, sim.state()):
-        assert torch.equal(a, b)
+        assert same_bits(a, b)
     assert sim.n == 5
     bare = api.Simulation(v, exchange="loopback")
     tr = bare.run(3, mode=mode)
@@ -239,7 +258,7 @@ def test_in_place_two_array_stepping_matches_three_arrays():
     a2 = a.clone()
     api.step(g, a2, b, a2, sim.vdt2, sim.sponge)
     torch.cuda.synchronize()
-    assert torch.equal(g.interior(out), g.interior(a2))
+    assert same_bits(g.interior(out), g.interior(a2))
 
 
 def test_mirror_symmetry_is_bitwise():
@@ -253,7 +272,7 @@ def test_mirror_symmetry_is_bitwise():
     u = sim.state()[1].cpu().numpy()
     assert np.abs(u).max() > 0
     for ax in range(3):
-        assert np.array_equal(u, np.flip(u, axis=ax))
+        assert same_bits(u, np.flip(u, axis=ax))
 
 
 def test_resume_is_bitwise():
@@ -264,8 +283,8 @@ def test_resume_is_bitwise():
     ta = torch.cat([a.run(30), a.run(20)])
     b = api.Simulation(v, sponge_width=6, geom=geom, exchange="loopback")
     tb = b.run(50)
-    assert torch.equal(ta, tb)
-    assert torch.equal(a.state()[1], b.state()[1])
+    assert same_bits(ta, tb)
+    assert same_bits(a.state()[1], b.state()[1])
 
 
 @pytest.mark.parametrize("nx,ny,nz", [(70, 9, 13), (72, 9, 13), (8, 5, 4)])
@@ -277,32 +296,32 @@ def test_pack_unpack_bit_exact(nx, ny, nz):
     api.halo_pack(g, u, faces)
     I = g.interior(u).cpu().numpy()
     f = [x.cpu().numpy() for x in faces]
-    assert np.array_equal(f[0].reshape(nz, ny, 4), I[:, :, :4])
-    assert np.array_equal(f[1].reshape(nz, ny, 4), I[:, :, -4:])
-    assert np.array_equal(f[2].reshape(nz, 4, nx), I[:, :4, :])
-    assert np.array_equal(f[3].reshape(nz, 4, nx), I[:, -4:, :])
-    assert np.array_equal(f[4].reshape(4, ny, nx), I[:4])
-    assert np.array_equal(f[5].reshape(4, ny, nx), I[-4:])
+    assert same_bits(f[0].reshape(nz, ny, 4), I[:, :, :4])
+    assert same_bits(f[1].reshape(nz, ny, 4), I[:, :, -4:])
+    assert same_bits(f[2].reshape(nz, 4, nx), I[:, :4, :])
+    assert same_bits(f[3].reshape(nz, 4, nx), I[:, -4:, :])
+    assert same_bits(f[4].reshape(4, ny, nx), I[:4])
+    assert same_bits(f[5].reshape(4, ny, nx), I[-4:])
     before = g.padded(u).cpu().numpy()
     api.halo_unpack(g, u, api.loopback(faces))
     P = g.padded(u).cpu().numpy()
-    assert np.array_equal(P[4:-4, 4:-4, :4], I[:, :, -4:])
-    assert np.array_equal(P[4:-4, 4:-4, -4:], I[:, :, :4])
-    assert np.array_equal(P[4:-4, :4, 4:-4], I[:, -4:, :])
-    assert np.array_equal(P[4:-4, -4:, 4:-4], I[:, :4, :])
-    assert np.array_equal(P[:4, 4:-4, 4:-4], I[-4:])
-    assert np.array_equal(P[-4:, 4:-4, 4:-4], I[:4])
+    assert same_bits(P[4:-4, 4:-4, :4], I[:, :, -4:])
+    assert same_bits(P[4:-4, 4:-4, -4:], I[:, :, :4])
+    assert same_bits(P[4:-4, :4, 4:-4], I[:, -4:, :])
+    assert same_bits(P[4:-4, -4:, 4:-4], I[:, :4, :])
+    assert same_bits(P[:4, 4:-4, 4:-4], I[-4:])
+    assert same_bits(P[-4:, 4:-4, 4:-4], I[:4])
     # interior, edges and corners untouched
-    assert np.array_equal(P[4:-4, 4:-4, 4:-4], before[4:-4, 4:-4, 4:-4])
-    assert np.array_equal(P[:4, :4], before[:4, :4])
+    assert same_bits(P[4:-4, 4:-4, 4:-4], before[4:-4, 4:-4, 4:-4])
+    assert same_bits(P[:4, :4], before[:4, :4])
     # a NULL face leaves its halo alone
     full = g.zeros()
     g.padded(full).copy_(torch.from_numpy(before))
     api.halo_unpack(g, full, [None, faces[0], None, None, None, None])
     P2 = g.padded(full).cpu().numpy()
-    assert np.array_equal(P2[4:-4, 4:-4, :4], before[4:-4, 4:-4, :4])
-    assert np.array_equal(P2[4:-4, 4:-4, -4:], I[:, :, :4])
-    assert np.array_equal(P2[4:-4, :4], before[4:-4, :4])
+    assert same_bits(P2[4:-4, 4:-4, :4], before[4:-4, 4:-4, :4])
+    assert same_bits(P2[4:-4, 4:-4, -4:], I[:, :, :4])
+    assert same_bits(P2[4:-4, :4], before[4:-4, :4])
 
 
 def test_full_size_512_sampled_per_step_parity():
@@ -425,10 +444,10 @@ def test_step_modes_match_bitwise(shape, width):
             ref = api.face_buffers(sim.grid)
             api.halo_pack(sim.grid, sim.u, ref)
             for a, b in zip(sim.send, ref):
-                assert torch.equal(a, b), mode
+                assert same_bits(a, b), mode
     for mode, other in zip(api.Simulation.MODES[1:], runs[1:]):
         for a, b in zip(runs[0], other):
-            assert torch.equal(a, b), mode
+            assert same_bits(a, b), mode
 
 
 @pytest.mark.parametrize("use_exchange_call", [False, True])
@@ -468,7 +487,7 @@ def test_two_subdomains_exchanging_faces_equal_one_domain(use_exchange_call):
                 api.step_fused(g, sl.u_prev, sl.u, sl.u_next, sl.vdt2, None, s, send[i][nxt])
             sl.u_prev, sl.u, sl.u_next = sl.u, sl.u_next, sl.u_prev
     got = torch.cat([sl.state()[1] for sl in slabs], dim=0)
-    assert torch.equal(got, whole.state()[1])
+    assert same_bits(got, whole.state()[1])
     assert float(got.abs().max()) > 0
 
 
@@ -489,14 +508,14 @@ def test_exchange_step_reads_only_the_receive_buffers():
     u_ref = u.clone()
     api.halo_unpack(g, u_ref, recv)
     api.step(g, up, u_ref, ref, sim.vdt2, sim.sponge)
-    assert torch.equal(g.interior(out1), g.interior(ref))
+    assert same_bits(g.interior(out1), g.interior(ref))
     # poison u's halo (interior kept): the result does not change
     P = g.padded(u)
     keep = g.interior(u).clone()
     P.fill_(float("nan"))
     g.interior(u).copy_(keep)
     api.step_exchange(g, up, u, out2, sim.vdt2, sim.sponge, None, recv, None)
-    assert torch.equal(g.interior(out2), g.interior(ref))
+    assert same_bits(g.interior(out2), g.interior(ref))
     # a NULL entry reads u's own halo on that face: with u's halo poisoned (again:
     # the call above may have left the received values in it) the -z
     # neighbourhood (k < 4) turns NaN and nothing else does
@@ -508,7 +527,7 @@ def test_exchange_step_reads_only_the_receive_buffers():
     api.step_exchange(g, up, u, out3, sim.vdt2, sim.sponge, None, recv_nz, None)
     I3 = g.interior(out3)
     assert torch.isnan(I3[:4]).all()
-    assert torch.equal(I3[4:], g.interior(ref)[4:])
+    assert same_bits(I3[4:], g.interior(ref)[4:])
 
 
 def test_large_subdomain_sampled_parity():
@@ -537,4 +556,4 @@ def test_large_subdomain_sampled_parity():
     gv = got[pts[:, 2], pts[:, 1], pts[:, 0]]
     assert rel_l2(gv, want) <= 1e-6
     # the receiver row is u^{n+1} at the receivers
-    assert np.array_equal(tr, got[4, 512, :])
+    assert same_bits(tr, got[4, 512, :])
