@@ -276,6 +276,15 @@ int record_receivers(const fd_grid* g, const float* u, const int64_t* rec_off,
  * A NULL face is skipped.  Faces need n >= 4 on their axis (else FD_EINVAL). */
 int halo_pack(const fd_grid* g, const float* u, float* const face[6], void* stream);
 
+/* S1 + S6 in one launch: halo_pack(g, u, face) and record_receivers(g, u,
+ * rec_off, nrec, trace_row), the faces and the receiver row of the same u (the
+ * end of a step: the data the next exchange sends and the trace row n).  Same
+ * arguments, layouts and errors as the two calls; nrec == 0 packs only.  Two
+ * launches instead of one where the faces cannot take 16-byte accesses. */
+int fd_halo_pack_record(const fd_grid* g, const float* u, float* const face[6],
+                        const int64_t* rec_off, int32_t nrec, float* trace_row,
+                        void* stream);
+
 /* S3: write six receive buffers (same layouts as halo_pack) into the face
  * halos of u: face[0] (-x, from the -x neighbour's +x face) fills
  * i = -4+q, face[1] (+x) fills i = nx+q, and likewise for y and z.  Edges and

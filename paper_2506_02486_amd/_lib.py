@@ -92,6 +92,7 @@ SIGNATURES = {
     "inject_source": (C.c_int, [_G, _P, _P, _S, _i32, _i32, _i32, _f32, _P]),
     "record_receivers": (C.c_int, [_G, _P, _P, _i32, _P, _P]),
     "halo_pack": (C.c_int, [_G, _P, C.POINTER(_P), _P]),
+    "fd_halo_pack_record": (C.c_int, [_G, _P, C.POINTER(_P), _P, _i32, _P, _P]),
     "halo_unpack": (C.c_int, [_G, _P, C.POINTER(_P), _P]),
     "fd_adjoint_step": (C.c_int, [_G, _P, _P, _P, _P, _S, _P, _P, C.POINTER(fd_source), _P]),
     "fd_scatter_add": (C.c_int, [_G, _P, _P, _P, _i32, _P]),

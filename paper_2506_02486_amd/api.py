@@ -231,6 +231,21 @@ def halo_pack(grid: Grid, u, faces, stream=None):
           "halo_pack")
 
 
+def halo_pack_record(grid: Grid, u, faces, rec_off: torch.Tensor | None = None,
+                     trace_row: torch.Tensor | None = None, stream=None):
+    """halo_pack and record_receivers of the same u in one launch
+    (fd_halo_pack_record); without receivers it only packs."""
+    grid.check(u, "u")
+    n = 0
+    if rec_off is not None and rec_off.numel():
+        _check_points("halo_pack_record", rec_off, trace_row)
+        n = rec_off.numel()
+    check(lib().fd_halo_pack_record(grid.ref, u.data_ptr(), _faces(faces, grid),
+                                    rec_off.data_ptr() if n else None, n,
+                                    trace_row.data_ptr() if n else None, _stream(stream)),
+          "fd_halo_pack_record")
+
+
 def halo_unpack(grid: Grid, u, faces, stream=None):
     grid.check(u, "u")
     check(lib().halo_unpack(grid.ref, u.data_ptr(), _faces(faces, grid), _stream(stream)),

@@ -378,11 +378,14 @@ static bool face_sets_overlap(const fd_grid* g, const float* const a[6], const f
 }
 
 // One step of the exchange form; arguments already checked.
+// One exchange step; with receivers (nrec > 0) the receiver row of un is taken in
+// the launch that packs its faces.
 static hipError_t step_exchange(const Geo& geo, const Coef& c, const float* up, float* u,
                                 float* un, const float* q, const float* ex, const float* ey,
                                 const float* ez, const fd_source* src,
                                 const float* const face_in[6], float* const face_out[6],
-                                hipStream_t s) {
+                                hipStream_t s, const int64_t* rec_off = nullptr, int nrec = 0,
+                                float* row = nullptr) {
   hipError_t e = hipSuccess;
   if (exchange_fits(geo) && face_in && face_out && face_in[0] && face_in[1] && face_out[0] &&
       face_out[1]) {
@@ -395,12 +398,13 @@ static hipError_t step_exchange(const Geo& geo, const Coef& c, const float* up, 
     e = launch_unpack(geo, u, in_yz, s);
     if (e == hipSuccess)
       e = launch_step_exchange(geo, c, up, u, un, q, ex, ey, ez, src, in_x, out_x, s);
-    if (e == hipSuccess) e = launch_pack(geo, un, out_yz, s);
+    if (e == hipSuccess) e = launch_pack_record(geo, un, out_yz, rec_off, nrec, row, s);
     return e;
   }
   if (face_in) e = launch_unpack(geo, u, face_in, s);
   if (e == hipSuccess) e = launch_step(geo, c, up, u, un, q, ex, ey, ez, src, s);
-  if (e == hipSuccess && face_out) e = launch_pack(geo, un, face_out, s);
+  if (e == hipSuccess && face_out) e = launch_pack_record(geo, un, face_out, rec_off, nrec, row, s);
+  else if (e == hipSuccess && nrec > 0) e = launch_record(un, rec_off, nrec, row, s);
   return e;
 }
 
@@ -498,18 +502,22 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
       src.w = run->wavelet[n];
     }
     const fd_source* sp_src = run->wavelet ? &src : nullptr;
+    // the receiver row of u^{n+1} is taken in the launch that packs its faces
+    float* row = run->nrec ? run->traces + (int64_t)n * run->nrec : nullptr;
     if (nsend2) {
-      e = step_exchange(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, recv, nxt, s);
+      e = step_exchange(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, recv, nxt, s,
+                        run->rec_off, run->nrec, row);
       float** t = cur;
       cur = nxt;
       nxt = t;
     } else {
       if (nsend) e = launch_unpack(geo, u, recv, s);
       if (e == hipSuccess) e = launch_step(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, s);
-      if (e == hipSuccess && nsend) e = launch_pack(geo, un, cur, s);
+      if (e == hipSuccess && nsend)
+        e = launch_pack_record(geo, un, cur, run->rec_off, run->nrec, row, s);
+      else if (e == hipSuccess && run->nrec)
+        e = launch_record(un, run->rec_off, run->nrec, row, s);
     }
-    if (e == hipSuccess && run->nrec)
-      e = launch_record(un, run->rec_off, run->nrec, run->traces + (int64_t)n * run->nrec, s);
     if (e != hipSuccess) {
       run->u_prev = up;
       run->u = u;
@@ -577,6 +585,21 @@ int halo_pack(const fd_grid* g, const float* u, float* const face[6], void* stre
   rc = check_faces(g, (const void* const*)face, "halo_pack");
   if (rc) return rc;
   return check_hip(launch_pack(make_geo(g), u, face, as_stream(stream)), "halo_pack launch");
+}
+
+int fd_halo_pack_record(const fd_grid* g, const float* u, float* const face[6],
+                        const int64_t* rec_off, int32_t nrec, float* trace_row, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!u) return fail(FD_EINVAL, "fd_halo_pack_record: u is NULL");
+  rc = check_faces(g, (const void* const*)face, "fd_halo_pack_record");
+  if (rc) return rc;
+  if (nrec < 0) return fail(FD_EINVAL, "fd_halo_pack_record: nrec < 0");
+  if (nrec > 0 && (!rec_off || !trace_row))
+    return fail(FD_EINVAL, "fd_halo_pack_record: NULL receiver array");
+  return check_hip(launch_pack_record(make_geo(g), u, face, rec_off, nrec, trace_row,
+                                      as_stream(stream)),
+                   "fd_halo_pack_record launch");
 }
 
 int halo_unpack(const fd_grid* g, float* u, const float* const face[6], void* stream) {

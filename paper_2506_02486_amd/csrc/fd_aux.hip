@@ -1,6 +1,8 @@
 // fd_aux.hip -- the small kernels around the stencil: halo face pack/unpack,
 // source injection, receiver sampling, adjoint residual scatter, model prep
 // (vdt2 and max velocity) and the gradient's change of variable.
+#include <algorithm>
+
 #include "fd_internal.h"
 
 namespace fd {
@@ -118,6 +120,24 @@ __device__ __forceinline__ long long face4_at(const Geo& g, int face, unsigned e
 
 __global__ void __launch_bounds__(BS) pack4_kernel(Geo g, const float* __restrict__ u, Faces f) {
   const int face = blockIdx.y;
+  float4* __restrict__ dst = reinterpret_cast<float4*>(f.p[face]);
+  if (!dst) return;
+  const unsigned n4 = (unsigned)(face_count(g, face) >> 2);
+  for (unsigned e = blockIdx.x * BS + threadIdx.x; e < n4; e += gridDim.x * BS)
+    dst[e] = *reinterpret_cast<const float4*>(u + face4_at(g, face, e, false));
+}
+
+// pack4_kernel with a seventh row of blocks that samples the receivers
+// (out[r] = u[off[r]]), so a step's pack and receiver row take one launch.
+__global__ void __launch_bounds__(BS) pack4_record_kernel(Geo g, const float* __restrict__ u,
+                                                          Faces f,
+                                                          const int64_t* __restrict__ off,
+                                                          int n, float* __restrict__ out) {
+  const int face = blockIdx.y;
+  if (face == 6) {
+    for (int r = blockIdx.x * BS + threadIdx.x; r < n; r += gridDim.x * BS) out[r] = u[off[r]];
+    return;
+  }
   float4* __restrict__ dst = reinterpret_cast<float4*>(f.p[face]);
   if (!dst) return;
   const unsigned n4 = (unsigned)(face_count(g, face) >> 2);
@@ -324,6 +344,25 @@ hipError_t launch_pack(const Geo& g, const float* u, float* const face[6], hipSt
     hipLaunchKernelGGL(pack4_kernel, dim3(blocks_for(mx / 4, 4096), 6), dim3(BS), 0, s, g, u, f);
   else
     hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(mx, 4096), 6), dim3(BS), 0, s, g, u, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_record(const Geo& g, const float* u, float* const face[6],
+                              const int64_t* off, int n, float* out, hipStream_t s) {
+  if (n <= 0) return launch_pack(g, u, face, s);
+  long long mx = 0;
+  Faces f;
+  for (int i = 0; i < 6; ++i) {
+    f.p[i] = face[i];
+    const long long c = i < 2 ? 4LL * g.ny * g.nz : (i < 4 ? 4LL * g.nx * g.nz : 4LL * g.nx * g.ny);
+    if (face[i] && c > mx) mx = c;
+  }
+  if (mx == 0 || !vec4_ok(g, u, reinterpret_cast<const void* const*>(face))) {
+    const hipError_t e = launch_pack(g, u, face, s);
+    return e == hipSuccess ? launch_record(u, off, n, out, s) : e;
+  }
+  const unsigned bx = std::max(blocks_for(mx / 4, 4096), (unsigned)((n + BS - 1) / BS));
+  hipLaunchKernelGGL(pack4_record_kernel, dim3(bx, 7), dim3(BS), 0, s, g, u, f, off, n, out);
   return hipGetLastError();
 }
 

@@ -137,6 +137,10 @@ hipError_t launch_record(const float* u, const int64_t* off, int n, float* out,
 hipError_t launch_scatter_add(float* a, const int64_t* off, const float* vals, int n,
                               hipStream_t s);
 hipError_t launch_pack(const Geo& g, const float* u, float* const face[6], hipStream_t s);
+// launch_pack and launch_record(u, off, n, out) in one launch where the faces
+// take the 16-byte form, else the two launches
+hipError_t launch_pack_record(const Geo& g, const float* u, float* const face[6],
+                              const int64_t* off, int n, float* out, hipStream_t s);
 hipError_t launch_unpack(const Geo& g, float* u, const float* const face[6], hipStream_t s);
 // from_m: the input is squared slowness m and vdt2 = dt^2/m; else velocity v and
 // vdt2 = (v dt)^2

@@ -173,6 +173,14 @@ def test_halo_and_adjoint_argument_checks(L):
     assert L.halo_unpack(C.byref(small), FAKE, faces, None) == EINVAL
     assert L.halo_pack(C.byref(small), None, faces, None) == EINVAL
     assert L.halo_pack(C.byref(small), FAKE, None, None) == EINVAL
+    pr = L.fd_halo_pack_record
+    assert pr(C.byref(small), FAKE, faces, FAKE, 4, FAKE, None) == EINVAL  # nx < 4 on an x face
+    ok_faces = (C.c_void_p * 6)(None, None, FAKE, None, None, None)
+    assert pr(C.byref(small), None, ok_faces, FAKE, 4, FAKE, None) == EINVAL    # NULL u
+    assert pr(C.byref(small), FAKE, ok_faces, FAKE, -1, FAKE, None) == EINVAL   # nrec < 0
+    assert pr(C.byref(small), FAKE, ok_faces, None, 4, FAKE, None) == EINVAL    # NULL offsets
+    assert pr(C.byref(small), FAKE, ok_faces, FAKE, 4, None, None) == EINVAL    # NULL row
+    assert pr(None, FAKE, ok_faces, FAKE, 4, FAKE, None) == EINVAL
     g = grid(L)
     n = L.fd_grid_elems(C.byref(g)) * 4
     a, b, c, q, u, gg = (FAKE + i * 4 * n for i in range(6))

@@ -287,6 +287,38 @@ def test_resume_is_bitwise():
     assert same_bits(a.state()[1], b.state()[1])
 
 
+@pytest.mark.parametrize("nx,ny,nz", [(70, 9, 13), (72, 9, 13), (8, 5, 4), (128, 40, 33)])
+def test_pack_record_equals_pack_and_record(nx, ny, nz):
+    """fd_halo_pack_record (one launch where the faces take 16-byte accesses, two
+    otherwise) writes the same faces and receiver row as halo_pack and
+    record_receivers, with all faces, only the y/z faces, none, and no receivers."""
+    g = api.Grid(nx, ny, nz)
+    u = _random_state(g, 5)[0]
+    rng = np.random.default_rng(3)
+    ijk = np.stack([rng.integers(0, m, 300) for m in (nx, ny, nz)], axis=1).astype(np.int32)
+    off = torch.from_numpy(g.offsets(ijk)).cuda()
+    for keep in (range(6), range(2, 6), ()):
+        want, got = api.face_buffers(g), api.face_buffers(g)
+        for f in range(6):
+            if f not in keep:
+                want[f] = got[f] = None
+        row_want = torch.full((300,), -1.0, device="cuda")
+        row_got = torch.full((300,), -1.0, device="cuda")
+        if keep:
+            api.halo_pack(g, u, want)
+        api.record_receivers(g, u, off, row_want)
+        api.halo_pack_record(g, u, got, off, row_got)
+        assert same_bits(row_got, row_want)
+        for a, b in zip(got, want):
+            assert (a is None and b is None) or same_bits(a, b)
+        empty = api.face_buffers(g)
+        api.halo_pack_record(g, u, empty)  # no receivers: the pack alone
+        ref = api.face_buffers(g)
+        api.halo_pack(g, u, ref)
+        for a, b in zip(empty, ref):
+            assert same_bits(a, b)
+
+
 @pytest.mark.parametrize("nx,ny,nz", [(70, 9, 13), (72, 9, 13), (8, 5, 4)])
 def test_pack_unpack_bit_exact(nx, ny, nz):
     """nx = 70 takes the scalar kernels; nx a multiple of 4 the 16-byte ones."""
