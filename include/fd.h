@@ -238,7 +238,10 @@ int fd_step_exchange(const fd_grid* g, const float* u_prev, float* u, float* u_n
  * pointers are rotated so u_prev, u hold the last two states.  wavelet is a
  * host array of nt floats, read before the call returns; traces is a device
  * array of nt*nrec floats (may be NULL when nt == 0); rec_off device int64
- * offsets. */
+ * offsets (needed whenever nrec > 0).  With rec_map set, a step without faces
+ * (or whose faces the stencil cannot exchange itself) takes its receiver row in
+ * the stencil launch; with faces the row is taken in the pack launch.  Same bits
+ * either way. */
 typedef struct fd_run {
   float* u_prev;
   float* u;
@@ -253,8 +256,20 @@ typedef struct fd_run {
   float* traces;                 /* device, nt*nrec */
   float* send[6];                /* device face buffers, or all NULL (no exchange) */
   float* send2[6];               /* second face set (one-kernel steps), or all NULL */
+  const int32_t* rec_map;        /* device, optional: receivers on plane rec_k, map from
+                                    fd_receiver_plane_map; the forward kernel then writes
+                                    the trace row itself where it takes no faces */
+  int32_t rec_k;
 } fd_run;
 int fd_forward_run(const fd_grid* g, fd_run* run, void* stream);
+
+/* Host helper for fd_run.rec_map: when all nrec >= 1 receivers (rec_ijk: 3*nrec
+ * interior (i,j,k) triples) lie on one z plane at distinct (i,j), fills map
+ * (host, nx*ny int32) with map[j*nx + i] = r for receiver r and -1 elsewhere,
+ * sets *k_out to the plane and returns FD_OK; else FD_EINVAL (the receivers
+ * are then sampled by a separate launch). */
+int fd_receiver_plane_map(const fd_grid* g, const int32_t* rec_ijk, int32_t nrec,
+                          int32_t* map, int32_t* k_out);
 
 /* S5: u_next[s] += vdt2[s] * w / (1+eta[s]) at interior point s = (i,j,k). */
 int inject_source(const fd_grid* g, float* u_next, const float* vdt2,

@@ -49,7 +49,7 @@ class fd_run(C.Structure):
                 ("vdt2", C.c_void_p), ("sponge", fd_sponge), ("nt", C.c_int32),
                 ("src", C.c_int32 * 3), ("wavelet", C.c_void_p), ("nrec", C.c_int32),
                 ("rec_off", C.c_void_p), ("traces", C.c_void_p), ("send", C.c_void_p * 6),
-                ("send2", C.c_void_p * 6)]
+                ("send2", C.c_void_p * 6), ("rec_map", C.c_void_p), ("rec_k", C.c_int32)]
 
 
 class FDError(RuntimeError):
@@ -89,6 +89,7 @@ SIGNATURES = {
     "fd_step_exchange": (C.c_int, [_G, _P, _P, _P, _P, _S, C.POINTER(fd_source),
                                    C.POINTER(_P), C.POINTER(_P), _P]),
     "fd_forward_run": (C.c_int, [_G, C.POINTER(fd_run), _P]),
+    "fd_receiver_plane_map": (C.c_int, [_G, _P, _i32, _P, C.POINTER(_i32)]),
     "inject_source": (C.c_int, [_G, _P, _P, _S, _i32, _i32, _i32, _f32, _P]),
     "record_receivers": (C.c_int, [_G, _P, _P, _i32, _P, _P]),
     "halo_pack": (C.c_int, [_G, _P, C.POINTER(_P), _P]),

@@ -357,9 +357,35 @@ def step_launch(grid: Grid) -> dict:
 
 # ----------------------------------------------------------------- forward model
 
+class ReceiverPlane:
+    """Receivers on one z plane as the forward kernel samples them itself
+    (fd_receiver_plane_map): ``map`` (device int32, nx*ny) and the plane ``k``."""
+
+    def __init__(self, map_: torch.Tensor, k: int):
+        self.map = map_
+        self.k = int(k)
+
+
+def receiver_plane(grid: Grid, rec_ijk: np.ndarray, device="cuda") -> ReceiverPlane | None:
+    """The plane map of receivers that all lie on one z plane at distinct points, or
+    None (they are then sampled by a separate launch)."""
+    ijk = np.ascontiguousarray(rec_ijk, dtype=np.int32).reshape(-1, 3)
+    if ijk.shape[0] == 0:
+        return None
+    m = np.empty(grid.nx * grid.ny, dtype=np.int32)
+    k = C.c_int32()
+    rc = lib().fd_receiver_plane_map(grid.ref, ijk.ctypes.data, ijk.shape[0], m.ctypes.data,
+                                     C.byref(k))
+    if rc == _lib.FD_EINVAL:
+        return None
+    check(rc, "fd_receiver_plane_map")
+    return ReceiverPlane(torch.from_numpy(m).to(device), k.value)
+
+
 def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: int, src=None,
                 wavelet=None, rec_off: torch.Tensor | None = None,
-                traces: torch.Tensor | None = None, send=None, send2=None, stream=None):
+                traces: torch.Tensor | None = None, send=None, send2=None, stream=None,
+                rec_plane: ReceiverPlane | None = None):
     """``nt`` steps in the library's native loop (fd_forward_run): per step unpack of
     ``send`` into the opposite halos (loopback; skipped when ``send`` is None), the
     fused update with the source ``src`` at amplitude ``wavelet[s]``, pack into
@@ -367,10 +393,19 @@ def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: 
     each step is one fd_step_exchange and the sets alternate.  Returns the rotated
     ``(u_prev, u, u_next)``: u^{n+nt-1}, u^{n+nt} and the spare array; with
     ``send2`` it returns ``(u_prev, u, u_next, send, send2)``, ``send`` holding the
-    faces of the new u."""
+    faces of the new u.  ``rec_plane`` (from ``receiver_plane`` of the same receivers
+    as ``rec_off``) lets the stencil launch take the receiver row where no faces are
+    packed."""
     for n, t in (("u_prev", u_prev), ("u", u), ("u_next", u_next), ("vdt2", vdt2)):
         grid.check(t, n)
     r = _lib.fd_run()
+    if rec_plane is not None:
+        m = rec_plane.map
+        if (m.dtype != torch.int32 or not m.is_cuda or not m.is_contiguous()
+                or m.numel() != grid.nx * grid.ny):
+            raise TypeError("forward_run: rec_plane map must be a device int32 nx*ny array")
+        r.rec_map = m.data_ptr()
+        r.rec_k = rec_plane.k
     bufs = {t.data_ptr(): t for t in (u_prev, u, u_next)}
     r.u_prev, r.u, r.u_next = u_prev.data_ptr(), u.data_ptr(), u_next.data_ptr()
     r.vdt2 = vdt2.data_ptr()
@@ -461,8 +496,11 @@ class Simulation:
         rec = self.geom.rec
         if rec is not None and len(rec):
             self.rec_off = torch.from_numpy(g.offsets(rec)).to(device)
+            # receivers on one plane: the native loops sample them in the stencil launch
+            self.rec_plane = receiver_plane(g, rec, device)
         else:
             self.rec_off = None
+            self.rec_plane = None
 
     @property
     def nrec(self) -> int:
@@ -536,7 +574,8 @@ class Simulation:
             src=self.geom.src if w is not None else None, wavelet=w, rec_off=self.rec_off,
             traces=traces if self.rec_off is not None else None,
             send=self.send if self.exchange else None,
-            send2=self.send2 if self.exchange and one_kernel else None, stream=stream)
+            send2=self.send2 if self.exchange and one_kernel else None, stream=stream,
+            rec_plane=self.rec_plane)
         self.u_prev, self.u, self.u_next = out[:3]
         if len(out) == 5:
             self.send, self.send2 = out[3], out[4]

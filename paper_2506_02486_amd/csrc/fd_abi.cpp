@@ -457,6 +457,8 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
   if (run->nt < 0) return fail(FD_EINVAL, "fd_forward_run: nt < 0");
   if (run->nrec < 0 || (run->nrec > 0 && run->nt > 0 && (!run->rec_off || !run->traces)))
     return fail(FD_EINVAL, "fd_forward_run: bad receivers");
+  if (run->rec_map && (run->rec_k < 0 || run->rec_k >= g->nz))
+    return fail(FD_EINVAL, "fd_forward_run: receiver plane %d outside the interior", run->rec_k);
   if (run->wavelet && (run->src[0] < 0 || run->src[0] >= g->nx || run->src[1] < 0 ||
                        run->src[1] >= g->ny || run->src[2] < 0 || run->src[2] >= g->nz))
     return fail(FD_EINVAL, "fd_forward_run: source outside the interior");
@@ -502,7 +504,8 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
       src.w = run->wavelet[n];
     }
     const fd_source* sp_src = run->wavelet ? &src : nullptr;
-    // the receiver row of u^{n+1} is taken in the launch that packs its faces
+    // the receiver row of u^{n+1} is taken in the launch that packs its faces, or
+    // with a receiver plane map and no faces by the stencil launch itself
     float* row = run->nrec ? run->traces + (int64_t)n * run->nrec : nullptr;
     if (nsend2) {
       e = step_exchange(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, recv, nxt, s,
@@ -511,11 +514,15 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
       cur = nxt;
       nxt = t;
     } else {
+      const RecPlane rp{run->rec_map, run->rec_k, row};
+      const bool in_kernel = run->rec_map && run->nrec > 0 && !nsend;
       if (nsend) e = launch_unpack(geo, u, recv, s);
-      if (e == hipSuccess) e = launch_step(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, s);
+      if (e == hipSuccess)
+        e = launch_step(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, s,
+                        in_kernel ? &rp : nullptr);
       if (e == hipSuccess && nsend)
         e = launch_pack_record(geo, un, cur, run->rec_off, run->nrec, row, s);
-      else if (e == hipSuccess && run->nrec)
+      else if (e == hipSuccess && run->nrec && !in_kernel)
         e = launch_record(un, run->rec_off, run->nrec, row, s);
     }
     if (e != hipSuccess) {
@@ -534,6 +541,28 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
   run->u_next = un;
   if (cur != run->send)  // ping-pong: run->send holds the faces of the final u
     for (int f = 0; f < 6; ++f) std::swap(run->send[f], run->send2[f]);
+  return FD_OK;
+}
+
+int fd_receiver_plane_map(const fd_grid* g, const int32_t* rec_ijk, int32_t nrec, int32_t* map,
+                          int32_t* k_out) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!rec_ijk || !map || !k_out) return fail(FD_EINVAL, "fd_receiver_plane_map: NULL argument");
+  if (nrec < 1) return fail(FD_EINVAL, "fd_receiver_plane_map: no receivers");
+  const int64_t nxy = (int64_t)g->nx * g->ny;
+  for (int64_t q = 0; q < nxy; ++q) map[q] = -1;
+  const int32_t k = rec_ijk[2];
+  for (int32_t r = 0; r < nrec; ++r) {
+    const int32_t i = rec_ijk[3 * r], j = rec_ijk[3 * r + 1], kr = rec_ijk[3 * r + 2];
+    if (i < 0 || i >= g->nx || j < 0 || j >= g->ny || kr < 0 || kr >= g->nz)
+      return fail(FD_EINVAL, "fd_receiver_plane_map: receiver %d outside the interior", r);
+    if (kr != k) return fail(FD_EINVAL, "fd_receiver_plane_map: receivers on more than one plane");
+    int32_t& m = map[(int64_t)j * g->nx + i];
+    if (m >= 0) return fail(FD_EINVAL, "fd_receiver_plane_map: receivers %d and %d coincide", m, r);
+    m = r;
+  }
+  *k_out = k;
   return FD_OK;
 }
 

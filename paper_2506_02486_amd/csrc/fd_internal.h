@@ -69,12 +69,22 @@ struct BatchStep {
   float w[MAX_BATCH_SLOTS];  // its source amplitude for this step
 };
 
+// Receivers that all lie on one z plane k: map[j * nx + i] is the index of the
+// receiver at (i, j, k) or -1 (device, nx * ny), row the trace row they fill.
+struct RecPlane {
+  const int32_t* map;
+  int k;
+  float* row;
+};
+
 // ------------------------------------------------------------ launchers
 // All validate nothing (the ABI layer has) and return a HIP error code.
-// src may be NULL (no fused source term)
+// src may be NULL (no fused source term); rp (optional) has the forward kernel
+// write the receiver row of un itself
 hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float* u,
                        float* un, const float* q, const float* ex, const float* ey,
-                       const float* ez, const fd_source* src, hipStream_t s);
+                       const float* ez, const fd_source* src, hipStream_t s,
+                       const RecPlane* rp = nullptr);
 // Planes per block (z chunk) for one launch over n grids, grid i with xy[i] x-y
 // tiles and nz[i] planes, with the least modelled time; at most kc_max planes
 // (0: no limit) and at most max_blocks blocks (the longest chunk is the fallback).

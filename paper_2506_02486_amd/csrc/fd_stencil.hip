@@ -64,6 +64,11 @@ struct Params {
   // sout[1] (halo_unpack / halo_pack layouts [nz][ny][4]; all four non-NULL)
   const float* rin[2];
   float* sout[2];
+  // FWD: receivers on plane rk: rmap[j * nx + i] is the receiver index of point
+  // (i, j, rk) or -1, and rrow[r] takes u_next there (rmap NULL: none)
+  const int32_t* rmap;
+  int rk;
+  float* rrow;
 };
 
 __device__ __forceinline__ int remap_block(int bid, int nb) {
@@ -87,7 +92,8 @@ __device__ __forceinline__ float ld_nt(const char* base, unsigned boff) {
 
 // The per-block work of every stencil kernel: tile (bx, by) of the x-y plane,
 // z-chunk bz, of the grid and operands described by p.
-template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY, bool XCH>
+template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY, bool XCH,
+          bool REC = false>
 __device__ __forceinline__ void stencil_block(const Params& p, const int bx, const int by,
                                               const int bz) {
   constexpr int TX = TXT;
@@ -385,6 +391,9 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
     const bool damped = SPONGE && (MODE == ADJ || tile_sponge || ezk != 0.f);
     // block-uniform: the source point lies in this tile-plane
     const bool src_plane = src_tile && k == p.sk;
+    // block-uniform: this plane holds the receivers (REC: a separate instantiation,
+    // so the kernels without it keep their registers)
+    const bool rec_plane = REC && MODE == FWD && k == p.rk;
     char* ok = O0 + (long long)k * szb;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -421,6 +430,10 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
           }
           __builtin_nontemporal_store(v, dst);
           if (XCH && xedge && sx_ptr) sx_ptr[((unsigned)k * (unsigned)ny + (unsigned)(yr + r)) * 4u] = v;
+          if (rec_plane) {
+            const int rr = p.rmap[(yr + r) * nx + x];
+            if (rr >= 0) p.rrow[rr] = v;
+          }
         } else if (MODE == ADJ) {
           const float c = cq[0][r];
           float v;
@@ -497,12 +510,12 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
 }
 
 template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY = (MODE == FWD),
-          bool XCH = false>
+          bool XCH = false, bool REC = false>
 __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
   const int logical = remap_block(blockIdx.x, gridDim.x);
   const int bx = logical % p.tiles_x;
   const int rest = logical / p.tiles_x;
-  stencil_block<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY, XCH>(p, bx, rest % p.tiles_y,
+  stencil_block<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY, XCH, REC>(p, bx, rest % p.tiles_y,
                                                              rest / p.tiles_y);
 }
 
@@ -534,11 +547,14 @@ __global__ void __launch_bounds__(TXT * NY) batched_kernel(const BatchShot* __re
   p.sj = b.sj;
   p.sk = b.sk;
   p.sw = a.w[t.x];
+  p.rmap = nullptr;
+  p.rk = -1;
+  p.rrow = nullptr;
   stencil_block<TXT, NY, RY, FWD, true, true, true, false>(p, t.y, t.z, t.w);
 }
 
 template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE = false,
-          bool EARLY = (MODE == FWD), bool XCH = false>
+          bool EARLY = (MODE == FWD), bool XCH = false, bool REC = false>
 hipError_t launch_mode(Params p, hipStream_t st) {
   const LaunchShape sh = stencil_shape(p.g, TXT, NY * RY, (TXT * NY + 63) / 64);
   p.tiles_x = sh.tiles_x;
@@ -546,7 +562,7 @@ hipError_t launch_mode(Params p, hipStream_t st) {
   p.kchunk = sh.kchunk;
   const long long nb = (long long)sh.tiles_x * sh.tiles_y * sh.zchunks;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((stencil_kernel<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY, XCH>), dim3((unsigned)nb),
+  hipLaunchKernelGGL((stencil_kernel<TXT, NY, RY, MODE, SPONGE, FUSE, EARLY, XCH, REC>), dim3((unsigned)nb),
                      dim3(TXT, NY), 0, st, p);
   return hipGetLastError();
 }
@@ -563,6 +579,9 @@ Params base_params(const Geo& g, const Coef& c, const float* ex, const float* ey
   p.sj = -1;
   p.sk = -1;
   p.sw = 0.f;
+  p.rmap = nullptr;
+  p.rk = -1;
+  p.rrow = nullptr;
   return p;
 }
 
@@ -574,10 +593,14 @@ constexpr int BATCH_TX = 64;      // tile width of the batched kernel (FWD_SHAPE
 constexpr int BATCH_TY = 8 * 4;   // tile height of the batched kernel (FWD_SHAPE)
 
 // The forward kernel in one tile shape: x faces exchanged inside (always with the
-// source epilogue, a negative source index meaning none), or the source fused, or
-// the plain update.
+// source epilogue, a negative source index meaning none), or the source and the
+// receiver row fused, or the source fused, or the plain update.
 template <int TXT, int NY, int RY>
 hipError_t launch_forward(const Params& p, bool sponge, bool fuse, bool xch, hipStream_t s) {
+  if (p.rmap && !xch) {  // the receiver row written by the kernel (fused epilogue)
+    if (sponge) return launch_mode<TXT, NY, RY, FWD, true, true, true, false, true>(p, s);
+    return launch_mode<TXT, NY, RY, FWD, false, true, true, false, true>(p, s);
+  }
   if (xch) {
     if (sponge) return launch_mode<TXT, NY, RY, FWD, true, true, true, true>(p, s);
     return launch_mode<TXT, NY, RY, FWD, false, true, true, true>(p, s);
@@ -623,8 +646,14 @@ hipError_t launch_batched(const BatchShot* shots, const int4* tiles, int ntiles,
 
 hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float* u,
                        float* un, const float* q, const float* ex, const float* ey,
-                       const float* ez, const fd_source* src, hipStream_t s) {
+                       const float* ez, const fd_source* src, hipStream_t s,
+                       const RecPlane* rp) {
   Params p = base_params(g, c, ex, ey, ez);
+  if (rp && rp->map) {
+    p.rmap = rp->map;
+    p.rk = rp->k;
+    p.rrow = rp->row;
+  }
   p.f = u;
   p.fq = u;
   p.pa = up;
@@ -636,7 +665,8 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
     p.sk = src->k;
     p.sw = src->w;
   }
-  return launch_forward(p, ex != nullptr, src != nullptr, false, s);
+  // the receiver plane needs the fused epilogue (a negative source index: none)
+  return launch_forward(p, ex != nullptr, src != nullptr || p.rmap != nullptr, false, s);
 }
 
 bool exchange_fits(const Geo& g) { return g.nx % BATCH_TX == 0; }

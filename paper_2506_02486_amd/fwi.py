@@ -60,6 +60,7 @@ class FWIProblem:
             self.sponge = None
         self.w = api.ricker(self.nt, self.dt, f0, t0)
         self.rec_off = torch.from_numpy(g.offsets(rec)).to(device)
+        self.rec_plane = api.receiver_plane(g, rec, device)  # sampled in the stencil launch
         self.nrec = self.rec_off.numel()
         self.src_off = torch.from_numpy(g.offsets(np.array([self.src], np.int32))).to(device)
         self.m = g.zeros(device)
@@ -91,7 +92,8 @@ class FWIProblem:
                 self.ckpt.append((up.clone(), u.clone()))
             up, u, un = api.forward_run(g, up, u, un, self.vdt2, self.sponge, e - s,
                                         src=self.src, wavelet=self.w[s:e],
-                                        rec_off=self.rec_off, traces=traces[s:e])
+                                        rec_off=self.rec_off, traces=traces[s:e],
+                                        rec_plane=self.rec_plane)
         return traces
 
     def _forward_store_all(self, traces: torch.Tensor) -> torch.Tensor:

@@ -259,6 +259,28 @@ def test_step_launch_shape(L):
     assert L.fd_step_launch(None, out) == _lib.FD_EINVAL
 
 
+def test_receiver_plane_map(L):
+    g = grid(L, 10, 6, 5)
+    ijk = np.array([[3, 2, 4], [0, 0, 4], [9, 5, 4]], np.int32)
+    m = np.empty(60, np.int32)
+    k = C.c_int32(-7)
+    assert L.fd_receiver_plane_map(C.byref(g), ijk.ctypes.data, 3, m.ctypes.data, C.byref(k)) == 0
+    want = np.full(60, -1, np.int32)
+    want[2 * 10 + 3], want[0], want[5 * 10 + 9] = 0, 1, 2
+    assert np.array_equal(m, want) and k.value == 4
+    EINVAL = _lib.FD_EINVAL
+    for bad in ([[3, 2, 4], [0, 0, 3]],   # two planes
+                [[3, 2, 4], [3, 2, 4]],   # the same point twice
+                [[10, 2, 4]],             # outside the interior
+                [[3, 2, 5]]):
+        b = np.array(bad, np.int32)
+        assert L.fd_receiver_plane_map(C.byref(g), b.ctypes.data, len(bad), m.ctypes.data,
+                                       C.byref(k)) == EINVAL
+    assert L.fd_receiver_plane_map(C.byref(g), ijk.ctypes.data, 0, m.ctypes.data, C.byref(k)) == EINVAL
+    assert L.fd_receiver_plane_map(C.byref(g), None, 3, m.ctypes.data, C.byref(k)) == EINVAL
+    assert L.fd_receiver_plane_map(C.byref(g), ijk.ctypes.data, 3, None, C.byref(k)) == EINVAL
+
+
 def test_shot_footprint_and_server_argument_checks(L):
     d = _lib.fd_shot_desc()
     d.nx, d.ny, d.nz, d.nt = 256, 256, 256, 500

@@ -287,6 +287,36 @@ def test_resume_is_bitwise():
     assert same_bits(a.state()[1], b.state()[1])
 
 
+@pytest.mark.parametrize("shape,tiles", [((64, 64, 64), 0), ((70, 33, 29), 1), ((70, 33, 29), 2),
+                                         ((256, 100, 48), 0)])
+@pytest.mark.parametrize("faces", [0, 1, 2])
+def test_receiver_plane_in_stencil_matches_separate_record(shape, tiles, faces):
+    """fd_forward_run with a receiver plane map (the stencil launch writes the trace
+    row where no faces are packed) gives the bits of the separate receiver launch,
+    for Dirichlet runs (faces=0) and the loopback exchange in both forms."""
+    nx, ny, nz = shape
+    v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
+    rng = np.random.default_rng(11)
+    pts = rng.choice(nx * ny, size=min(700, nx * ny), replace=False)
+    rec = np.stack([pts % nx, pts // nx, np.full(pts.size, nz // 3)], axis=1).astype(np.int32)
+    geom = api.Geometry(src=(nx // 2, ny // 2, nz // 2), rec=rec)
+    api.set_tiles(tiles)
+    try:
+        out = []
+        for use_map in (False, True):
+            sim = api.Simulation(v, sponge_width=5, geom=geom,
+                                 exchange="loopback" if faces else None)
+            assert sim.rec_plane is not None and sim.rec_plane.k == nz // 3
+            if not use_map:
+                sim.rec_plane = None
+            tr = sim.run(31, mode="native" if faces != 2 else "native-fused")
+            out.append((tr.clone(), sim.state()[0].clone(), sim.state()[1].clone()))
+        for a, b in zip(*out):
+            assert same_bits(a, b)
+    finally:
+        api.set_tiles(0)
+
+
 @pytest.mark.parametrize("nx,ny,nz", [(70, 9, 13), (72, 9, 13), (8, 5, 4), (128, 40, 33)])
 def test_pack_record_equals_pack_and_record(nx, ny, nz):
     """fd_halo_pack_record (one launch where the faces take 16-byte accesses, two
