@@ -147,8 +147,10 @@ class ShotServer:
 
 
 class PlainLoop:
-    """The comparison loop: each shot alone, in order, with the same kernels
-    (fd_step_fused + record_receivers) on buffers sized for the largest grid."""
+    """The comparison loop: each shot alone, in order, with the same kernels in the
+    library's native step loop (fd_forward_run: the fused update, the receiver row
+    taken by the stencil launch when the receivers share one plane) on buffers sized
+    for the largest grid."""
 
     def __init__(self, max_shape, d=(10.0, 10.0, 10.0), device="cuda"):
         nx, ny, nz = max_shape
@@ -169,11 +171,11 @@ class PlainLoop:
             vmax = shot.sponge_vmax if shot.sponge_vmax > 0 else float(shot.v.max().item())
             sp = api.Sponge(g, shot.sponge_width, vmax, shot.dt, device=self.device)
         w = api.ricker(shot.nt, shot.dt, shot.f0, shot.t0)
-        off = torch.from_numpy(g.offsets(shot.rec)).to(self.device) if shot.nrec else None
+        off = plane = None
+        if shot.nrec:
+            off = torch.from_numpy(g.offsets(shot.rec)).to(self.device)
+            plane = api.receiver_plane(g, shot.rec, self.device)
         tr = torch.zeros((shot.nt, max(shot.nrec, 1)), dtype=torch.float32, device=self.device)
-        for n in range(shot.nt):
-            api.step_fused(g, up, u, un, q, sp, (shot.src, float(w[n])), None)
-            if off is not None:
-                api.record_receivers(g, un, off, tr[n])
-            up, u, un = u, un, up
+        api.forward_run(g, up, u, un, q, sp, shot.nt, src=shot.src, wavelet=w, rec_off=off,
+                        traces=tr if off is not None else None, rec_plane=plane)
         return tr[:, :shot.nrec].cpu().numpy()

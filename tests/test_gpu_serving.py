@@ -98,6 +98,20 @@ def test_admission_cap_runs_shots_in_turn(model):
         assert same_bits(tr, solo(shot))
 
 
+def test_plain_loop_equals_server(model):
+    """The comparison loop of the serving benchmark (one shot at a time in the native
+    step loop, the receiver row taken by the stencil) gives the server's bits."""
+    shots = make_shots(model, 5, nt=30, seed=9)
+    plain = serving.PlainLoop((72, 72, 72))
+    want = [plain.run(s) for s in shots]
+    with serving.ShotServer(2 << 30, max_slots=8) as srv:
+        ids = [srv.submit(s) for s in shots]
+        got = [srv.wait(i) for i in ids]
+    for (code, tr, _), w in zip(got, want):
+        assert code == _lib.FD_OK
+        assert same_bits(tr, w)
+
+
 def test_small_shots_match_oracle(model):
     v, _, dt, vmax = model
     shots = sorted(make_shots(model, 8, nt=40), key=lambda s: np.prod(s.shape))[:4]
