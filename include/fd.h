@@ -404,7 +404,8 @@ typedef struct fd_shot_desc {
 } fd_shot_desc;
 
 /* Arena bytes one shot occupies while active (4 padded volumes, sponge
- * tables, receiver offsets, traces); -1 for an invalid descriptor. */
+ * tables, receiver offsets, traces, and with receivers an nx*ny receiver-plane
+ * map, used when they share one z plane); -1 for an invalid descriptor. */
 int64_t fd_shot_footprint(const fd_shot_desc* d);
 
 /* Create a server over the caller-owned device arena [arena_dev,

@@ -58,7 +58,9 @@ struct BatchShot {
   const int64_t* rec;   // receiver offsets
   float* traces;        // nt x nrec
   int nrec;
-  int pad_;
+  int rk;               // receiver plane of rmap
+  const int32_t* rmap;  // receivers on one plane: [ny][nx] receiver index or -1; the
+                        // batched kernel writes their rows (NULL: batched_record does)
 };
 
 constexpr int MAX_BATCH_SLOTS = 64;

@@ -63,7 +63,7 @@ int64_t now_ns() {
 struct ShotLayout {
   fd_grid g;
   int64_t elems;
-  size_t vol, sponge, rec, traces, total;  // byte offsets and total
+  size_t vol, sponge, rec, traces, rmap, total;  // byte offsets and total
   int tiles;
 };
 
@@ -86,7 +86,9 @@ int layout_for(const fd_shot_desc* d, ShotLayout* L) {
   L->sponge = 4 * vbytes;
   L->rec = L->sponge + align_up(4 * (size_t)(d->nx + d->ny + d->nz));
   L->traces = L->rec + align_up(8 * (size_t)std::max(d->nrec, 1));
-  L->total = L->traces + align_up(4 * (size_t)d->nt * (size_t)std::max(d->nrec, 1));
+  L->rmap = L->traces + align_up(4 * (size_t)d->nt * (size_t)std::max(d->nrec, 1));
+  // receiver plane map (receivers on one z plane), nx * ny int32
+  L->total = L->rmap + (d->nrec > 0 ? align_up(4 * (size_t)d->nx * (size_t)d->ny) : 0);
   int tx, ty;
   batch_tile_shape(&tx, &ty);
   const long long t = (long long)((d->nx + tx - 1) / tx) * ((d->ny + ty - 1) / ty) *
@@ -193,6 +195,7 @@ int admit_device(Server* S, Shot* s, int slot) {
   float* sp = reinterpret_cast<float*>(blk + L.sponge);
   int64_t* rec = reinterpret_cast<int64_t*>(blk + L.rec);
   float* tr = reinterpret_cast<float*>(blk + L.traces);
+  int32_t* rmap = reinterpret_cast<int32_t*>(blk + L.rmap);
   const Geo geo = make_geo(&L.g);
   hipError_t e = hipSuccess;
   for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_zero(vol[i], L.elems, S->as);
@@ -214,7 +217,8 @@ int admit_device(Server* S, Shot* s, int slot) {
   e = launch_prepare_vdt2_view(geo, d.v_dev, d.v_ystride, d.v_zstride, vol[3], d.dt, S->as);
   if (e != hipSuccess) return check_hip(e, "shot vdt2");
   // sponge tables and receiver offsets through the pinned staging buffer
-  const size_t need = (size_t)(d.nx + d.ny + d.nz) + 2 + 2 * (size_t)std::max(d.nrec, 1);
+  const size_t need = (size_t)(d.nx + d.ny + d.nz) + 2 + 2 * (size_t)std::max(d.nrec, 1) +
+                      (d.nrec > 0 ? (size_t)d.nx * (size_t)d.ny : 0);
   if (need > S->h_stage_cap) {
     if (S->h_stage) (void)hipHostFree(S->h_stage);
     S->h_stage = nullptr;
@@ -237,6 +241,15 @@ int admit_device(Server* S, Shot* s, int slot) {
                      S->as);
   if (e == hipSuccess && d.nrec > 0)
     e = hipMemcpyAsync(rec, hrec, 8 * (size_t)d.nrec, hipMemcpyHostToDevice, S->as);
+  // receivers on one plane: the batched kernel writes their rows (no record launch)
+  int32_t plane_k = -1;
+  if (d.nrec > 0) {
+    int32_t* hmap = reinterpret_cast<int32_t*>(hrec + d.nrec);
+    if (fd_receiver_plane_map(&L.g, s->rec.data(), d.nrec, hmap, &plane_k) != FD_OK) plane_k = -1;
+    if (e == hipSuccess && plane_k >= 0)
+      e = hipMemcpyAsync(rmap, hmap, 4 * (size_t)d.nx * (size_t)d.ny, hipMemcpyHostToDevice,
+                         S->as);
+  }
   // the staging buffer is reused, and the compute stream may use the shot from
   // its next step on: all of the shot's admission work has finished after this
   if (e == hipSuccess) e = hipStreamSynchronize(S->as);
@@ -256,7 +269,8 @@ int admit_device(Server* S, Shot* s, int slot) {
   b.rec = rec;
   b.traces = tr;
   b.nrec = d.nrec;
-  b.pad_ = 0;
+  b.rk = plane_k;
+  b.rmap = plane_k >= 0 ? rmap : nullptr;
   s->w.resize(d.nt);
   fd_ricker(s->w.data(), d.nt, 0, d.dt, d.f0, d.t0);
   return FD_OK;
@@ -288,8 +302,10 @@ hipError_t upload_tables(Server* S) {
   for (int slot = 0; slot < S->max_slots; ++slot) {
     Shot* s = S->slots[slot];
     if (!s) continue;
-    h_slots[na++] = slot;
-    mr = std::max(mr, s->d.nrec);
+    if (s->d.nrec > 0 && !S->shots_host[slot].rmap) {  // rows left to batched_record
+      h_slots[na++] = slot;
+      mr = std::max(mr, s->d.nrec);
+    }
     const int bxn = (s->d.nx + tx - 1) / tx, byn = (s->d.ny + ty - 1) / ty;
     const int bzn = (s->d.nz + kc - 1) / kc;
     S->h_shots[st][slot].kchunk = kc;

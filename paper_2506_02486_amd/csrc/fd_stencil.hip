@@ -521,7 +521,8 @@ __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
 
 // Many grids in one launch: block b runs tile tiles[remap(b)] = (slot, bx, by, bz)
 // of shot `slot`, whose step is a.n[slot] (u^n in arr[n % 3]) and source
-// amplitude a.w[slot].  Every point runs exactly the code of stencil_kernel.
+// amplitude a.w[slot].  Every point runs exactly the code of stencil_kernel; a shot
+// whose receivers share one plane has its trace row written here too.
 template <int TXT, int NY, int RY>
 __global__ void __launch_bounds__(TXT * NY) batched_kernel(const BatchShot* __restrict__ shots,
                                                            const int4* __restrict__ tiles,
@@ -547,10 +548,10 @@ __global__ void __launch_bounds__(TXT * NY) batched_kernel(const BatchShot* __re
   p.sj = b.sj;
   p.sk = b.sk;
   p.sw = a.w[t.x];
-  p.rmap = nullptr;
-  p.rk = -1;
-  p.rrow = nullptr;
-  stencil_block<TXT, NY, RY, FWD, true, true, true, false>(p, t.y, t.z, t.w);
+  p.rmap = b.rmap;
+  p.rk = b.rmap ? b.rk : -1;  // no plane: the receiver epilogue never runs
+  p.rrow = b.traces + (size_t)n * (size_t)b.nrec;
+  stencil_block<TXT, NY, RY, FWD, true, true, true, false, true>(p, t.y, t.z, t.w);
 }
 
 template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE = false,
