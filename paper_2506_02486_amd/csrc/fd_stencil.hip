@@ -27,13 +27,18 @@
 // plane base (the padded corner (-4,-4) of plane k), so the address of each
 // load is one scalar base plus one 32-bit register.
 // Sponge: a block whose x-y tile lies outside the damping layer takes the
-// undamped update on planes where eta_z is zero too (a uniform branch); points
-// with eta == 0 compute the same expression on both paths.
+// undamped update on planes where eta_z is zero too (a uniform branch), and
+// inside such tiles the damped form applies only where eta != 0, so a point's
+// bits never depend on its tile.
 // Blocks are renumbered so that each of the 8 XCDs (each with its own L2) gets
 // one contiguous run of tiles: hardware dispatches block b to XCD b % 8.
 // Exchange form (XCH, fd_step_exchange): the -x/+x halos are read from receive
 // buffers and the x faces of the result written to send buffers by the lanes
 // that own them, instead of a separate unpack/pack over 16-byte row pieces.
+// Receiver plane (REC): when the receivers share one z plane, the forward
+// kernel writes their trace row at that plane from a per-point index map.
+// Tile shapes: 64 x 32 (8 waves, 4 rows per thread); 64 x 16 (2 rows per
+// thread) for small grids, where it doubles the blocks.
 #include <type_traits>
 
 #include "fd_internal.h"
