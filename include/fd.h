@@ -353,6 +353,17 @@ int fd_adjoint_step_scaled(const fd_grid* g, const float* b_nn, const float* b_n
                            const float* u_n, float* g_b, const fd_source* src,
                            void* stream);
 
+/* fd_adjoint_step_scaled followed by fd_scatter_add_scaled(b_out, res_row) of
+ * receivers that all lie on plane res_k (res_map: device nx*ny map from
+ * fd_receiver_plane_map), the residual added in the update's own launch; same
+ * bits as the two calls.  FD_EINVAL for a NULL map or row or a plane outside
+ * the interior, else as fd_adjoint_step_scaled. */
+int fd_adjoint_step_scaled_res(const fd_grid* g, const float* b_nn, const float* b_n1,
+                               float* b_out, const float* vdt2, const fd_sponge* sp,
+                               const float* u_n, float* g_b, const fd_source* src,
+                               const int32_t* res_map, int32_t res_k, const float* res_row,
+                               void* stream);
+
 /* The adjoint source in the scaled variable: b[off[r]] += vals[r] Q / (1+eta)
  * at each offset (device arrays; offsets must be interior points of g, an
  * offset outside the interior is taken with eta = 0; duplicates add). */

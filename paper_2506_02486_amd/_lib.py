@@ -100,6 +100,8 @@ SIGNATURES = {
     "fd_grad_finalize": (C.c_int, [_G, _P, _P, _f64, _P, _P]),
     "fd_adjoint_step_scaled": (C.c_int, [_G, _P, _P, _P, _P, _S, _P, _P, C.POINTER(fd_source),
                                          _P]),
+    "fd_adjoint_step_scaled_res": (C.c_int, [_G, _P, _P, _P, _P, _S, _P, _P,
+                                             C.POINTER(fd_source), _P, _i32, _P, _P]),
     "fd_scatter_add_scaled": (C.c_int, [_G, _P, _P, _P, _P, _S, _i32, _P]),
     "fd_grad_finalize_scaled": (C.c_int, [_G, _P, _P, _f64, _P, _P]),
     "fd_shot_footprint": (_i64, [C.POINTER(fd_shot_desc)]),

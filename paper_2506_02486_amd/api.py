@@ -301,9 +301,11 @@ def grad_finalize(grid: Grid, g_vdt2, vdt2, dt: float, grad_m, stream=None):
 
 
 def adjoint_step_scaled(grid: Grid, b_nn, b_n1, b_out, vdt2, sponge=None, u_n=None, g_b=None,
-                        src=None, stream=None):
+                        src=None, stream=None, res=None):
     """b_out = D (2 b_n1 - E b_nn + Q L b_n1) (the adjoint in b = Q D lambda), and
-    optionally g_b += b_n1 (L u_n + f)."""
+    optionally g_b += b_n1 (L u_n + f).  ``res = (plane, row)`` (a ReceiverPlane and
+    a device row of its receivers' values) also adds the row at the receivers as
+    scatter_add_scaled would, in the same launch (fd_adjoint_step_scaled_res)."""
     if b_nn is None or b_n1 is None or b_out is None:
         raise ValueError("adjoint_step_scaled: b_nn, b_n1 and b_out are required")
     for n, t in (("b_nn", b_nn), ("b_n1", b_n1), ("b_out", b_out), ("vdt2", vdt2),
@@ -313,6 +315,21 @@ def adjoint_step_scaled(grid: Grid, b_nn, b_n1, b_out, vdt2, sponge=None, u_n=No
     if src is not None:
         (i, j, k), w = src
         sref = C.byref(fd_source(int(i), int(j), int(k), float(w)))
+    if res is not None:
+        plane, row = res
+        m = plane.map
+        if (m.dtype != torch.int32 or not m.is_cuda or not m.is_contiguous()
+                or m.numel() != grid.nx * grid.ny):
+            raise TypeError("adjoint_step_scaled: the plane map must be a device int32 nx*ny array")
+        if (row.dtype != torch.float32 or not row.is_cuda or not row.is_contiguous()
+                or row.numel() < plane.nrec):
+            raise TypeError("adjoint_step_scaled: the row must be a contiguous device float32 "
+                            "array covering every receiver of the plane")
+        check(lib().fd_adjoint_step_scaled_res(
+            grid.ref, b_nn.data_ptr(), b_n1.data_ptr(), b_out.data_ptr(), vdt2.data_ptr(),
+            sponge_ref(sponge), _ptr(u_n), _ptr(g_b), sref, m.data_ptr(), plane.k,
+            row.data_ptr(), _stream(stream)), "fd_adjoint_step_scaled_res")
+        return
     check(lib().fd_adjoint_step_scaled(grid.ref, b_nn.data_ptr(), b_n1.data_ptr(),
                                        b_out.data_ptr(), vdt2.data_ptr(), sponge_ref(sponge),
                                        _ptr(u_n), _ptr(g_b), sref, _stream(stream)),
@@ -361,9 +378,10 @@ class ReceiverPlane:
     """Receivers on one z plane as the forward kernel samples them itself
     (fd_receiver_plane_map): ``map`` (device int32, nx*ny) and the plane ``k``."""
 
-    def __init__(self, map_: torch.Tensor, k: int):
+    def __init__(self, map_: torch.Tensor, k: int, nrec: int):
         self.map = map_
         self.k = int(k)
+        self.nrec = int(nrec)
 
 
 def receiver_plane(grid: Grid, rec_ijk: np.ndarray, device="cuda") -> ReceiverPlane | None:
@@ -379,7 +397,7 @@ def receiver_plane(grid: Grid, rec_ijk: np.ndarray, device="cuda") -> ReceiverPl
     if rc == _lib.FD_EINVAL:
         return None
     check(rc, "fd_receiver_plane_map")
-    return ReceiverPlane(torch.from_numpy(m).to(device), k.value)
+    return ReceiverPlane(torch.from_numpy(m).to(device), k.value, ijk.shape[0])
 
 
 def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: int, src=None,

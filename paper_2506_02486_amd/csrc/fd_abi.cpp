@@ -699,9 +699,9 @@ int fd_grad_finalize(const fd_grid* g, const float* g_vdt2, const float* vdt2, d
       "fd_grad_finalize launch");
 }
 
-int fd_adjoint_step_scaled(const fd_grid* g, const float* b_nn, const float* b_n1, float* b_out,
-                           const float* vdt2, const fd_sponge* sp, const float* u_n, float* g_b,
-                           const fd_source* src, void* stream) {
+static int adjoint_scaled(const fd_grid* g, const float* b_nn, const float* b_n1, float* b_out,
+                          const float* vdt2, const fd_sponge* sp, const float* u_n, float* g_b,
+                          const fd_source* src, const RecPlane* inj, void* stream) {
   int rc = check_grid(g);
   if (rc) return rc;
   if (!b_nn || !b_n1 || !b_out || !vdt2)
@@ -734,9 +734,32 @@ int fd_adjoint_step_scaled(const fd_grid* g, const float* b_nn, const float* b_n
                    "gradient launch");
     if (rc) return rc;
   }
-  // the forward update run backward in time: b_out = D (2 b_n1 - E b_nn + Q L b_n1)
-  return check_hip(launch_step(geo, c, b_nn, b_n1, b_out, vdt2, ex, ey, ez, nullptr, s),
+  // the forward update run backward in time: b_out = D (2 b_n1 - E b_nn + Q L b_n1),
+  // with inj the scaled residual row added at the receivers in the same launch
+  return check_hip(launch_step(geo, c, b_nn, b_n1, b_out, vdt2, ex, ey, ez, nullptr, s, inj),
                    "fd_adjoint_step_scaled launch");
+}
+
+int fd_adjoint_step_scaled(const fd_grid* g, const float* b_nn, const float* b_n1, float* b_out,
+                           const float* vdt2, const fd_sponge* sp, const float* u_n, float* g_b,
+                           const fd_source* src, void* stream) {
+  return adjoint_scaled(g, b_nn, b_n1, b_out, vdt2, sp, u_n, g_b, src, nullptr, stream);
+}
+
+int fd_adjoint_step_scaled_res(const fd_grid* g, const float* b_nn, const float* b_n1,
+                               float* b_out, const float* vdt2, const fd_sponge* sp,
+                               const float* u_n, float* g_b, const fd_source* src,
+                               const int32_t* res_map, int32_t res_k, const float* res_row,
+                               void* stream) {
+  if (!g) return fail(FD_EINVAL, "grid is NULL");
+  if (!res_map || !res_row)
+    return fail(FD_EINVAL, "fd_adjoint_step_scaled_res: NULL receiver map or row");
+  if (res_k < 0 || res_k >= g->nz)
+    return fail(FD_EINVAL, "fd_adjoint_step_scaled_res: receiver plane %d outside the interior",
+                res_k);
+  RecPlane inj{res_map, res_k, const_cast<float*>(res_row)};
+  inj.add = true;
+  return adjoint_scaled(g, b_nn, b_n1, b_out, vdt2, sp, u_n, g_b, src, &inj, stream);
 }
 
 int fd_scatter_add_scaled(const fd_grid* g, float* b, const int64_t* off, const float* vals,

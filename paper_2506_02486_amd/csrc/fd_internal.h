@@ -77,12 +77,13 @@ struct RecPlane {
   const int32_t* map;
   int k;
   float* row;
+  bool add = false;  // row is added at the points, scaled by vdt2 / (1+eta) (adjoint)
 };
 
 // ------------------------------------------------------------ launchers
 // All validate nothing (the ABI layer has) and return a HIP error code.
 // src may be NULL (no fused source term); rp (optional) has the forward kernel
-// write the receiver row of un itself
+// write the receiver row of un itself (or, with rp->add, add that row to un)
 hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float* u,
                        float* un, const float* q, const float* ex, const float* ey,
                        const float* ez, const fd_source* src, hipStream_t s,

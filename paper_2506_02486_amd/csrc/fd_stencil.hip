@@ -74,6 +74,7 @@ struct Params {
   const int32_t* rmap;
   int rk;
   float* rrow;
+  bool radd;  // rrow is a row to add (scaled by vdt2 / (1+eta)) instead of to write
 };
 
 __device__ __forceinline__ int remap_block(int bid, int nb) {
@@ -98,7 +99,7 @@ __device__ __forceinline__ float ld_nt(const char* base, unsigned boff) {
 // The per-block work of every stencil kernel: tile (bx, by) of the x-y plane,
 // z-chunk bz, of the grid and operands described by p.
 template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY, bool XCH,
-          bool REC = false>
+          int REC = 0>
 __device__ __forceinline__ void stencil_block(const Params& p, const int bx, const int by,
                                               const int bz) {
   constexpr int TX = TXT;
@@ -397,8 +398,9 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
     // block-uniform: the source point lies in this tile-plane
     const bool src_plane = src_tile && k == p.sk;
     // block-uniform: this plane holds the receivers (REC: a separate instantiation,
-    // so the kernels without it keep their registers)
-    const bool rec_plane = REC && MODE == FWD && k == p.rk;
+    // so the kernels without it keep their registers; 1 writes their trace row,
+    // 2 adds a row scaled by vdt2 / (1+eta) as fd_scatter_add_scaled would)
+    const bool rec_plane = REC != 0 && MODE == FWD && k == p.rk;
     char* ok = O0 + (long long)k * szb;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -433,11 +435,23 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
 #pragma clang fp contract(off)
             if (x == p.si && yr + r == p.sj) v += pb[r] * p.sw / (1.f + eta);
           }
+          if constexpr (REC == 2) {
+            if (rec_plane) {
+              const int rr = p.rmap[(yr + r) * nx + x];
+              if (rr >= 0) {
+                // rounds as fd_scatter_add_scaled: the row value times vdt2 / (1+eta)
+#pragma clang fp contract(off)
+                v += p.rrow[rr] * (pb[r] / (1.f + eta));
+              }
+            }
+          }
           __builtin_nontemporal_store(v, dst);
           if (XCH && xedge && sx_ptr) sx_ptr[((unsigned)k * (unsigned)ny + (unsigned)(yr + r)) * 4u] = v;
-          if (rec_plane) {
-            const int rr = p.rmap[(yr + r) * nx + x];
-            if (rr >= 0) p.rrow[rr] = v;
+          if constexpr (REC == 1) {
+            if (rec_plane) {
+              const int rr = p.rmap[(yr + r) * nx + x];
+              if (rr >= 0) p.rrow[rr] = v;
+            }
           }
         } else if (MODE == ADJ) {
           const float c = cq[0][r];
@@ -515,7 +529,7 @@ __device__ __forceinline__ void stencil_block(const Params& p, const int bx, con
 }
 
 template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE, bool EARLY = (MODE == FWD),
-          bool XCH = false, bool REC = false>
+          bool XCH = false, int REC = 0>
 __global__ void __launch_bounds__(TXT * NY) stencil_kernel(Params p) {
   const int logical = remap_block(blockIdx.x, gridDim.x);
   const int bx = logical % p.tiles_x;
@@ -556,11 +570,12 @@ __global__ void __launch_bounds__(TXT * NY) batched_kernel(const BatchShot* __re
   p.rmap = b.rmap;
   p.rk = b.rmap ? b.rk : -1;  // no plane: the receiver epilogue never runs
   p.rrow = b.traces + (size_t)n * (size_t)b.nrec;
-  stencil_block<TXT, NY, RY, FWD, true, true, true, false, true>(p, t.y, t.z, t.w);
+  p.radd = false;
+  stencil_block<TXT, NY, RY, FWD, true, true, true, false, 1>(p, t.y, t.z, t.w);
 }
 
 template <int TXT, int NY, int RY, int MODE, bool SPONGE, bool FUSE = false,
-          bool EARLY = (MODE == FWD), bool XCH = false, bool REC = false>
+          bool EARLY = (MODE == FWD), bool XCH = false, int REC = 0>
 hipError_t launch_mode(Params p, hipStream_t st) {
   const LaunchShape sh = stencil_shape(p.g, TXT, NY * RY, (TXT * NY + 63) / 64);
   p.tiles_x = sh.tiles_x;
@@ -588,6 +603,7 @@ Params base_params(const Geo& g, const Coef& c, const float* ex, const float* ey
   p.rmap = nullptr;
   p.rk = -1;
   p.rrow = nullptr;
+  p.radd = false;
   return p;
 }
 
@@ -603,9 +619,13 @@ constexpr int BATCH_TY = 8 * 4;   // tile height of the batched kernel (FWD_SHAP
 // receiver row fused, or the source fused, or the plain update.
 template <int TXT, int NY, int RY>
 hipError_t launch_forward(const Params& p, bool sponge, bool fuse, bool xch, hipStream_t s) {
-  if (p.rmap && !xch) {  // the receiver row written by the kernel (fused epilogue)
-    if (sponge) return launch_mode<TXT, NY, RY, FWD, true, true, true, false, true>(p, s);
-    return launch_mode<TXT, NY, RY, FWD, false, true, true, false, true>(p, s);
+  if (p.rmap && !xch && !p.radd) {  // the receiver row written by the kernel
+    if (sponge) return launch_mode<TXT, NY, RY, FWD, true, true, true, false, 1>(p, s);
+    return launch_mode<TXT, NY, RY, FWD, false, true, true, false, 1>(p, s);
+  }
+  if (p.rmap && !xch) {  // a scaled row added at the receiver points
+    if (sponge) return launch_mode<TXT, NY, RY, FWD, true, true, true, false, 2>(p, s);
+    return launch_mode<TXT, NY, RY, FWD, false, true, true, false, 2>(p, s);
   }
   if (xch) {
     if (sponge) return launch_mode<TXT, NY, RY, FWD, true, true, true, true>(p, s);
@@ -659,6 +679,7 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
     p.rmap = rp->map;
     p.rk = rp->k;
     p.rrow = rp->row;
+    p.radd = rp->add;
   }
   p.f = u;
   p.fq = u;

@@ -198,9 +198,12 @@ class FWIProblem:
             for n in range(e - 1, s - 1, -1):
                 if grad_w is not None:
                     api.record_receivers(g, B, self.src_off, grad_w[n:n + 1])
+                # the residual of step n-1 enters at the receivers: in the update's own
+                # launch when they share one plane
+                inj = (self.rec_plane, res[n - 1]) if n >= 1 and self.rec_plane else None
                 api.adjoint_step_scaled(g, A, B, A, self.vdt2, self.sponge, u_n=seg[n - s],
-                                        g_b=gb, src=(self.src, float(self.w[n])))
-                if n >= 1:
+                                        g_b=gb, src=(self.src, float(self.w[n])), res=inj)
+                if n >= 1 and inj is None:
                     api.scatter_add_scaled(g, A, self.rec_off, res[n - 1], self.vdt2,
                                            self.sponge)
                 A, B = B, A

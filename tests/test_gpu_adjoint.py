@@ -231,6 +231,41 @@ def test_fwi_gradient_matches_oracle_and_central_differences():
     assert rel_l2(gm.flat[vox], fd) <= 2e-2
 
 
+@pytest.mark.parametrize("tiles", [1, 2])
+def test_residual_plane_in_adjoint_launch_matches_scatter(tiles):
+    """fd_adjoint_step_scaled_res (the residual row added at receivers on one plane in
+    the update's launch) gives the bits of fd_adjoint_step_scaled followed by
+    fd_scatter_add_scaled, receivers inside and outside the sponge, both tile shapes."""
+    nx, ny, nz = 70, 37, 29
+    v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
+    sim = api.Simulation(v, sponge_width=6)
+    g = sim.grid
+    b2, b1, u = _fields(g, (21, 22, 23), False)
+    rng = np.random.default_rng(4)
+    pts = rng.choice(nx * ny, size=400, replace=False)
+    rec = np.stack([pts % nx, pts // nx, np.full(400, nz - 3)], axis=1).astype(np.int32)
+    plane = api.receiver_plane(g, rec)
+    assert plane is not None and plane.k == nz - 3
+    off = torch.from_numpy(g.offsets(rec)).cuda()
+    row = torch.from_numpy(rng.standard_normal(400).astype(np.float32)).cuda()
+    api.set_tiles(tiles)
+    try:
+        outs = []
+        for fused in (False, True):
+            out, gb = g.zeros(), g.zeros()
+            if fused:
+                api.adjoint_step_scaled(g, b2, b1, out, sim.vdt2, sim.sponge, u_n=u, g_b=gb,
+                                        src=((5, 6, 7), 2.0), res=(plane, row))
+            else:
+                api.adjoint_step_scaled(g, b2, b1, out, sim.vdt2, sim.sponge, u_n=u, g_b=gb,
+                                        src=((5, 6, 7), 2.0))
+                api.scatter_add_scaled(g, out, off, row, sim.vdt2, sim.sponge)
+            outs.append((out, gb))
+        assert same_bits(outs[0][0], outs[1][0]) and same_bits(outs[0][1], outs[1][1])
+    finally:
+        api.set_tiles(0)
+
+
 def test_fwi_checkpoint_interval_does_not_change_the_gradient():
     n, nt = 40, 90
     v0, vt, dt, src, rec = _fwi_case(n, nt, 32, 5.0)
@@ -238,9 +273,15 @@ def test_fwi_checkpoint_interval_does_not_change_the_gradient():
     m = torch.from_numpy((1.0 / v0.astype(np.float64) ** 2).astype(np.float32)).cuda()
     obs = None
     grads = []
-    for C in (1, 7, 32, 90, 200, 0):  # 0: every state kept, no recompute
+    # 0: every state kept, no recompute; the last run samples and injects at the
+    # receivers by separate launches instead of inside the stencil launches
+    for C, plane in ((1, True), (7, True), (32, True), (90, True), (200, True), (0, True),
+                     (32, False)):
         prob = fwi.FWIProblem((n, n, n), dt, src, rec, nt, sponge_width=8, sponge_vmax=vmax,
                               checkpoint_every=C)
+        assert prob.rec_plane is not None
+        if not plane:
+            prob.rec_plane = None
         if obs is None:
             mt = torch.from_numpy((1.0 / vt.astype(np.float64) ** 2).astype(np.float32)).cuda()
             obs = prob.forward(mt, checkpoints=False)
