@@ -515,7 +515,7 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
       nxt = t;
     } else {
       const RecPlane rp{run->rec_map, run->rec_k, row};
-      const bool in_kernel = run->rec_map && run->nrec > 0 && !nsend;
+      const bool in_kernel = run->rec_map && run->nrec > 0 && !nsend && receiver_plane_pays(geo);
       if (nsend) e = launch_unpack(geo, u, recv, s);
       if (e == hipSuccess)
         e = launch_step(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, s,

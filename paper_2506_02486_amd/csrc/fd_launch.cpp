@@ -102,4 +102,12 @@ bool forward_small_tiles(const Geo& g) {
 
 void set_tile_override(int mode) { g_tile_override.store(mode, std::memory_order_relaxed); }
 
+// The receiver row taken by the stencil launch saves a launch per step but adds a
+// dependent map lookup to the blocks of the receiver plane, whose finish sets the
+// launch time: a gain where launches dominate (64^3: 6.4 -> 4.7 us per step), a loss
+// on bandwidth-bound grids (256^3: +6 us per launch against a 4.8 us receiver launch).
+bool receiver_plane_pays(const Geo& g) {
+  return (long long)g.nx * g.ny * g.nz <= kSmallGridPoints;
+}
+
 }  // namespace fd

@@ -33,6 +33,10 @@ import torch
 
 from . import api
 
+# grids up to this many points are launch-bound: there the receiver residual is added
+# in the adjoint update's own launch (fd_adjoint_step_scaled_res)
+SMALL_GRID_POINTS = 1 << 20
+
 
 class FWIProblem:
     """One shot of an FWI gradient: geometry, time axis, source, receivers."""
@@ -185,6 +189,11 @@ class FWIProblem:
             before = seg[i]
         return s, e, seg
 
+    @property
+    def _inject_in_step(self) -> bool:
+        g = self.grid
+        return self.rec_plane is not None and g.nx * g.ny * g.nz <= SMALL_GRID_POINTS
+
     def _backward_scaled(self, res: torch.Tensor, want_grad_w: bool):
         g, nt = self.grid, self.nt
         A = g.zeros(self.device)  # b^{n+2}
@@ -199,8 +208,9 @@ class FWIProblem:
                 if grad_w is not None:
                     api.record_receivers(g, B, self.src_off, grad_w[n:n + 1])
                 # the residual of step n-1 enters at the receivers: in the update's own
-                # launch when they share one plane
-                inj = (self.rec_plane, res[n - 1]) if n >= 1 and self.rec_plane else None
+                # launch when they share one plane of a small grid (on bandwidth-bound
+                # grids the separate launch costs less than the lookup in the update)
+                inj = (self.rec_plane, res[n - 1]) if n >= 1 and self._inject_in_step else None
                 api.adjoint_step_scaled(g, A, B, A, self.vdt2, self.sponge, u_n=seg[n - s],
                                         g_b=gb, src=(self.src, float(self.w[n])), res=inj)
                 if n >= 1 and inj is None:
