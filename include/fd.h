@@ -257,8 +257,9 @@ typedef struct fd_run {
   float* send[6];                /* device face buffers, or all NULL (no exchange) */
   float* send2[6];               /* second face set (one-kernel steps), or all NULL */
   const int32_t* rec_map;        /* device, optional: receivers on plane rec_k, map from
-                                    fd_receiver_plane_map; the forward kernel then writes
-                                    the trace row itself where it takes no faces */
+                                    fd_receiver_plane_map (entries -1 or < nrec, not
+                                    checked on the device); the forward kernel then
+                                    writes the trace row itself where it takes no faces */
   int32_t rec_k;
 } fd_run;
 int fd_forward_run(const fd_grid* g, fd_run* run, void* stream);
@@ -355,7 +356,7 @@ int fd_adjoint_step_scaled(const fd_grid* g, const float* b_nn, const float* b_n
 
 /* fd_adjoint_step_scaled followed by fd_scatter_add_scaled(b_out, res_row) of
  * receivers that all lie on plane res_k (res_map: device nx*ny map from
- * fd_receiver_plane_map), the residual added in the update's own launch; same
+ * fd_receiver_plane_map, each entry -1 or an index into res_row), the residual added in the update's own launch; same
  * bits as the two calls.  FD_EINVAL for a NULL map or row or a plane outside
  * the interior, else as fd_adjoint_step_scaled. */
 int fd_adjoint_step_scaled_res(const fd_grid* g, const float* b_nn, const float* b_n1,

@@ -311,43 +311,6 @@ int fd_step(const fd_grid* g, const float* u_prev, const float* u, float* u_next
 
 static int check_faces(const fd_grid* g, const void* const* face, const char* who);
 
-int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* u_next,
-                  const float* vdt2, const fd_sponge* sp, const fd_source* src,
-                  float* const face_out[6], void* stream) {
-  int rc = check_grid(g);
-  if (rc) return rc;
-  if (!u_prev || !u || !u_next || !vdt2) return fail(FD_EINVAL, "fd_step_fused: NULL array");
-  if (overlaps(g, u, u_next)) return fail(FD_EINVAL, "fd_step_fused: u_next overlaps u");
-  if (overlaps(g, vdt2, u_next)) return fail(FD_EINVAL, "fd_step_fused: u_next overlaps vdt2");
-  if (u_next != u_prev && overlaps(g, u_prev, u_next))
-    return fail(FD_EINVAL, "fd_step_fused: u_next partially overlaps u_prev");
-  if (src && (src->i < 0 || src->i >= g->nx || src->j < 0 || src->j >= g->ny || src->k < 0 ||
-              src->k >= g->nz))
-    return fail(FD_EINVAL, "fd_step_fused: source outside the interior");
-  if (face_out) {
-    rc = check_faces(g, (const void* const*)face_out, "fd_step_fused");
-    if (rc) return rc;
-    for (int f = 0; f < 6; ++f) {
-      const float* fp = face_out[f];
-      if (!fp) continue;
-      const int64_t n = fd_face_elems(g, f);
-      const float* vols[4] = {u_prev, u, u_next, vdt2};
-      for (const float* a : vols)
-        if (fp < a + last_elem(g) + 1 && a < fp + n)
-          return fail(FD_EINVAL, "fd_step_fused: face %d overlaps a volume array", f);
-    }
-  }
-  const float *ex, *ey, *ez;
-  rc = check_sponge(sp, &ex, &ey, &ez);
-  if (rc) return rc;
-  const Geo geo = make_geo(g);
-  hipStream_t s = as_stream(stream);
-  rc = check_hip(launch_step(geo, make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez, src, s),
-                 "fd_step_fused launch");
-  if (rc || !face_out) return rc;
-  return check_hip(launch_pack(geo, u_next, face_out, s), "fd_step_fused pack launch");
-}
-
 // Overlap checks of six face buffers against the volume arrays of one call.
 static int faces_clear_of(const fd_grid* g, const float* const face[6], const float* const* vols,
                           int nvol, const char* who) {
@@ -364,6 +327,37 @@ static int faces_clear_of(const fd_grid* g, const float* const face[6], const fl
   return FD_OK;
 }
 
+int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* u_next,
+                  const float* vdt2, const fd_sponge* sp, const fd_source* src,
+                  float* const face_out[6], void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!u_prev || !u || !u_next || !vdt2) return fail(FD_EINVAL, "fd_step_fused: NULL array");
+  if (overlaps(g, u, u_next)) return fail(FD_EINVAL, "fd_step_fused: u_next overlaps u");
+  if (overlaps(g, vdt2, u_next)) return fail(FD_EINVAL, "fd_step_fused: u_next overlaps vdt2");
+  if (u_next != u_prev && overlaps(g, u_prev, u_next))
+    return fail(FD_EINVAL, "fd_step_fused: u_next partially overlaps u_prev");
+  if (src && (src->i < 0 || src->i >= g->nx || src->j < 0 || src->j >= g->ny || src->k < 0 ||
+              src->k >= g->nz))
+    return fail(FD_EINVAL, "fd_step_fused: source outside the interior");
+  if (face_out) {
+    rc = check_faces(g, (const void* const*)face_out, "fd_step_fused");
+    if (rc) return rc;
+    const float* vols[4] = {u_prev, u, u_next, vdt2};
+    rc = faces_clear_of(g, face_out, vols, 4, "fd_step_fused");
+    if (rc) return rc;
+  }
+  const float *ex, *ey, *ez;
+  rc = check_sponge(sp, &ex, &ey, &ez);
+  if (rc) return rc;
+  const Geo geo = make_geo(g);
+  hipStream_t s = as_stream(stream);
+  rc = check_hip(launch_step(geo, make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez, src, s),
+                 "fd_step_fused launch");
+  if (rc || !face_out) return rc;
+  return check_hip(launch_pack(geo, u_next, face_out, s), "fd_step_fused pack launch");
+}
+
 static bool face_sets_overlap(const fd_grid* g, const float* const a[6], const float* const b[6]) {
   for (int f = 0; f < 6; ++f) {
     if (!a[f]) continue;
@@ -377,9 +371,8 @@ static bool face_sets_overlap(const fd_grid* g, const float* const a[6], const f
   return false;
 }
 
-// One step of the exchange form; arguments already checked.
-// One exchange step; with receivers (nrec > 0) the receiver row of un is taken in
-// the launch that packs its faces.
+// One step of the exchange form, arguments already checked; with receivers
+// (nrec > 0) the receiver row of un is taken in the launch that packs its faces.
 static hipError_t step_exchange(const Geo& geo, const Coef& c, const float* up, float* u,
                                 float* un, const float* q, const float* ex, const float* ey,
                                 const float* ez, const fd_source* src,

@@ -10,7 +10,9 @@
 //             compute stream), then writes the shot's entry of the slot table.
 //   step    : one batched stencil launch over the tile table of all active
 //             shots (each at its own step n, its source amplitude w[n] passed
-//             by value), then one batched receiver launch.
+//             by value), which also writes the trace rows of shots whose
+//             receivers lie on one z plane; then one batched receiver launch
+//             for the other shots with receivers.
 //   retire  : a shot that reached nt has its traces copied to pinned host
 //             memory on the copy stream; when that copy has landed the shot
 //             is done and its arena block is released.
@@ -448,6 +450,8 @@ void progress(Server* S) {
       for (int slot = 0; slot < S->max_slots; ++slot)
         if (Shot* s = S->slots[slot]) {
           S->slots[slot] = nullptr;
+          if (s->has_block) S->arena->release(s->off, s->L.total);
+          s->has_block = false;
           S->running--;
           finish_locked(S, s, FD_EDEVICE);
         }
@@ -510,13 +514,14 @@ void stop_server(Server* S) {
       S->running--;
       finish_locked(S, s, FD_ECANCELED);
     }
-  for (Shot* s : S->draining) {  // copies completed in the final synchronisation
+  for (Shot* s : S->draining) {  // copies ended in the final synchronisation
+    const bool landed = s->copied && hipEventQuery(s->copied) == hipSuccess;
     if (s->copied) (void)hipEventDestroy(s->copied);
     s->copied = nullptr;
     if (s->has_block) S->arena->release(s->off, s->L.total);
     s->has_block = false;
     S->running--;
-    finish_locked(S, s, FD_OK);
+    finish_locked(S, s, landed ? FD_OK : FD_EDEVICE);
   }
   S->draining.clear();
   S->stopped = true;
