@@ -156,7 +156,7 @@ def test_degenerate_small_grids(shape):
     assert rel_l2(tr, tr_o) <= 1e-5
 
 
-@pytest.mark.parametrize("shape", [(128, 40, 45), (70, 33, 29), (192, 80, 64)])
+@pytest.mark.parametrize("shape", [(128, 40, 45), (70, 33, 29), (192, 80, 64), (128, 64, 40)])
 def test_results_independent_of_launch_shape(shape):
     """The tile shape (fd_set_tiles: 64 x 32 or 64 x 16) and the z chunk (planes per
     block, fd_set_kchunk) change the launch, never the bits: forward runs in the
@@ -288,7 +288,7 @@ def test_resume_is_bitwise():
 
 
 @pytest.mark.parametrize("shape,tiles", [((64, 64, 64), 0), ((70, 33, 29), 1), ((70, 33, 29), 2),
-                                         ((256, 100, 48), 0)])
+                                         ((256, 100, 48), 0), ((128, 64, 40), 1)])
 @pytest.mark.parametrize("faces", [0, 1, 2])
 def test_receiver_plane_in_stencil_matches_separate_record(shape, tiles, faces):
     """fd_forward_run with a receiver plane map (the stencil launch writes the trace
@@ -590,6 +590,52 @@ def test_exchange_step_reads_only_the_receive_buffers():
     I3 = g.interior(out3)
     assert torch.isnan(I3[:4]).all()
     assert same_bits(I3[4:], g.interior(ref)[4:])
+
+
+@pytest.mark.parametrize("tiles", [0, 1])
+@pytest.mark.parametrize("nz,kc", [(20, 0), (20, 3), (5, 0), (4, 1)])
+def test_exchange_step_with_all_faces_matches_separate_calls(tiles, nz, kc):
+    """fd_step_exchange with all twelve face buffers (x faces inside the stencil
+    kernel, y and z faces unpacked and packed around it) on a grid the tiles cover
+    exactly: with NaN in every halo cell of u, u_next and the six sent faces are bit
+    for bit those of halo_unpack + fd_step + inject_source + halo_pack, also for z
+    chunks that split the z faces and for grids whose planes are all in both z
+    faces; u's edge and corner halo cells, which no point reads, keep their NaN."""
+    nx, ny = 64, 32
+    v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
+    api.set_tiles(tiles)
+    api.set_kchunk(kc)
+    try:
+        sim = api.Simulation(v, sponge_width=3, exchange="loopback")
+        g = sim.grid
+        up, u = _random_state(g, 37)
+        faces = api.face_buffers(g)
+        api.halo_pack(g, u, faces)
+        recv = api.loopback(faces)
+        u_ref = u.clone()
+        api.halo_unpack(g, u_ref, recv)
+        ref = g.zeros()
+        src = (5, 7, nz // 2)
+        api.step(g, up, u_ref, ref, sim.vdt2, sim.sponge)
+        api.inject_source(g, ref, sim.vdt2, sim.sponge, src, 0.37)
+        ref_faces = api.face_buffers(g)
+        api.halo_pack(g, ref, ref_faces)
+        P = g.padded(u)
+        keep = g.interior(u).clone()
+        P.fill_(float("nan"))
+        g.interior(u).copy_(keep)
+        out = g.zeros()
+        sent = api.face_buffers(g)
+        for f in sent:
+            f.fill_(float("nan"))
+        api.step_exchange(g, up, u, out, sim.vdt2, sim.sponge, (src, 0.37), recv, sent)
+        assert same_bits(g.interior(out), g.interior(ref))
+        for a, b in zip(sent, ref_faces):
+            assert same_bits(a, b)
+        assert bool(torch.isnan(P).any())  # edges and corners are never written
+    finally:
+        api.set_kchunk(0)
+        api.set_tiles(0)
 
 
 def test_large_subdomain_sampled_parity():
