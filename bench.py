@@ -310,11 +310,30 @@ def small_bench(steps=100, repeats=5):
             times.append(time.perf_counter() - t0)
         del sim, tr
     el = float(np.median(times))
+    # the same run recorded once as a HIP graph (fd_forward_graph) and launched again
+    # and again: each launch starts from zero and writes the same traces
+    sim = api.Simulation(v, geom=geom)
+    tr = torch.zeros((steps, sim.nrec), dtype=torch.float32, device="cuda")
+    G = api.ForwardGraph(sim.grid, sim.u_prev, sim.u, sim.u_next, sim.vdt2, sim.sponge, steps,
+                         src=geom.src, wavelet=api.ricker(steps, sim.dt), rec_off=sim.rec_off,
+                         traces=tr, rec_plane=sim.rec_plane)
+    gtimes = []
+    for r in range(repeats + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G.launch()
+        torch.cuda.synchronize()
+        if r:
+            gtimes.append(time.perf_counter() - t0)
+    G.close()
+    gel = float(np.median(gtimes))
     return {"workload": "64^3 layered model, Dirichlet, no sponge, 4096 receivers at k=0, "
                         f"{steps} steps (launch-bound; HBM fraction not meaningful)",
             "steps": steps, "repeats": repeats,
             "Gpts_per_s": round(n ** 3 * steps / el / 1e9, 2),
-            "us_per_step": round(el * 1e6 / steps, 2)}
+            "us_per_step": round(el * 1e6 / steps, 2),
+            "graph_Gpts_per_s": round(n ** 3 * steps / gel / 1e9, 2),
+            "graph_us_per_step": round(gel * 1e6 / steps, 2)}
 
 
 def large_bench(steps=500, warmup=5):

@@ -264,6 +264,27 @@ typedef struct fd_run {
 } fd_run;
 int fd_forward_run(const fd_grid* g, fd_run* run, void* stream);
 
+/* A recorded forward run (HIP graph), for launch-bound grids that are modelled
+ * again and again (FWI iterations, model scans): one graph launch replaces the
+ * per-step launches of fd_forward_run, whose host and dispatch cost dominates
+ * small grids.  fd_forward_graph checks *run exactly as fd_forward_run does and
+ * records, without running anything: zeroing u_prev and u (whole padded arrays)
+ * and, with faces, send[0..5]; then the run->nt steps of fd_forward_run.  The
+ * wavelet values and every pointer are fixed at recording; array contents (vdt2,
+ * sponge tables, receiver map) are read at each launch, so a new model written
+ * into vdt2 is picked up.  On FD_OK, *out holds the graph and *run is rotated as
+ * one fd_forward_run would rotate it: after each launch u_prev, u (and, with
+ * faces, send) name the arrays that hold the final state.  Each fd_graph_launch
+ * enqueues the whole run on `stream` (of the device current at recording) and
+ * gives the bits of fd_forward_run from a zero state; launches must not overlap
+ * in time with one another or with other work on the same arrays.  FD_EINVAL as
+ * fd_forward_run, FD_EDEVICE if recording fails. */
+typedef struct fd_graph fd_graph;
+int fd_forward_graph(const fd_grid* g, fd_run* run, fd_graph** out);
+int fd_graph_launch(fd_graph* graph, void* stream);
+/* Frees the graph (NULL: no-op); the caller makes sure no launch is pending. */
+int fd_graph_destroy(fd_graph* graph);
+
 /* Host helper for fd_run.rec_map: when all nrec >= 1 receivers (rec_ijk: 3*nrec
  * interior (i,j,k) triples) lie on one z plane at distinct (i,j), fills map
  * (host, nx*ny int32) with map[j*nx + i] = r for receiver r and -1 elsewhere,

@@ -89,6 +89,9 @@ SIGNATURES = {
     "fd_step_exchange": (C.c_int, [_G, _P, _P, _P, _P, _S, C.POINTER(fd_source),
                                    C.POINTER(_P), C.POINTER(_P), _P]),
     "fd_forward_run": (C.c_int, [_G, C.POINTER(fd_run), _P]),
+    "fd_forward_graph": (C.c_int, [_G, C.POINTER(fd_run), C.POINTER(_P)]),
+    "fd_graph_launch": (C.c_int, [_P, _P]),
+    "fd_graph_destroy": (C.c_int, [_P]),
     "fd_receiver_plane_map": (C.c_int, [_G, _P, _i32, _P, C.POINTER(_i32)]),
     "inject_source": (C.c_int, [_G, _P, _P, _S, _i32, _i32, _i32, _f32, _P]),
     "record_receivers": (C.c_int, [_G, _P, _P, _i32, _P, _P]),

@@ -400,6 +400,55 @@ def receiver_plane(grid: Grid, rec_ijk: np.ndarray, device="cuda") -> ReceiverPl
     return ReceiverPlane(torch.from_numpy(m).to(device), k.value, ijk.shape[0])
 
 
+def _run_struct(grid, u_prev, u, u_next, vdt2, sponge, nt, src, wavelet, rec_off, traces,
+                send, send2, rec_plane, who):
+    """The fd_run of forward_run / forward_graph, the arrays by address, and the host
+    objects that must outlive the call."""
+    for n, t in (("u_prev", u_prev), ("u", u), ("u_next", u_next), ("vdt2", vdt2)):
+        grid.check(t, n)
+    r = _lib.fd_run()
+    if rec_plane is not None:
+        m = rec_plane.map
+        if (m.dtype != torch.int32 or not m.is_cuda or not m.is_contiguous()
+                or m.numel() != grid.nx * grid.ny):
+            raise TypeError(f"{who}: rec_plane map must be a device int32 nx*ny array")
+        r.rec_map = m.data_ptr()
+        r.rec_k = rec_plane.k
+    bufs = {t.data_ptr(): t for t in (u_prev, u, u_next)}
+    r.u_prev, r.u, r.u_next = u_prev.data_ptr(), u.data_ptr(), u_next.data_ptr()
+    r.vdt2 = vdt2.data_ptr()
+    if sponge is not None:
+        r.sponge = sponge.c
+    r.nt = int(nt)
+    wa = None
+    if src is not None:
+        wa = np.ascontiguousarray(wavelet, dtype=np.float32)
+        if wa.size < nt:
+            raise ValueError(f"{who}: wavelet shorter than nt")
+        r.wavelet = wa.ctypes.data
+        r.src[0], r.src[1], r.src[2] = (int(x) for x in src)
+    if rec_off is not None and rec_off.numel():
+        if (rec_off.dtype != torch.int64 or traces is None or traces.dtype != torch.float32
+                or not traces.is_contiguous() or traces.dim() != 2
+                or traces.shape[0] < nt or traces.shape[1] != rec_off.numel()):
+            raise TypeError(f"{who}: rec_off int64 and contiguous float32 traces "
+                            "(>= nt, nrec)")
+        r.nrec = rec_off.numel()
+        r.rec_off = rec_off.data_ptr()
+        r.traces = traces.data_ptr()
+    if send is not None:
+        fs = _faces(send, grid)
+        for f in range(6):
+            r.send[f] = fs[f]
+    if send2 is not None:
+        if send is None:
+            raise ValueError(f"{who}: send2 needs send")
+        fs = _faces(send2, grid)
+        for f in range(6):
+            r.send2[f] = fs[f]
+    return r, bufs, wa
+
+
 def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: int, src=None,
                 wavelet=None, rec_off: torch.Tensor | None = None,
                 traces: torch.Tensor | None = None, send=None, send2=None, stream=None,
@@ -414,48 +463,8 @@ def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: 
     faces of the new u.  ``rec_plane`` (from ``receiver_plane`` of the same receivers
     as ``rec_off``) lets the stencil launch take the receiver row where no faces are
     packed."""
-    for n, t in (("u_prev", u_prev), ("u", u), ("u_next", u_next), ("vdt2", vdt2)):
-        grid.check(t, n)
-    r = _lib.fd_run()
-    if rec_plane is not None:
-        m = rec_plane.map
-        if (m.dtype != torch.int32 or not m.is_cuda or not m.is_contiguous()
-                or m.numel() != grid.nx * grid.ny):
-            raise TypeError("forward_run: rec_plane map must be a device int32 nx*ny array")
-        r.rec_map = m.data_ptr()
-        r.rec_k = rec_plane.k
-    bufs = {t.data_ptr(): t for t in (u_prev, u, u_next)}
-    r.u_prev, r.u, r.u_next = u_prev.data_ptr(), u.data_ptr(), u_next.data_ptr()
-    r.vdt2 = vdt2.data_ptr()
-    if sponge is not None:
-        r.sponge = sponge.c
-    r.nt = int(nt)
-    wa = None
-    if src is not None:
-        wa = np.ascontiguousarray(wavelet, dtype=np.float32)
-        if wa.size < nt:
-            raise ValueError("forward_run: wavelet shorter than nt")
-        r.wavelet = wa.ctypes.data
-        r.src[0], r.src[1], r.src[2] = (int(x) for x in src)
-    if rec_off is not None and rec_off.numel():
-        if (rec_off.dtype != torch.int64 or traces is None or traces.dtype != torch.float32
-                or not traces.is_contiguous() or traces.dim() != 2
-                or traces.shape[0] < nt or traces.shape[1] != rec_off.numel()):
-            raise TypeError("forward_run: rec_off int64 and contiguous float32 traces "
-                            "(>= nt, nrec)")
-        r.nrec = rec_off.numel()
-        r.rec_off = rec_off.data_ptr()
-        r.traces = traces.data_ptr()
-    if send is not None:
-        fs = _faces(send, grid)
-        for f in range(6):
-            r.send[f] = fs[f]
-    if send2 is not None:
-        if send is None:
-            raise ValueError("forward_run: send2 needs send")
-        fs = _faces(send2, grid)
-        for f in range(6):
-            r.send2[f] = fs[f]
+    r, bufs, keep = _run_struct(grid, u_prev, u, u_next, vdt2, sponge, nt, src, wavelet, rec_off,
+                                traces, send, send2, rec_plane, "forward_run")
     check(lib().fd_forward_run(grid.ref, C.byref(r), _stream(stream)), "fd_forward_run")
     if send2 is None:
         return bufs[r.u_prev], bufs[r.u], bufs[r.u_next]
@@ -463,6 +472,48 @@ def forward_run(grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: 
     if swapped:
         send, send2 = send2, send
     return bufs[r.u_prev], bufs[r.u], bufs[r.u_next], send, send2
+
+
+class ForwardGraph:
+    """A forward run recorded once as a HIP graph (fd_forward_graph) and launched as
+    often as wanted: each ``launch`` re-runs the ``nt`` steps from a zero state with
+    the fixed source wavelet, reading the current contents of ``vdt2`` (a new model
+    written into it is picked up) and writing ``traces``.  After a launch the final
+    state is in ``u_prev``, ``u`` (and, with faces, the faces of ``u`` in ``send``)."""
+
+    def __init__(self, grid: Grid, u_prev, u, u_next, vdt2, sponge: Sponge | None, nt: int,
+                 src=None, wavelet=None, rec_off=None, traces=None, send=None, send2=None,
+                 rec_plane: ReceiverPlane | None = None):
+        r, bufs, _ = _run_struct(grid, u_prev, u, u_next, vdt2, sponge, nt, src, wavelet, rec_off,
+                                 traces, send, send2, rec_plane, "ForwardGraph")
+        h = C.c_void_p()
+        check(lib().fd_forward_graph(grid.ref, C.byref(r), C.byref(h)), "fd_forward_graph")
+        self._h = h
+        # every array the graph touches stays referenced while it lives
+        self._keep = (grid, vdt2, sponge, rec_off, traces, send, send2, rec_plane, u_prev, u, u_next)
+        self.u_prev, self.u, self.u_next = bufs[r.u_prev], bufs[r.u], bufs[r.u_next]
+        self.send = self.send2 = None
+        if send2 is not None:
+            swapped = r.send[0] != send[0].data_ptr()
+            self.send, self.send2 = (send2, send) if swapped else (send, send2)
+        elif send is not None:
+            self.send = send
+
+    def launch(self, stream=None):
+        if self._h is None:
+            raise RuntimeError("ForwardGraph: closed")
+        check(lib().fd_graph_launch(self._h, _stream(stream)), "fd_graph_launch")
+
+    def close(self):
+        if self._h is not None:
+            check(lib().fd_graph_destroy(self._h), "fd_graph_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @dataclass

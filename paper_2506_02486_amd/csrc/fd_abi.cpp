@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <limits>
+#include <new>
 
 #include "fd_internal.h"
 
@@ -117,7 +118,7 @@ const char* fd_strerror(int code) {
 
 const char* fd_last_error(void) { return t_err; }
 
-int fd_version(void) { return 10100; }
+int fd_version(void) { return 10200; }
 
 int fd_grid_init(fd_grid* g, int32_t nx, int32_t ny, int32_t nz, double dx, double dy,
                  double dz) {
@@ -437,11 +438,14 @@ int fd_step_exchange(const fd_grid* g, const float* u_prev, float* u, float* u_n
                    "fd_step_exchange launch");
 }
 
-int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
+// Argument checks of fd_forward_run (and of the graph that records it): the
+// number of face buffers of each set and the sponge tables.
+static int forward_checked(const fd_grid* g, const fd_run* run, int* nsend_out, int* nsend2_out,
+                           const float** ex_out, const float** ey_out, const float** ez_out) {
   int rc = check_grid(g);
   if (rc) return rc;
   if (!run) return fail(FD_EINVAL, "fd_forward_run: run is NULL");
-  float *up = run->u_prev, *u = run->u, *un = run->u_next;
+  const float *up = run->u_prev, *u = run->u, *un = run->u_next;
   if (!up || !u || !un || !run->vdt2) return fail(FD_EINVAL, "fd_forward_run: NULL array");
   if (overlaps(g, up, u) || overlaps(g, u, un) || overlaps(g, up, un))
     return fail(FD_EINVAL, "fd_forward_run: the three wavefields must be distinct");
@@ -481,9 +485,22 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
   const float *ex, *ey, *ez;
   rc = check_sponge(&run->sponge, &ex, &ey, &ez);
   if (rc) return rc;
+  *nsend_out = nsend;
+  *nsend2_out = nsend2;
+  *ex_out = ex;
+  *ey_out = ey;
+  *ez_out = ez;
+  return FD_OK;
+}
+
+// The nt steps of a checked fd_run, enqueued on s; the struct's pointers are
+// rotated as the steps go (also when a launch fails part way).
+static hipError_t forward_steps(const fd_grid* g, fd_run* run, int nsend, int nsend2,
+                                const float* ex, const float* ey, const float* ez,
+                                hipStream_t s) {
+  float *up = run->u_prev, *u = run->u, *un = run->u_next;
   const Geo geo = make_geo(g);
   const Coef c = make_coef(g);
-  hipStream_t s = as_stream(stream);
   float** cur = run->send;   // faces of u
   float** nxt = run->send2;  // ping-pong: faces of u_next
   for (int32_t n = 0; n < run->nt; ++n) {
@@ -522,7 +539,7 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
       run->u_prev = up;
       run->u = u;
       run->u_next = un;
-      return check_hip(e, "fd_forward_run launch");
+      return e;
     }
     float* t = up;
     up = u;
@@ -534,8 +551,77 @@ int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
   run->u_next = un;
   if (cur != run->send)  // ping-pong: run->send holds the faces of the final u
     for (int f = 0; f < 6; ++f) std::swap(run->send[f], run->send2[f]);
+  return hipSuccess;
+}
+
+int fd_forward_run(const fd_grid* g, fd_run* run, void* stream) {
+  int nsend, nsend2;
+  const float *ex, *ey, *ez;
+  const int rc = forward_checked(g, run, &nsend, &nsend2, &ex, &ey, &ez);
+  if (rc) return rc;
+  return check_hip(forward_steps(g, run, nsend, nsend2, ex, ey, ez, as_stream(stream)),
+                   "fd_forward_run launch");
+}
+
+struct fd_graph {
+  hipGraphExec_t exec;
+};
+
+int fd_forward_graph(const fd_grid* g, fd_run* run, fd_graph** out) {
+  if (!out) return fail(FD_EINVAL, "fd_forward_graph: out is NULL");
+  *out = nullptr;
+  int nsend, nsend2;
+  const float *ex, *ey, *ez;
+  int rc = forward_checked(g, run, &nsend, &nsend2, &ex, &ey, &ez);
+  if (rc) return rc;
+  // recorded on a private stream (capture needs one that is not the null stream);
+  // the caller's struct changes only on success
+  hipStream_t cs = nullptr;
+  rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "fd_forward_graph stream");
+  if (rc) return rc;
+  fd_run r = *run;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    // the zero start: u^{n-1}, u^n and (exchange) the faces of u^n, by fill kernels
+    const int64_t n = last_elem(g) + 1;
+    hipError_t le = launch_zero(r.u_prev, n, cs);
+    if (le == hipSuccess) le = launch_zero(r.u, n, cs);
+    for (int f = 0; f < 6 && le == hipSuccess && nsend; ++f)
+      le = launch_zero(r.send[f], fd_face_elems(g, f), cs);
+    if (le == hipSuccess) le = forward_steps(g, &r, nsend, nsend2, ex, ey, ez, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    e = le != hipSuccess ? le : ee;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    return check_hip(e, "fd_forward_graph capture");
+  }
+  *out = new (std::nothrow) fd_graph{exec};
+  if (!*out) {
+    (void)hipGraphExecDestroy(exec);
+    return fail(FD_ENOMEM, "fd_forward_graph: out of host memory");
+  }
+  *run = r;
   return FD_OK;
 }
+
+int fd_graph_launch(fd_graph* graph, void* stream) {
+  if (!graph) return fail(FD_EINVAL, "fd_graph_launch: graph is NULL");
+  return check_hip(hipGraphLaunch(graph->exec, as_stream(stream)), "fd_graph_launch");
+}
+
+int fd_graph_destroy(fd_graph* graph) {
+  if (!graph) return FD_OK;
+  const int rc = check_hip(hipGraphExecDestroy(graph->exec), "fd_graph_destroy");
+  delete graph;
+  return rc;
+}
+
 
 int fd_receiver_plane_map(const fd_grid* g, const int32_t* rec_ijk, int32_t nrec, int32_t* map,
                           int32_t* k_out) {

@@ -302,3 +302,20 @@ def test_shot_footprint_and_server_argument_checks(L):
     assert L.shot_submit(None, C.byref(d), C.byref(C.c_int64())) == EINVAL
     assert L.shot_poll(None, 1, None, 0, None) == EINVAL
     assert L.fd_server_set_admission(None, 0) == EINVAL
+
+
+def test_forward_graph_argument_checks(L):
+    """fd_forward_graph checks its run exactly as fd_forward_run does, before it
+    records anything; launching or destroying a NULL graph is refused or a no-op."""
+    g = grid(L)
+    h = C.c_void_p()
+    r = _lib.fd_run()
+    assert L.fd_forward_graph(C.byref(g), C.byref(r), None) == _lib.FD_EINVAL
+    assert L.fd_forward_graph(C.byref(g), C.byref(r), C.byref(h)) == _lib.FD_EINVAL
+    assert b"NULL array" in L.fd_last_error()
+    assert h.value is None
+    r.u_prev, r.u, r.u_next, r.vdt2 = FAKE, FAKE, FAKE + 4, FAKE + 8
+    assert L.fd_forward_graph(C.byref(g), C.byref(r), C.byref(h)) == _lib.FD_EINVAL
+    assert b"distinct" in L.fd_last_error()
+    assert L.fd_graph_launch(None, None) == _lib.FD_EINVAL
+    assert L.fd_graph_destroy(None) == _lib.FD_OK

@@ -638,6 +638,76 @@ def test_exchange_step_with_all_faces_matches_separate_calls(tiles, nz, kc):
         api.set_tiles(0)
 
 
+@pytest.mark.parametrize("case", ["dirichlet", "exchange", "fused"])
+def test_forward_graph_replays_match_eager_runs(case):
+    """fd_forward_graph records a forward run once; every launch re-runs it from a
+    zero state (whatever the arrays held) with the bits of the eager native loop, with
+    eager work and synchronisations between launches, and a new model written into
+    vdt2 is picked up by the next launch: the 64^3 layered receiver-plane run, and
+    the loopback exchange with a sponge in its one-kernel and fused forms."""
+    if case == "dirichlet":
+        nx = ny = nz = 64
+        v = layered_velocity(nx, ny, nz, seed=1)
+        geom = api.Geometry(src=center_source(nx, ny, nz), rec=receivers_plane(nx, ny, 0))
+        width, exchange, mode, nt = 0, None, "native", 100
+    else:
+        nx, ny, nz = 64, 32, 24
+        v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
+        geom = api.Geometry(src=(5, 7, 11), rec=receivers_xline(nx, ny // 2, nz // 3))
+        width, exchange, nt = 4, "loopback", 40
+        mode = "native" if case == "exchange" else "native-fused"
+
+    def eager(vel, dt=None):
+        sim = api.Simulation(vel, sponge_width=width, exchange=exchange, geom=geom, dt=dt)
+        tr = sim.run(nt, mode=mode).clone()
+        return sim, tr, sim.state()[0].clone(), sim.state()[1].clone()
+
+    ref, tr_ref, up_ref, u_ref = eager(v)
+    sim = api.Simulation(v, sponge_width=width, exchange=exchange, geom=geom)
+    g = sim.grid
+    send = sim.send if exchange else None
+    send2 = sim.send2 if case == "exchange" else None
+
+    def poison():  # interiors and face buffers: the graph must start from zero anyway
+        for a in (sim.u_prev, sim.u, sim.u_next):
+            g.interior(a).copy_(torch.randn(nz, ny, nx, device="cuda"))
+        for f in (send or []) + (send2 or []):
+            f.copy_(torch.randn_like(f))
+
+    tr = torch.full((nt, sim.nrec), float("nan"), device="cuda")
+    poison()
+    G = api.ForwardGraph(g, sim.u_prev, sim.u, sim.u_next, sim.vdt2, sim.sponge, nt,
+                         src=geom.src, wavelet=api.ricker(nt, sim.dt), rec_off=sim.rec_off,
+                         traces=tr, send=send, send2=send2, rec_plane=sim.rec_plane)
+    try:
+        for rep in range(3):
+            tr.fill_(float("nan"))
+            G.launch()
+            torch.cuda.synchronize()
+            assert same_bits(tr, tr_ref), rep
+            assert same_bits(g.interior(G.u_prev), up_ref), rep
+            assert same_bits(g.interior(G.u), u_ref), rep
+            if send is not None:  # the faces of the final u
+                faces = api.face_buffers(g)
+                api.halo_pack(g, G.u, faces)
+                for a, b in zip(G.send, faces):
+                    assert same_bits(a, b), rep
+            x = torch.randn(1 << 16, device="cuda")
+            assert float((x * 2).sum()) == float((x * 2).sum())
+            poison()
+            torch.cuda.synchronize()
+        if case == "dirichlet":  # a new model in the same vdt2 array
+            other, tr_o, up_o, u_o = eager(v * 0.95, dt=ref.dt)
+            sim.vdt2.copy_(other.vdt2)
+            G.launch()
+            torch.cuda.synchronize()
+            assert same_bits(tr, tr_o)
+            assert same_bits(g.interior(G.u), u_o)
+            assert not same_bits(tr_o, tr_ref)
+    finally:
+        G.close()
+
+
 def test_large_subdomain_sampled_parity():
     """1024 x 1024 x 512 (four padded volumes of 2.3 GB), the smooth model, 16-cell
     sponge, Dirichlet halo, receivers on x = 0..1023 at y = 512, z = 4: after 12 steps
