@@ -123,12 +123,18 @@ int fd_set_kchunk(int32_t kchunk);
 /* Performance knob: tile shape of the forward stencil kernels (fd_step,
  * fd_step_fused, fd_step_exchange, fd_forward_run, fd_adjoint_step_scaled):
  * 0 = automatic (64 x 16 points for grids of at most 2^20 interior points,
- * 64 x 32 above), 1 = always 64 x 32, 2 = always 64 x 16.  Process-wide;
- * results do not depend on it.  FD_EINVAL for another mode. */
+ * 64 x 32 above; and a forward update that takes no faces inside the kernel --
+ * fd_step, fd_step_fused, fd_forward_run without a second face set -- runs one
+ * thread per point on grids of at most 2^22 points, which stay in cache and whose
+ * step is latency-bound), 1 = always 64 x 32, 2 = always 64 x 16 (both: never
+ * one thread per point), 3 = one thread per point wherever it applies (64 x 16
+ * elsewhere).  Process-wide; results do not depend on it.  FD_EINVAL for another
+ * mode. */
 int fd_set_tiles(int32_t mode);
 
-/* Launch shape of the forward stencil kernel (fd_step, fd_step_fused,
- * fd_step_exchange) over g, as the next such call would use it: out[0..3] =
+/* Launch shape of the z-marching forward stencil kernel (fd_step_exchange,
+ * and fd_step / fd_step_fused on grids that do not take the one-thread-per-point
+ * kernel, see fd_set_tiles) over g, as the next such call would use it: out[0..3] =
  * x tiles, y tiles, z planes per block, z chunks (blocks = their product; a
  * tile is 64 x 32 points, or 64 x 16, see fd_set_tiles).  Host only, no device
  * call; FD_EINVAL for a bad grid or NULL out. */

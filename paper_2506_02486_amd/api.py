@@ -360,7 +360,8 @@ def set_kchunk(kchunk: int):
 
 
 def set_tiles(mode: int):
-    """Forward tile shape: 0 automatic, 1 = 64 x 32, 2 = 64 x 16 (fd_set_tiles)."""
+    """Forward kernel shape (fd_set_tiles): 0 automatic, 1 = 64 x 32 tiles, 2 = 64 x 16
+    tiles, 3 = one thread per point wherever the update takes no faces inside."""
     check(lib().fd_set_tiles(int(mode)), "fd_set_tiles")
 
 

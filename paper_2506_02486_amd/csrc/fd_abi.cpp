@@ -99,6 +99,18 @@ bool overlaps(const fd_grid* g, const float* a, const float* b) {
   return a < b + n && b < a + n;
 }
 
+// The forward update with no faces inside the kernel: the one-thread-per-point
+// kernel on grids small enough to stay in cache, else the z-marching kernel (the
+// same bits either way).
+hipError_t forward_update(const Geo& geo, const Coef& c, const float* up, const float* u,
+                          float* un, const float* q, const float* ex, const float* ey,
+                          const float* ez, const fd_source* src, hipStream_t s,
+                          const RecPlane* rp = nullptr) {
+  if (point_kernel_pays(geo) && !(rp && rp->add))
+    return launch_step_point(geo, c, up, u, un, q, ex, ey, ez, src, rp, s);
+  return launch_step(geo, c, up, u, un, q, ex, ey, ez, src, s, rp);
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,8 +186,10 @@ int fd_set_kchunk(int32_t kchunk) {
 }
 
 int fd_set_tiles(int32_t mode) {
-  if (mode < 0 || mode > 2)
-    return fail(FD_EINVAL, "tile mode %d: 0 (automatic), 1 (64 x 32) or 2 (64 x 16)", mode);
+  if (mode < 0 || mode > 3)
+    return fail(FD_EINVAL,
+                "tile mode %d: 0 (automatic), 1 (64 x 32), 2 (64 x 16) or 3 (one thread per point)",
+                mode);
   set_tile_override(mode);
   return FD_OK;
 }
@@ -305,8 +319,8 @@ int fd_step(const fd_grid* g, const float* u_prev, const float* u, float* u_next
   const float *ex, *ey, *ez;
   rc = check_sponge(sp, &ex, &ey, &ez);
   if (rc) return rc;
-  return check_hip(launch_step(make_geo(g), make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez,
-                               nullptr, as_stream(stream)),
+  return check_hip(forward_update(make_geo(g), make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez,
+                                  nullptr, as_stream(stream)),
                    "fd_step launch");
 }
 
@@ -353,7 +367,7 @@ int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* 
   if (rc) return rc;
   const Geo geo = make_geo(g);
   hipStream_t s = as_stream(stream);
-  rc = check_hip(launch_step(geo, make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez, src, s),
+  rc = check_hip(forward_update(geo, make_coef(g), u_prev, u, u_next, vdt2, ex, ey, ez, src, s),
                  "fd_step_fused launch");
   if (rc || !face_out) return rc;
   return check_hip(launch_pack(geo, u_next, face_out, s), "fd_step_fused pack launch");
@@ -396,7 +410,7 @@ static hipError_t step_exchange(const Geo& geo, const Coef& c, const float* up, 
     return e;
   }
   if (face_in) e = launch_unpack(geo, u, face_in, s);
-  if (e == hipSuccess) e = launch_step(geo, c, up, u, un, q, ex, ey, ez, src, s);
+  if (e == hipSuccess) e = forward_update(geo, c, up, u, un, q, ex, ey, ez, src, s);
   if (e == hipSuccess && face_out) e = launch_pack_record(geo, un, face_out, rec_off, nrec, row, s);
   else if (e == hipSuccess && nrec > 0) e = launch_record(un, rec_off, nrec, row, s);
   return e;
@@ -528,8 +542,8 @@ static hipError_t forward_steps(const fd_grid* g, fd_run* run, int nsend, int ns
       const bool in_kernel = run->rec_map && run->nrec > 0 && !nsend && receiver_plane_pays(geo);
       if (nsend) e = launch_unpack(geo, u, recv, s);
       if (e == hipSuccess)
-        e = launch_step(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, s,
-                        in_kernel ? &rp : nullptr);
+        e = forward_update(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, s,
+                           in_kernel ? &rp : nullptr);
       if (e == hipSuccess && nsend)
         e = launch_pack_record(geo, un, cur, run->rec_off, run->nrec, row, s);
       else if (e == hipSuccess && run->nrec && !in_kernel)

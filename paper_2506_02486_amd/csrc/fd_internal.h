@@ -88,6 +88,16 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
                        float* un, const float* q, const float* ex, const float* ey,
                        const float* ez, const fd_source* src, hipStream_t s,
                        const RecPlane* rp = nullptr);
+// The same forward step by the one-thread-per-point kernel (small grids; same
+// bits).  rp, if given, must not be rp->add.
+hipError_t launch_step_point(const Geo& g, const Coef& c, const float* up, const float* u,
+                             float* un, const float* q, const float* ex, const float* ey,
+                             const float* ez, const fd_source* src, const RecPlane* rp,
+                             hipStream_t s);
+// Whether forward steps over g without faces in the kernel take the point kernel:
+// grids of at most kPointGridPoints points, or as forced by set_tile_override
+// (3: always, 1 or 2: never).
+bool point_kernel_pays(const Geo& g);
 // Planes per block (z chunk) for one launch over n grids, grid i with xy[i] x-y
 // tiles and nz[i] planes, with the least modelled time; at most kc_max planes
 // (0: no limit) and at most max_blocks blocks (the longest chunk is the fallback).

@@ -96,11 +96,25 @@ void set_kchunk_override(int kc) { g_kchunk_override.store(kc, std::memory_order
 bool forward_small_tiles(const Geo& g) {
   const int mode = g_tile_override.load(std::memory_order_relaxed);
   if (mode == 1) return false;
-  if (mode == 2) return true;
+  if (mode == 2 || mode == 3) return true;
   return (long long)g.nx * g.ny * g.nz <= kSmallGridPoints;
 }
 
 void set_tile_override(int mode) { g_tile_override.store(mode, std::memory_order_relaxed); }
+
+// Grids small enough to sit in cache run their forward step latency-bound; up to
+// about this size the one-thread-per-point kernel finishes first (native loop, 200
+// steps, us per step, marching against point: 64^3 4.52 / 3.51, with a sponge 5.16
+// / 3.72, 96^3 9.58 / 6.91, 128^3 13.4 / 12.1, 160^3 22.8 / 21.6, 176^3 27.8 /
+// 27.6, 192^3 29.4 / 30.0, 256^3 56.1 / 91.6).
+constexpr long long kPointGridPoints = 1LL << 22;
+
+bool point_kernel_pays(const Geo& g) {
+  const int mode = g_tile_override.load(std::memory_order_relaxed);
+  if (mode == 3) return true;
+  if (mode == 1 || mode == 2) return false;
+  return (long long)g.nx * g.ny * g.nz <= kPointGridPoints;
+}
 
 // The receiver row taken by the stencil launch saves a launch per step but adds a
 // dependent map lookup to the blocks of the receiver plane, whose finish sets the

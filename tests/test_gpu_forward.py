@@ -158,11 +158,12 @@ def test_degenerate_small_grids(shape):
 
 @pytest.mark.parametrize("shape", [(128, 40, 45), (70, 33, 29), (192, 80, 64), (128, 64, 40)])
 def test_results_independent_of_launch_shape(shape):
-    """The tile shape (fd_set_tiles: 64 x 32 or 64 x 16) and the z chunk (planes per
-    block, fd_set_kchunk) change the launch, never the bits: forward runs in the
-    exchange and fused forms and both adjoint steps give the same traces, fields and
-    gradient accumulators in both tile shapes, for chunks that end inside, at and past
-    the 9-plane unrolled loop, one plane and the whole depth."""
+    """The kernel shape (fd_set_tiles: 64 x 32 or 64 x 16 tiles, or one thread per
+    point, which the automatic choice takes for the fused form on these grids) and the
+    z chunk (planes per block, fd_set_kchunk) change the launch, never the bits:
+    forward runs in the exchange and fused forms and both adjoint steps give the same
+    traces, fields and gradient accumulators in every shape, for chunks that end
+    inside, at and past the 9-plane unrolled loop, one plane and the whole depth."""
     nx, ny, nz = shape
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
     geom = api.Geometry(src=(nx // 3, ny // 2, nz // 2), rec=receivers_xline(nx, ny // 3, nz // 3))
@@ -209,7 +210,7 @@ def test_results_independent_of_launch_shape(shape):
     api.set_tiles(0)
     ref = everything()
     try:
-        for tiles in (1, 2):
+        for tiles in (1, 2, 3):
             api.set_tiles(tiles)
             for kc in (0, 1, 2, 5, 9, 10, 17, nz):
                 api.set_kchunk(kc)
@@ -288,7 +289,8 @@ def test_resume_is_bitwise():
 
 
 @pytest.mark.parametrize("shape,tiles", [((64, 64, 64), 0), ((70, 33, 29), 1), ((70, 33, 29), 2),
-                                         ((256, 100, 48), 0), ((128, 64, 40), 1)])
+                                         ((256, 100, 48), 0), ((128, 64, 40), 1),
+                                         ((70, 33, 29), 3)])
 @pytest.mark.parametrize("faces", [0, 1, 2])
 def test_receiver_plane_in_stencil_matches_separate_record(shape, tiles, faces):
     """fd_forward_run with a receiver plane map (the stencil launch writes the trace
