@@ -287,8 +287,8 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
 def small_bench(steps=100, repeats=5):
     """64^3 plain forward: layered model (seed 1), Dirichlet halo, no sponge, Ricker at
     the centre, 4096 receivers on the k = 0 plane, run by the library's native step
-    loop.  The arrays (1.2 MB each) stay in cache, so the rate is launch-bound and
-    its HBM fraction means nothing; reported as the median of `repeats` runs."""
+    loop.  The arrays (1.2 MB each) stay in cache, so the rate is bound by latency
+    and its HBM fraction means nothing; reported as the median of `repeats` runs."""
     import numpy as np
     import torch
 
@@ -328,7 +328,7 @@ def small_bench(steps=100, repeats=5):
     G.close()
     gel = float(np.median(gtimes))
     return {"workload": "64^3 layered model, Dirichlet, no sponge, 4096 receivers at k=0, "
-                        f"{steps} steps (launch-bound; HBM fraction not meaningful)",
+                        f"{steps} steps (in cache, latency-bound; HBM fraction not meaningful)",
             "steps": steps, "repeats": repeats,
             "Gpts_per_s": round(n ** 3 * steps / el / 1e9, 2),
             "us_per_step": round(el * 1e6 / steps, 2),
@@ -436,7 +436,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--large", action="store_true", help="also time the 1024x1024x512 subdomain")
     ap.add_argument("--fwi", action="store_true", help="also time the 256^3 FWI gradient")
-    ap.add_argument("--no-small", action="store_true", help="skip the 64^3 launch-bound leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64^3 small-grid leg")
     ap.add_argument("--shots", type=int, default=256, help="shots in the serving stream")
     ap.add_argument("--vcache", default=None,
                     help="optional .npy path to cache the generated velocity model")
