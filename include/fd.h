@@ -245,9 +245,10 @@ int fd_step_exchange(const fd_grid* g, const float* u_prev, float* u, float* u_n
  * host array of nt floats, read before the call returns; traces is a device
  * array of nt*nrec floats (may be NULL when nt == 0); rec_off device int64
  * offsets (needed whenever nrec > 0).  With rec_map set, a step without faces
- * over a grid of at most 2^20 points (launch-bound) takes its receiver row in
- * the stencil launch; with faces the row is taken in the pack launch, otherwise
- * in a launch of its own.  Same bits either way. */
+ * over a grid of at most 2^20 points, or one that runs the one-thread-per-point
+ * kernel (see fd_set_tiles), takes its receiver row in the stencil launch; with
+ * faces the row is taken in the pack launch, otherwise in a launch of its own.
+ * Same bits either way. */
 typedef struct fd_run {
   float* u_prev;
   float* u;

@@ -539,7 +539,10 @@ static hipError_t forward_steps(const fd_grid* g, fd_run* run, int nsend, int ns
       nxt = t;
     } else {
       const RecPlane rp{run->rec_map, run->rec_k, row};
-      const bool in_kernel = run->rec_map && run->nrec > 0 && !nsend && receiver_plane_pays(geo);
+      // the one-thread-per-point kernel takes the row at the cost of one map load
+      // per thread of the plane (128^3, sponge: 12.6 -> 10.1 us per step)
+      const bool in_kernel = run->rec_map && run->nrec > 0 && !nsend &&
+                             (receiver_plane_pays(geo) || point_kernel_pays(geo));
       if (nsend) e = launch_unpack(geo, u, recv, s);
       if (e == hipSuccess)
         e = forward_update(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, s,
