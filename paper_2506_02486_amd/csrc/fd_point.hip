@@ -17,10 +17,12 @@ constexpr int PX = 64, PY = 4;
 
 template <bool SPONGE, bool REC>
 __global__ void __launch_bounds__(PX * PY)
-    point_kernel(Geo g, Coef c, const float* __restrict__ up, const float* __restrict__ u,
-                 float* __restrict__ un, const float* __restrict__ q, const float* __restrict__ ex,
+    point_kernel(Geo g, Coef c, const float* up, const float* __restrict__ u, float* un,
+                 const float* __restrict__ q, const float* __restrict__ ex,
                  const float* __restrict__ ey, const float* __restrict__ ez, int si, int sj, int sk,
                  float sw, const int32_t* __restrict__ rmap, int rk, float* __restrict__ rrow) {
+  // up and un may be one array (two-array stepping): each thread reads its point of
+  // up before it writes the same point of un, and touches no other point of either
   const int x = blockIdx.x * PX + threadIdx.x;
   const int y = blockIdx.y * PY + threadIdx.y;
   const int k = blockIdx.z;
