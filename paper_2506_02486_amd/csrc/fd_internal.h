@@ -116,8 +116,8 @@ void set_kchunk_override(int kc);
 // (0: automatic, 1: always 64 x 32, 2: always 64 x 16).
 bool forward_small_tiles(const Geo& g);
 void set_tile_override(int mode);
-// Whether a step over g takes its receiver row in the stencil launch (small,
-// launch-bound grids) rather than in a launch of its own.
+// Whether a z-marching step over g takes its receiver row in the stencil launch
+// (small grids, whose launches are short) rather than in a launch of its own.
 bool receiver_plane_pays(const Geo& g);
 // tiles_x, tiles_y, kchunk, zchunks of the forward stencil launch over g
 void forward_launch_shape(const Geo& g, int out[4]);

@@ -33,8 +33,8 @@ import torch
 
 from . import api
 
-# grids up to this many points are launch-bound: there the receiver residual is added
-# in the adjoint update's own launch (fd_adjoint_step_scaled_res)
+# grids up to this many points run short, latency-bound launches: there the receiver
+# residual is added in the adjoint update's own launch (fd_adjoint_step_scaled_res)
 SMALL_GRID_POINTS = 1 << 20
 
 
