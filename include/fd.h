@@ -126,7 +126,9 @@ int fd_set_kchunk(int32_t kchunk);
  * 64 x 32 above; and a forward update that takes no faces inside the kernel --
  * fd_step, fd_step_fused, fd_forward_run without a second face set -- runs one
  * thread per point on grids of at most 2^22 points, which stay in cache and whose
- * step is latency-bound), 1 = always 64 x 32, 2 = always 64 x 16 (both: never
+ * step is latency-bound, and so does fd_step_exchange / fd_forward_run with all
+ * twelve face buffers on grids of at most 2^21 points, the faces then read and
+ * written in that one launch), 1 = always 64 x 32, 2 = always 64 x 16 (both: never
  * one thread per point), 3 = one thread per point wherever it applies (64 x 16
  * elsewhere).  Process-wide; results do not depend on it.  FD_EINVAL for another
  * mode. */
@@ -217,7 +219,9 @@ int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* 
  * multiple of 64 and all four x-face buffers are given, the x faces are
  * exchanged inside the stencil kernel (their 16-byte row pieces would otherwise
  * cost whole cache lines in a separate pack and unpack); the y and z faces,
- * whole rows and planes, go through the unpack and pack kernels.  On return u's
+ * whole rows and planes, go through the unpack and pack kernels.  On grids of at
+ * most 2^21 points with all twelve face buffers given, the whole step is one
+ * launch of the one-thread-per-point kernel (see fd_set_tiles).  On return u's
  * face halos are unspecified (they may hold the face_in values).  face_in
  * buffers must not overlap face_out buffers or any volume array (a real
  * exchange double-buffers them: the loopback passes the faces of the previous

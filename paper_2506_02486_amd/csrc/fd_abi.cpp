@@ -387,14 +387,27 @@ static bool face_sets_overlap(const fd_grid* g, const float* const a[6], const f
 }
 
 // One step of the exchange form, arguments already checked; with receivers
-// (nrec > 0) the receiver row of un is taken in the launch that packs its faces.
+// (nrec > 0) the receiver row of un is taken in the launch that packs its faces,
+// or, on grids that run one thread per point with all twelve faces, in that one
+// launch (with a plane map, rec_map) or one of its own.
 static hipError_t step_exchange(const Geo& geo, const Coef& c, const float* up, float* u,
                                 float* un, const float* q, const float* ex, const float* ey,
                                 const float* ez, const fd_source* src,
                                 const float* const face_in[6], float* const face_out[6],
                                 hipStream_t s, const int64_t* rec_off = nullptr, int nrec = 0,
-                                float* row = nullptr) {
+                                float* row = nullptr, const int32_t* rec_map = nullptr,
+                                int rec_k = -1) {
   hipError_t e = hipSuccess;
+  bool all12 = face_in && face_out && point_exchange_pays(geo);
+  for (int f = 0; f < 6 && all12; ++f) all12 = face_in[f] && face_out[f];
+  if (all12) {  // small grid: the whole step in one launch
+    const RecPlane rp{rec_map, rec_k, row};
+    const bool in_kernel = rec_map && nrec > 0;
+    e = launch_step_point(geo, c, up, u, un, q, ex, ey, ez, src, in_kernel ? &rp : nullptr, s,
+                          face_in, face_out);
+    if (e == hipSuccess && nrec > 0 && !in_kernel) e = launch_record(un, rec_off, nrec, row, s);
+    return e;
+  }
   if (exchange_fits(geo) && face_in && face_out && face_in[0] && face_in[1] && face_out[0] &&
       face_out[1]) {
     // x faces inside the stencil kernel; y and z faces (whole rows and planes)
@@ -533,7 +546,7 @@ static hipError_t forward_steps(const fd_grid* g, fd_run* run, int nsend, int ns
     float* row = run->nrec ? run->traces + (int64_t)n * run->nrec : nullptr;
     if (nsend2) {
       e = step_exchange(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, recv, nxt, s,
-                        run->rec_off, run->nrec, row);
+                        run->rec_off, run->nrec, row, run->rec_map, run->rec_k);
       float** t = cur;
       cur = nxt;
       nxt = t;

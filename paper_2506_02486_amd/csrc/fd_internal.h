@@ -89,15 +89,21 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
                        const float* ez, const fd_source* src, hipStream_t s,
                        const RecPlane* rp = nullptr);
 // The same forward step by the one-thread-per-point kernel (small grids; same
-// bits).  rp, if given, must not be rp->add.
+// bits).  rp, if given, must not be rp->add.  With rin and sout (all twelve
+// non-NULL; every axis at least 4 long) the whole exchange step: u's halos read
+// from rin, the faces of un written to sout (halo_unpack / halo_pack layouts).
 hipError_t launch_step_point(const Geo& g, const Coef& c, const float* up, const float* u,
                              float* un, const float* q, const float* ex, const float* ey,
                              const float* ez, const fd_source* src, const RecPlane* rp,
-                             hipStream_t s);
+                             hipStream_t s, const float* const rin[6] = nullptr,
+                             float* const sout[6] = nullptr);
 // Whether forward steps over g without faces in the kernel take the point kernel:
 // grids of at most kPointGridPoints points, or as forced by set_tile_override
 // (3: always, 1 or 2: never).
 bool point_kernel_pays(const Geo& g);
+// The same for the exchange step with all six faces in the launch (at most
+// kPointExchangePoints points, or as forced).
+bool point_exchange_pays(const Geo& g);
 // Planes per block (z chunk) for one launch over n grids, grid i with xy[i] x-y
 // tiles and nz[i] planes, with the least modelled time; at most kc_max planes
 // (0: no limit) and at most max_blocks blocks (the longest chunk is the fallback).

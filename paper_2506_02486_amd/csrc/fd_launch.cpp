@@ -116,6 +116,19 @@ bool point_kernel_pays(const Geo& g) {
   return (long long)g.nx * g.ny * g.nz <= kPointGridPoints;
 }
 
+// The exchange step (six faces read and written in the same launch) pays off on
+// smaller grids only: loopback, sponge 8, x-line receivers, native loop, us per
+// step, point against the marching kernel with its pack and unpack launches: 64^3
+// 4.96 / 9.74, 96^3 10.5 / 15.1, 128^3 15.5 / 16.7, 160^3 30.1 / 27.3.
+constexpr long long kPointExchangePoints = 1LL << 21;
+
+bool point_exchange_pays(const Geo& g) {
+  const int mode = g_tile_override.load(std::memory_order_relaxed);
+  if (mode == 3) return true;
+  if (mode == 1 || mode == 2) return false;
+  return (long long)g.nx * g.ny * g.nz <= kPointExchangePoints;
+}
+
 // The receiver row taken by the stencil launch saves a launch per step but adds a
 // dependent map lookup to the blocks of the receiver plane, whose finish sets the
 // launch time: a gain where launches dominate (64^3: 6.4 -> 4.7 us per step), a loss
