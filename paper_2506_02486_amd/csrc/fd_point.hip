@@ -1,7 +1,8 @@
 // fd_point.hip -- the forward update of small grids, one thread per point.
 //
-// A grid of up to about a million points sits in the L2 and MALL caches between
-// steps, so its step is bound by latency, not bandwidth: the z-marching kernel's
+// A grid of up to a few million points (the limits are in fd_launch.cpp) sits in
+// the L2 and MALL caches between steps, so its step is bound by latency rather than
+// bandwidth: the z-marching kernel's
 // blocks spend most of their life filling the nine-plane register queue of a short
 // chunk.  Here every thread reads its 25 stencil values directly (cache hits after
 // the first step) and writes its point, so the whole grid is in flight at once.
