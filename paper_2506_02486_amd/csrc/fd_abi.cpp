@@ -106,8 +106,7 @@ hipError_t forward_update(const Geo& geo, const Coef& c, const float* up, const 
                           float* un, const float* q, const float* ex, const float* ey,
                           const float* ez, const fd_source* src, hipStream_t s,
                           const RecPlane* rp = nullptr) {
-  if (point_kernel_pays(geo) && !(rp && rp->add))
-    return launch_step_point(geo, c, up, u, un, q, ex, ey, ez, src, rp, s);
+  if (point_kernel_pays(geo)) return launch_step_point(geo, c, up, u, un, q, ex, ey, ez, src, rp, s);
   return launch_step(geo, c, up, u, un, q, ex, ey, ez, src, s, rp);
 }
 
@@ -845,7 +844,7 @@ static int adjoint_scaled(const fd_grid* g, const float* b_nn, const float* b_n1
   }
   // the forward update run backward in time: b_out = D (2 b_n1 - E b_nn + Q L b_n1),
   // with inj the scaled residual row added at the receivers in the same launch
-  return check_hip(launch_step(geo, c, b_nn, b_n1, b_out, vdt2, ex, ey, ez, nullptr, s, inj),
+  return check_hip(forward_update(geo, c, b_nn, b_n1, b_out, vdt2, ex, ey, ez, nullptr, s, inj),
                    "fd_adjoint_step_scaled launch");
 }
 

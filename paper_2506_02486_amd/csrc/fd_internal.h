@@ -89,9 +89,10 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
                        const float* ez, const fd_source* src, hipStream_t s,
                        const RecPlane* rp = nullptr);
 // The same forward step by the one-thread-per-point kernel (small grids; same
-// bits).  rp, if given, must not be rp->add.  With rin and sout (all twelve
-// non-NULL; every axis at least 4 long) the whole exchange step: u's halos read
-// from rin, the faces of un written to sout (halo_unpack / halo_pack layouts).
+// bits); rp as for launch_step (rp->add not in the exchange form).  With rin and
+// sout (all twelve non-NULL; every axis at least 4 long) the whole exchange step:
+// u's halos read from rin, the faces of un written to sout (halo_unpack /
+// halo_pack layouts).
 hipError_t launch_step_point(const Geo& g, const Coef& c, const float* up, const float* u,
                              float* un, const float* q, const float* ex, const float* ey,
                              const float* ez, const fd_source* src, const RecPlane* rp,

@@ -25,7 +25,9 @@ struct PFaces {
   float* out[6];
 };
 
-template <bool SPONGE, bool REC, bool XCH>
+// REC: 1 writes the receiver row of plane rk, 2 adds the row scaled by
+// vdt2 / (1+eta) there (the scaled adjoint's residual), as the marching kernel does
+template <bool SPONGE, int REC, bool XCH>
 __global__ void __launch_bounds__(PX * PY)
     point_kernel(Geo g, Coef c, const float* up, const float* __restrict__ u, float* un,
                  const float* __restrict__ q, const float* __restrict__ ex,
@@ -83,6 +85,14 @@ __global__ void __launch_bounds__(PX * PY)
 #pragma clang fp contract(off)
     v += pb * sw / (1.f + eta);
   }
+  if (REC == 2 && k == rk) {
+    const int rr = rmap[y * g.nx + x];
+    if (rr >= 0) {
+      // rounds as fd_scatter_add_scaled: the row value times vdt2 / (1+eta)
+#pragma clang fp contract(off)
+      v += rrow[rr] * (pb / (1.f + eta));
+    }
+  }
   un[o] = v;  // a plain store: the next step reads it from cache
   if (XCH) {  // the faces of the result that hold this point
     const unsigned ux = (unsigned)x, uy = (unsigned)y, uk = (unsigned)k;
@@ -93,7 +103,7 @@ __global__ void __launch_bounds__(PX * PY)
     if (k < 4) fc.out[4][(uk * ny + uy) * nx + ux] = v;
     if (k >= g.nz - 4) fc.out[5][((uk - (nz - 4u)) * ny + uy) * nx + ux] = v;
   }
-  if (REC && k == rk) {
+  if (REC == 1 && k == rk) {
     const int rr = rmap[y * g.nx + x];
     if (rr >= 0) rrow[rr] = v;
   }
@@ -105,8 +115,8 @@ hipError_t launch_step_point(const Geo& g, const Coef& c, const float* up, const
                              float* un, const float* q, const float* ex, const float* ey,
                              const float* ez, const fd_source* src, const RecPlane* rp,
                              hipStream_t s, const float* const rin[6], float* const sout[6]) {
-  if (rp && rp->map && rp->add) return hipErrorInvalidValue;  // the forward step only records
   const bool xch = rin != nullptr;
+  if (xch && rp && rp->map && rp->add) return hipErrorInvalidValue;  // exchange: records only
   PFaces fc{};
   if (xch) {
     if (!sout || g.nx < 4 || g.ny < 4 || g.nz < 4) return hipErrorInvalidValue;
@@ -124,19 +134,22 @@ hipError_t launch_step_point(const Geo& g, const Coef& c, const float* up, const
   const int32_t* map = rec ? rp->map : nullptr;
   const int rk = rec ? rp->k : -1;
   float* row = rec ? rp->row : nullptr;
-  const int variant = (ex ? 4 : 0) | (rec ? 2 : 0) | (xch ? 1 : 0);
+  const int recm = rec ? (rp->add ? 2 : 1) : 0;
+  const int variant = (ex ? 8 : 0) | (recm << 1) | (xch ? 1 : 0);
 #define FD_POINT(SP, RC, XC)                                                                   \
   hipLaunchKernelGGL((point_kernel<SP, RC, XC>), grid, dim3(PX, PY), 0, s, g, c, up, u, un, q, \
                      ex, ey, ez, si, sj, sk, sw, map, rk, row, fc)
   switch (variant) {
-    case 7: FD_POINT(true, true, true); break;
-    case 6: FD_POINT(true, true, false); break;
-    case 5: FD_POINT(true, false, true); break;
-    case 4: FD_POINT(true, false, false); break;
-    case 3: FD_POINT(false, true, true); break;
-    case 2: FD_POINT(false, true, false); break;
-    case 1: FD_POINT(false, false, true); break;
-    default: FD_POINT(false, false, false); break;
+    case 8 | 2 | 1: FD_POINT(true, 1, true); break;
+    case 8 | 2: FD_POINT(true, 1, false); break;
+    case 8 | 4: FD_POINT(true, 2, false); break;
+    case 8 | 1: FD_POINT(true, 0, true); break;
+    case 8: FD_POINT(true, 0, false); break;
+    case 2 | 1: FD_POINT(false, 1, true); break;
+    case 2: FD_POINT(false, 1, false); break;
+    case 4: FD_POINT(false, 2, false); break;
+    case 1: FD_POINT(false, 0, true); break;
+    default: FD_POINT(false, 0, false); break;
   }
 #undef FD_POINT
   return hipGetLastError();
