@@ -124,7 +124,8 @@ int fd_set_kchunk(int32_t kchunk);
  * fd_step_fused, fd_step_exchange, fd_forward_run, fd_adjoint_step_scaled):
  * 0 = automatic (64 x 16 points for grids of at most 2^20 interior points,
  * 64 x 32 above; and a forward update that takes no faces inside the kernel --
- * fd_step, fd_step_fused, fd_forward_run without a second face set -- runs one
+ * fd_step, fd_step_fused, fd_forward_run without a second face set,
+ * fd_adjoint_step_scaled(_res) -- runs one
  * thread per point on grids of at most 2^22 points, which stay in cache and whose
  * step is latency-bound, and so does fd_step_exchange / fd_forward_run with all
  * twelve face buffers on grids of at most 2^21 points, the faces then read and
