@@ -366,7 +366,8 @@ def set_tiles(mode: int):
 
 
 def step_launch(grid: Grid) -> dict:
-    """Launch shape of the forward stencil kernel over ``grid`` (fd_step_launch)."""
+    """Launch shape of the z-marching forward kernel over ``grid`` (fd_step_launch); grids
+    of at most 2^22 points run fd_step and the fused forms one thread per point."""
     out = (C.c_int32 * 4)()
     check(lib().fd_step_launch(grid.ref, out), "fd_step_launch")
     tx, ty, kc, zc = out
