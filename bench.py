@@ -336,6 +336,38 @@ def small_bench(steps=100, repeats=5):
             "graph_us_per_step": round(gel * 1e6 / steps, 2)}
 
 
+def small_exchange_bench(n=64, steps=200, repeats=5):
+    """A small subdomain's exchange step: n^3 smooth model (seed 2), sponge 8, Ricker at
+    the centre, receivers on the centre x-line, the six faces exchanged (loopback) every
+    step, run by the library's native loop with two face sets (on a grid this small the
+    whole step is one launch of the one-thread-per-point kernel); median of `repeats`."""
+    import numpy as np
+    import torch
+
+    from paper_2506_02486_amd import api
+    from workloads import center_source, receivers_xline, smooth_velocity
+
+    v = smooth_velocity(n, n, n, seed=2, sigma=4.0)
+    geom = api.Geometry(src=center_source(n, n, n), rec=receivers_xline(n, n // 2, n // 2))
+    times = []
+    for r in range(repeats + 1):
+        sim = api.Simulation(v, sponge_width=8, exchange="loopback", geom=geom)
+        tr = torch.zeros((steps, sim.nrec), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(steps, tr, mode="native")
+        torch.cuda.synchronize()
+        if r:
+            times.append(time.perf_counter() - t0)
+        del sim, tr
+    el = float(np.median(times))
+    return {"workload": f"{n}^3 smooth model, sponge 8, six faces exchanged (loopback) every "
+                        f"step, {n}-point x-line receivers, {steps} steps (in cache, latency-bound)",
+            "steps": steps, "repeats": repeats,
+            "Gpts_per_s": round(n ** 3 * steps / el / 1e9, 2),
+            "us_per_step": round(el * 1e6 / steps, 2)}
+
+
 def large_bench(steps=500, warmup=5):
     """1024 x 1024 x 512 subdomain, sponge 16, Dirichlet halo, receivers on a 1024-point
     line at z = 4: the same per-step path without the exchange."""
@@ -604,6 +636,7 @@ def main():
         out["serving_small"] = serving_bench(nshots=args.shots, lo=48, hi=128, caps=())
     if not args.no_small:
         out["small"] = small_bench()
+        out["small_exchange"] = small_exchange_bench()
     if args.large:
         out["large"] = large_bench()
     if args.fwi:
