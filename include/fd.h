@@ -98,7 +98,11 @@ int fd_version(void);
 
 /* ----------------------------------------------------------- geometry */
 
-/* Fill *g for an nx*ny*nz interior with spacing (dx,dy,dz): halo 4, the
+/* The subdomain of one rank with its boundary planes (Sec. 4.5 and Listing 1:
+ * each rank owns a block of the grid and exchanges the planes next to its
+ * faces); the paper gives no memory layout, the one below is this library's.
+ *
+ * Fill *g for an nx*ny*nz interior with spacing (dx,dy,dz): halo 4, the
  * interior row start 128-byte aligned (32 floats of left padding, of which
  * the last 4 are the x halo), ystride a multiple of 32 floats, zstride =
  * ystride*(ny+8).  FD_EINVAL on bad sizes or spacing, or if zstride would
@@ -115,7 +119,10 @@ int64_t fd_face_elems(const fd_grid* g, int32_t face);
  * [-4, n+4) on an axis. */
 int64_t fd_offset(const fd_grid* g, int32_t i, int32_t j, int32_t k);
 
-/* Performance knob: number of z planes each block of the stencil kernels
+/* Performance knobs (no passage of the paper defines them; they change launch
+ * shapes, never results).
+ *
+ * Number of z planes each block of the stencil kernels
  * marches through (0 = automatic, the default).  Process-wide; results do not
  * depend on it. */
 int fd_set_kchunk(int32_t kchunk);
@@ -144,7 +151,10 @@ int fd_set_tiles(int32_t mode);
 int fd_step_launch(const fd_grid* g, int32_t out[4]);
 
 /* ----------------------------------------------------------- model prep
- * (set-up, step S0; not on the per-step path) */
+ * (set-up, step S0; not on the per-step path).  The paper names the acoustic
+ * isotropic kernel (Sec. 4.5) but states no time step, velocity scaling,
+ * boundary damping, source or receivers; each call below is one reading of
+ * what such a kernel needs, stated with the call. */
 
 /* Device reduction of max(v) over the interior of v; writes it to
  * *vmax_host and computes dt = courant * min(dx,dy,dz) / max(v) into *dt_out
@@ -190,7 +200,10 @@ int fd_receiver_offsets(const fd_grid* g, const int32_t* ijk_host, int32_t nrec,
 
 /* ------------------------------------------------------- per-step path */
 
-/* S4: one leapfrog update of every interior point,
+/* S4, the stencil update that the paper's Minimod runs as one device kernel
+ * per time step over the rank's subdomain (Sec. 4.5); the stencil order and
+ * the time scheme are this library's reading (file header).
+ * One leapfrog update of every interior point,
  *   u_next = (2u - (1-eta) u_prev + vdt2 * L u) / (1+eta)
  * (eta = 0 without a sponge).  L reads u's face halos as they are (zeros for
  * a Dirichlet boundary, or what halo_unpack wrote).  Reads only interior
@@ -200,7 +213,8 @@ int fd_receiver_offsets(const fd_grid* g, const int32_t* ijk_host, int32_t nrec,
 int fd_step(const fd_grid* g, const float* u_prev, const float* u, float* u_next,
             const float* vdt2, const fd_sponge* sp, void* stream);
 
-/* S4+S5+S1 in one call: fd_step with (src non-NULL) the source term src->w
+/* S4+S5+S1 in one call (Sec. 4.5 update, then the pack of the planes that
+ * Listing 1 puts to the neighbours): fd_step with (src non-NULL) the source term src->w
  * added in the same kernel exactly as inject_source adds it, then
  * (face_out non-NULL) the six-face pack of the new u_next exactly as
  * halo_pack writes it (NULL entries skipped; faces need n >= 4 on their axis
@@ -211,7 +225,7 @@ int fd_step_fused(const fd_grid* g, const float* u_prev, const float* u, float* 
                   float* const face_out[6], void* stream);
 
 /* S3+S4+S5+S1, the whole per-step exchange path (the paper's subdomain step
- * between two halo exchanges, Sec. 4 and Listing 1): the face halos of u are
+ * between two halo exchanges, Sec. 4.5 and Listing 1): the face halos of u are
  * read from the receive buffers face_in (halo_unpack layouts; NULL array or
  * NULL entry: u's own halo on that face), u_next is updated as by fd_step with
  * the source term of src (may be NULL), and the faces of u_next are written to
@@ -232,7 +246,8 @@ int fd_step_exchange(const fd_grid* g, const float* u_prev, float* u, float* u_n
                      const float* const face_in[6], float* const face_out[6],
                      void* stream);
 
-/* S1-S7 for nt steps, the host loop in native code: per step n,
+/* S1-S7 for nt steps (the time loop of Sec. 4.5, with the exchange of
+ * Listing 1 each step), the host loop in native code: per step n,
  *   (send given) halo_unpack(u, receive = the opposite face of send),
  *   fd_step_fused(u_prev, u -> u_next, source w[n] at src if wavelet non-NULL),
  *   (send given) halo_pack(u_next -> send),
@@ -276,11 +291,12 @@ typedef struct fd_run {
 } fd_run;
 int fd_forward_run(const fd_grid* g, fd_run* run, void* stream);
 
-/* A recorded forward run (HIP graph), for small grids that are modelled again
+/* No passage of the paper defines this call (a launch-cost optimisation of
+ * fd_forward_run).  A recorded forward run (HIP graph), for small grids that are modelled again
  * and again (FWI iterations, model scans): one graph launch replaces the
  * per-step launches of fd_forward_run, whose host and dispatch cost is a share
  * of a small grid's step (64^3: 3.37 against 3.61 us per step).  fd_forward_graph checks *run exactly as fd_forward_run does and
- * records, without running anything: zeroing u_prev and u (whole padded arrays)
+ * records, without running anything: zeroing u_prev, u and u_next (whole padded arrays)
  * and, with faces, send[0..5]; then the run->nt steps of fd_forward_run.  The
  * wavelet values and every pointer are fixed at recording; array contents (vdt2,
  * sponge tables, receiver map) are read at each launch, so a new model written
@@ -297,7 +313,8 @@ int fd_graph_launch(fd_graph* graph, void* stream);
 /* Frees the graph (NULL: no-op); the caller makes sure no launch is pending. */
 int fd_graph_destroy(fd_graph* graph);
 
-/* Host helper for fd_run.rec_map: when all nrec >= 1 receivers (rec_ijk: 3*nrec
+/* No passage of the paper defines receivers (see record_receivers).
+ * Host helper for fd_run.rec_map: when all nrec >= 1 receivers (rec_ijk: 3*nrec
  * interior (i,j,k) triples) lie on one z plane at distinct (i,j), fills map
  * (host, nx*ny int32) with map[j*nx + i] = r for receiver r and -1 elsewhere,
  * sets *k_out to the plane and returns FD_OK; else FD_EINVAL (the receivers
@@ -305,17 +322,24 @@ int fd_graph_destroy(fd_graph* graph);
 int fd_receiver_plane_map(const fd_grid* g, const int32_t* rec_ijk, int32_t nrec,
                           int32_t* map, int32_t* k_out);
 
-/* S5: u_next[s] += vdt2[s] * w / (1+eta[s]) at interior point s = (i,j,k). */
+/* S5: the paper's application is seismic wave propagation (Sec. 4.5) but it
+ * states no source term; this is the reading the library takes:
+ * u_next[s] += vdt2[s] * w / (1+eta[s]) at interior point s = (i,j,k). */
 int inject_source(const fd_grid* g, float* u_next, const float* vdt2,
                   const fd_sponge* sp, int32_t i, int32_t j, int32_t k, float w,
                   void* stream);
 
-/* S6: trace_row[r] = u[rec_off[r]] for r < nrec (rec_off: device int64
+/* S6: no passage of the paper defines receivers (Sec. 4.5 names the
+ * application only); the reading here samples the updated field:
+ * trace_row[r] = u[rec_off[r]] for r < nrec (rec_off: device int64
  * element offsets, e.g. from fd_receiver_offsets; trace_row: device). */
 int record_receivers(const fd_grid* g, const float* u, const int64_t* rec_off,
                      int32_t nrec, float* trace_row, void* stream);
 
-/* S1: copy the 4 outermost interior planes of u on each face into the six
+/* S1, the send side of the halo exchange of Listing 1 (Sec. 4.5): the
+ * boundary planes a rank puts to its neighbours, here packed into contiguous
+ * buffers (the paper's 1-D decomposition puts them in place; six faces serve
+ * any decomposition).  Copy the 4 outermost interior planes of u on each face into the six
  * contiguous device buffers face[0..5] = -x,+x,-y,+y,-z,+z (the data a halo
  * exchange sends to the neighbour on that side).  Layouts, x fastest, q = 0..3
  * counting from the lower index:
@@ -325,7 +349,8 @@ int record_receivers(const fd_grid* g, const float* u, const int64_t* rec_off,
  * A NULL face is skipped.  Faces need n >= 4 on their axis (else FD_EINVAL). */
 int halo_pack(const fd_grid* g, const float* u, float* const face[6], void* stream);
 
-/* S1 + S6 in one launch: halo_pack(g, u, face) and record_receivers(g, u,
+/* S1 + S6 in one launch (Listing 1's send side and the receiver reading of
+ * record_receivers): halo_pack(g, u, face) and record_receivers(g, u,
  * rec_off, nrec, trace_row), the faces and the receiver row of the same u (the
  * end of a step: the data the next exchange sends and the trace row n).  Same
  * arguments, layouts and errors as the two calls; nrec == 0 packs only.  Two
@@ -334,7 +359,9 @@ int fd_halo_pack_record(const fd_grid* g, const float* u, float* const face[6],
                         const int64_t* rec_off, int32_t nrec, float* trace_row,
                         void* stream);
 
-/* S3: write six receive buffers (same layouts as halo_pack) into the face
+/* S3, the receive side of Listing 1: after the fence, the planes the
+ * neighbours put are in place; here they are copied from contiguous receive
+ * buffers into the halo.  Write six receive buffers (same layouts as halo_pack) into the face
  * halos of u: face[0] (-x, from the -x neighbour's +x face) fills
  * i = -4+q, face[1] (+x) fills i = nx+q, and likewise for y and z.  Edges and
  * corners of the halo are never touched.  A NULL face leaves that halo as it
@@ -343,6 +370,9 @@ int fd_halo_pack_record(const fd_grid* g, const float* u, float* const face[6],
 int halo_unpack(const fd_grid* g, float* u, const float* const face[6], void* stream);
 
 /* ----------------------------------------------------------- adjoint
+ * No passage of the paper defines an adjoint or a gradient (it runs the
+ * forward kernel only); these calls are the exact transpose of the forward
+ * recurrence above, an addition of this library.
  * Transpose of the forward step, for the FWI gradient with respect to
  * squared slowness.  With D = 1/(1+eta), E = 1-eta, Q = vdt2, the forward
  * step is u^{n+1} = D (2u^n - E u^{n-1} + Q (L u^n + f^n)). */
@@ -363,7 +393,8 @@ int fd_adjoint_step(const fd_grid* g, const float* a_nn, const float* a_n1,
 int fd_scatter_add(const fd_grid* g, float* a, const int64_t* off, const float* vals,
                    int32_t n, void* stream);
 
-/* grad_m = -g_vdt2 * vdt2^2 / dt^2 on the interior (m = 1/v^2, dt fixed). */
+/* grad_m = -g_vdt2 * vdt2^2 / dt^2 on the interior (m = 1/v^2, dt fixed);
+ * grad_m may alias g_vdt2 (in place), not vdt2. */
 int fd_grad_finalize(const fd_grid* g, const float* g_vdt2, const float* vdt2,
                      double dt, float* grad_m, void* stream);
 
@@ -406,11 +437,16 @@ int fd_scatter_add_scaled(const fd_grid* g, float* b, const int64_t* off,
                           int32_t n, void* stream);
 
 /* grad_m = -g_b * vdt2 / dt^2 on the interior, for the g_b accumulated by
- * fd_adjoint_step_scaled (grad_m may alias g_b). */
+ * fd_adjoint_step_scaled (grad_m may alias g_b, not vdt2). */
 int fd_grad_finalize_scaled(const fd_grid* g, const float* g_b, const float* vdt2,
                             double dt, float* grad_m, void* stream);
 
 /* ------------------------------------------------------- shot serving
+ * No passage of the paper defines shot serving.  The server is this library's
+ * one-device analogue of two runtime mechanisms of the paper: device memory
+ * taken from one runtime-owned segment by a heap allocator (Sec. 3.1, the
+ * global segment with a linear-heap or buddy allocator) and a bounded number
+ * of concurrently active units of work (Sec. 3.2, MAX_ACTIVE_STREAMS).
  * S8/S9: a server that runs many independent forward-modelling shots of
  * different grid sizes at once.  Shots are admitted in submission order
  * (strict FIFO) while a slot is free and the shot's footprint fits in the

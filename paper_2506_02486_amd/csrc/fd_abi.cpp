@@ -612,10 +612,12 @@ int fd_forward_graph(const fd_grid* g, fd_run* run, fd_graph** out) {
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    // the zero start: u^{n-1}, u^n and (exchange) the faces of u^n, by fill kernels
+    // the zero start: u^{n-1}, u^n, u^{n+1} (whose halo is the boundary once it
+    // rotates into u^n) and (exchange) the faces of u^n, by fill kernels
     const int64_t n = last_elem(g) + 1;
     hipError_t le = launch_zero(r.u_prev, n, cs);
     if (le == hipSuccess) le = launch_zero(r.u, n, cs);
+    if (le == hipSuccess && r.u_next != r.u_prev) le = launch_zero(r.u_next, n, cs);
     for (int f = 0; f < 6 && le == hipSuccess && nsend; ++f)
       le = launch_zero(r.send[f], fd_face_elems(g, f), cs);
     if (le == hipSuccess) le = forward_steps(g, &r, nsend, nsend2, ex, ey, ez, cs);

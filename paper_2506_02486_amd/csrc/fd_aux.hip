@@ -291,10 +291,11 @@ __global__ void __launch_bounds__(BS) vmax_kernel(int nx, int ny, int nz,
 
 // scaled: the accumulator holds sum b (L u + f) with b = Q D lambda, so that
 // g_vdt2 = acc / Q and grad_m = -acc Q / dt^2; else acc = g_vdt2 and
-// grad_m = -acc Q^2 / dt^2.
-__global__ void __launch_bounds__(BS) grad_finalize_kernel(Geo g, const float* __restrict__ gq,
+// grad_m = -acc Q^2 / dt^2.  gm may be gq itself (in place: each thread reads and
+// then writes its own element), so neither carries __restrict__.
+__global__ void __launch_bounds__(BS) grad_finalize_kernel(Geo g, const float* gq,
                                                            const float* __restrict__ q, float s,
-                                                           bool scaled, float* __restrict__ gm) {
+                                                           bool scaled, float* gm) {
   const int j = blockIdx.y;
   const int k = blockIdx.z;
   for (int i = blockIdx.x * BS + threadIdx.x; i < g.nx; i += gridDim.x * BS) {

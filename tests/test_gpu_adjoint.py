@@ -201,19 +201,27 @@ def test_fwi_gradient_matches_oracle_and_central_differences():
     # The residual is a small difference of nearby models, so the FP32 forward error
     # (~1e-5 of the traces) is amplified in J and in the adjoint source; those two are
     # compared loosely against the oracle's own forward ...
-    assert abs(J - ref["J"]) <= 1e-2 * ref["J"]
-    assert rel_l2(gm, ref["grad_m"]) <= 2e-2
+    e_J = abs(J - ref["J"]) / ref["J"]
+    e_g = rel_l2(gm, ref["grad_m"])
+    print(f"FWI 64^3: J rel err {e_J:.2e}, gradient vs oracle rel L2 {e_g:.2e}")
+    assert e_J <= 1e-2
+    assert e_g <= 2e-2
     # ... and the adjoint sweep itself tightly: the oracle is driven by exactly the
     # residual the GPU saw (obs shifted by the GPU-minus-oracle trace difference).
     tr_gpu = prob.forward(m, checkpoints=False).cpu().numpy().astype(np.float64)
     obs_same = ref["traces"] - (tr_gpu - obs.astype(np.float32).astype(np.float64))
     ref_same = ora.fwi_gradient(None, nt, dt, obs_same, src, w, rec, D10, eta, q=dt * dt / m0)
-    assert rel_l2(gm, ref_same["grad_m"]) <= 1e-3
+    e_same = rel_l2(gm, ref_same["grad_m"])
     # the adjoint in lambda itself (fd_adjoint_step) gives the same gradient
     tr = prob.forward(m)
     gm_a = prob.backward(tr - obs_t, scaled=False).cpu().numpy()
-    assert rel_l2(gm_a, ref_same["grad_m"]) <= 1e-3
-    assert rel_l2(gm_a, gm) <= 5e-4
+    e_same_a = rel_l2(gm_a, ref_same["grad_m"])
+    e_ab = rel_l2(gm_a, gm)
+    print(f"FWI 64^3: same residual: scaled {e_same:.2e}, lambda {e_same_a:.2e}, "
+          f"scaled vs lambda {e_ab:.2e}")
+    assert e_same <= 1e-3
+    assert e_same_a <= 1e-3
+    assert e_ab <= 5e-4
     vox = fd_voxels(ref["grad_m"], count=16, seed=5)
 
     def Jo(mm):
@@ -227,15 +235,20 @@ def test_fwi_gradient_matches_oracle_and_central_differences():
         mm = m0.copy(); mm.flat[p] -= h
         fd.append((Jo(mp) - Jo(mm)) / (2 * h))
     fd = np.array(fd)
-    assert rel_l2(ref["grad_m"].flat[vox], fd) <= 1e-6
-    assert rel_l2(gm.flat[vox], fd) <= 2e-2
+    e_ofd = rel_l2(ref["grad_m"].flat[vox], fd)
+    e_gfd = rel_l2(gm.flat[vox], fd)
+    print(f"FWI 64^3: oracle vs FD {e_ofd:.2e}, GPU vs FD {e_gfd:.2e}")
+    assert e_ofd <= 1e-6
+    assert e_gfd <= 2e-2
 
 
-@pytest.mark.parametrize("tiles", [1, 2])
+@pytest.mark.parametrize("tiles", [0, 1, 2, 3])
 def test_residual_plane_in_adjoint_launch_matches_scatter(tiles):
     """fd_adjoint_step_scaled_res (the residual row added at receivers on one plane in
     the update's launch) gives the bits of fd_adjoint_step_scaled followed by
-    fd_scatter_add_scaled, receivers inside and outside the sponge, both tile shapes."""
+    fd_scatter_add_scaled, receivers inside and outside the sponge: automatic shape (this
+    small grid takes the one-thread-per-point kernel), both marching tile shapes, and the
+    point kernel forced."""
     nx, ny, nz = 70, 37, 29
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
     sim = api.Simulation(v, sponge_width=6)
