@@ -18,8 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfd.so")
 
-SOURCES = ["fd_abi.cpp", "fd_launch.cpp", "fd_stencil.hip", "fd_point.hip", "fd_aux.hip",
-           "fd_server.cpp"]
+SOURCES = ["fd_abi.cpp", "fd_launch.cpp", "fd_stencil.hip", "fd_stencil4.hip", "fd_point.hip",
+           "fd_aux.hip", "fd_server.cpp"]
 
 ARCH = "gfx950"
 FLAGS = [

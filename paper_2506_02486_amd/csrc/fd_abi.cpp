@@ -185,9 +185,10 @@ int fd_set_kchunk(int32_t kchunk) {
 }
 
 int fd_set_tiles(int32_t mode) {
-  if (mode < 0 || mode > 3)
+  if (mode < 0 || mode > 4)
     return fail(FD_EINVAL,
-                "tile mode %d: 0 (automatic), 1 (64 x 32), 2 (64 x 16) or 3 (one thread per point)",
+                "tile mode %d: 0 (automatic), 1 (64 x 32), 2 (64 x 16), 3 (one thread per point) "
+                "or 4 (128 x 32, 16-byte lanes)",
                 mode);
   set_tile_override(mode);
   return FD_OK;

@@ -123,6 +123,24 @@ void set_kchunk_override(int kc);
 // (0: automatic, 1: always 64 x 32, 2: always 64 x 16).
 bool forward_small_tiles(const Geo& g);
 void set_tile_override(int mode);
+// Forward updates over g (no receiver row in the kernel) take the 16-byte-lane
+// kernel of fd_stencil4.hip: bandwidth-bound grids (more than kWideGridPoints
+// interior points), or as forced by set_tile_override (4: wherever it fits; 1, 2,
+// 3: never).
+bool forward_wide_tiles(const Geo& g);
+// Whether the 16-byte-lane kernel can take a step over g: rows, strides and origin
+// multiples of 4 floats, the four volume arrays (u_prev, u, u_next, vdt2) 16-byte
+// aligned; with faces (-x in, +x in, -x out, +x out; NULL: no exchange) nx a multiple
+// of its tile width and the four buffers 16-byte aligned.
+bool wide_forward_fits(const Geo& g, const float* const arrays[4], const float* const faces[4]);
+// tiles_x, tiles_y, kchunk, zchunks of the 16-byte-lane kernel's launch over g
+void wide_forward_shape(const Geo& g, int out[4]);
+// The forward step (launch_step, or with rin/sout launch_step_exchange) by the
+// 16-byte-lane kernel; same bits.
+hipError_t launch_forward_wide(const Geo& g, const Coef& c, const float* up, const float* u,
+                               float* un, const float* q, const float* ex, const float* ey,
+                               const float* ez, const fd_source* src, const float* const rin[2],
+                               float* const sout[2], hipStream_t s);
 // Whether a z-marching step over g takes its receiver row in the stencil launch
 // (small grids, whose launches are short) rather than in a launch of its own.
 bool receiver_plane_pays(const Geo& g);

@@ -95,12 +95,23 @@ void set_kchunk_override(int kc) { g_kchunk_override.store(kc, std::memory_order
 
 bool forward_small_tiles(const Geo& g) {
   const int mode = g_tile_override.load(std::memory_order_relaxed);
-  if (mode == 1) return false;
+  if (mode == 1 || mode == 4) return false;
   if (mode == 2 || mode == 3) return true;
   return (long long)g.nx * g.ny * g.nz <= kSmallGridPoints;
 }
 
 void set_tile_override(int mode) { g_tile_override.store(mode, std::memory_order_relaxed); }
+
+// Above this size a grid's arrays stream from HBM every step and the 16-byte-lane
+// kernel's wider, deeper loads pay.
+constexpr long long kWideGridPoints = 1LL << 24;
+
+bool forward_wide_tiles(const Geo& g) {
+  const int mode = g_tile_override.load(std::memory_order_relaxed);
+  if (mode == 4) return true;
+  if (mode != 0) return false;
+  return (long long)g.nx * g.ny * g.nz >= kWideGridPoints;
+}
 
 // Grids small enough to sit in cache run their forward step latency-bound; up to
 // about this size the one-thread-per-point kernel finishes first (native loop, 200
@@ -112,7 +123,7 @@ constexpr long long kPointGridPoints = 1LL << 22;
 bool point_kernel_pays(const Geo& g) {
   const int mode = g_tile_override.load(std::memory_order_relaxed);
   if (mode == 3) return true;
-  if (mode == 1 || mode == 2) return false;
+  if (mode == 1 || mode == 2 || mode == 4) return false;
   return (long long)g.nx * g.ny * g.nz <= kPointGridPoints;
 }
 
@@ -125,7 +136,7 @@ constexpr long long kPointExchangePoints = 1LL << 21;
 bool point_exchange_pays(const Geo& g) {
   const int mode = g_tile_override.load(std::memory_order_relaxed);
   if (mode == 3) return true;
-  if (mode == 1 || mode == 2) return false;
+  if (mode == 1 || mode == 2 || mode == 4) return false;
   return (long long)g.nx * g.ny * g.nz <= kPointExchangePoints;
 }
 

@@ -674,6 +674,11 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
                        float* un, const float* q, const float* ex, const float* ey,
                        const float* ez, const fd_source* src, hipStream_t s,
                        const RecPlane* rp) {
+  if (!(rp && rp->map) && forward_wide_tiles(g)) {
+    const float* const arr[4] = {up, u, un, q};
+    if (wide_forward_fits(g, arr, nullptr))
+      return launch_forward_wide(g, c, up, u, un, q, ex, ey, ez, src, nullptr, nullptr, s);
+  }
   Params p = base_params(g, c, ex, ey, ez);
   if (rp && rp->map) {
     p.rmap = rp->map;
@@ -703,6 +708,12 @@ hipError_t launch_step_exchange(const Geo& g, const Coef& c, const float* up, co
                                 const float* ez, const fd_source* src, const float* const rin[2],
                                 float* const sout[2], hipStream_t s) {
   if (!exchange_fits(g)) return hipErrorInvalidValue;
+  if (forward_wide_tiles(g)) {
+    const float* const arr[4] = {up, u, un, q};
+    const float* const fc[4] = {rin[0], rin[1], sout[0], sout[1]};
+    if (wide_forward_fits(g, arr, fc))
+      return launch_forward_wide(g, c, up, u, un, q, ex, ey, ez, src, rin, sout, s);
+  }
   Params p = base_params(g, c, ex, ey, ez);
   p.f = u;
   p.fq = u;

@@ -240,7 +240,7 @@ def test_step_launch_shape(L):
         assert launch(L, 512, 512, 512, tile_rows=16) == (256, 512)
     finally:
         assert L.fd_set_tiles(0) == 0
-    assert L.fd_set_tiles(4) == _lib.FD_EINVAL and L.fd_set_tiles(-1) == _lib.FD_EINVAL
+    assert L.fd_set_tiles(5) == _lib.FD_EINVAL and L.fd_set_tiles(-1) == _lib.FD_EINVAL
     assert L.fd_set_tiles(3) == 0  # one thread per point; the marching shape is 64 x 16
     try:
         assert launch(L, 512, 512, 512, tile_rows=16) == (256, 512)

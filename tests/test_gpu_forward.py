@@ -184,10 +184,13 @@ def test_degenerate_small_grids(shape):
     assert rel_l2(tr, tr_o) <= 1e-5
 
 
-@pytest.mark.parametrize("shape", [(128, 40, 45), (70, 33, 29), (192, 80, 64), (128, 64, 40)])
+@pytest.mark.parametrize("shape", [(128, 40, 45), (70, 33, 29), (192, 80, 64), (128, 64, 40),
+                                   (260, 36, 20), (256, 72, 30)])
 def test_results_independent_of_launch_shape(shape):
-    """The kernel shape (fd_set_tiles: 64 x 32 or 64 x 16 tiles, or one thread per
-    point, which the automatic choice takes for the fused form on these grids) and the
+    """The kernel shape (fd_set_tiles: 64 x 32 or 64 x 16 tiles, one thread per point,
+    which the automatic choice takes for the fused form on these grids, or 128 x 32 tiles
+    of 16-byte lanes where nx is a multiple of 4 -- ragged last x tiles of 64 and of 4
+    points, and with the x faces inside where nx is a multiple of 128) and the
     z chunk (planes per block, fd_set_kchunk) change the launch, never the bits:
     forward runs in the exchange and fused forms and both adjoint steps give the same
     traces, fields and gradient accumulators in every shape, for chunks that end
@@ -238,7 +241,7 @@ def test_results_independent_of_launch_shape(shape):
     api.set_tiles(0)
     ref = everything()
     try:
-        for tiles in (1, 2, 3):
+        for tiles in (1, 2, 3, 4):
             api.set_tiles(tiles)
             for kc in (0, 1, 2, 5, 9, 10, 17, nz):
                 api.set_kchunk(kc)
