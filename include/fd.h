@@ -129,26 +129,46 @@ int fd_set_kchunk(int32_t kchunk);
 
 /* Performance knob: tile shape of the forward stencil kernels (fd_step,
  * fd_step_fused, fd_step_exchange, fd_forward_run, fd_adjoint_step_scaled):
- * 0 = automatic (64 x 16 points for grids of at most 2^20 interior points,
- * 64 x 32 above; and a forward update that takes no faces inside the kernel --
+ * 0 = automatic: a forward update that takes no faces inside the kernel --
  * fd_step, fd_step_fused, fd_forward_run without a second face set,
- * fd_adjoint_step_scaled(_res) -- runs one
- * thread per point on grids of at most 2^22 points, which stay in cache and whose
- * step is latency-bound, and so does fd_step_exchange / fd_forward_run with all
- * twelve face buffers on grids of at most 2^21 points, the faces then read and
- * written in that one launch), 1 = always 64 x 32, 2 = always 64 x 16 (both: never
- * one thread per point), 3 = one thread per point wherever it applies (64 x 16
- * elsewhere).  Process-wide; results do not depend on it.  FD_EINVAL for another
- * mode. */
+ * fd_adjoint_step_scaled(_res) -- runs one thread per point on grids of at most
+ * 2^22 points, which stay in cache and whose step is latency-bound, and so does
+ * fd_step_exchange / fd_forward_run with all twelve face buffers on grids of at
+ * most 2^21 points, the faces then read and written in that one launch; grids of
+ * at least 7.5 million points take the kernel of 16-byte lanes and 128 x 32 tiles
+ * (the exchange form where nx is a multiple of 128; not where the receiver row is
+ * taken in the stencil launch; arrays and face buffers 16-byte aligned); the others
+ * the z-marching kernel of one float per lane, 64 x 16 tiles for grids of at most
+ * 2^20 points, 64 x 32 above.  1 = always 64 x 32, 2 = always 64 x 16 (both: never
+ * one thread per point nor 16-byte lanes), 3 = one thread per point wherever it
+ * applies (64 x 16 elsewhere), 4 = 16-byte lanes wherever they apply (64 x 32
+ * elsewhere).  Process-wide; results do not depend on it (fd_step_kernel reports the
+ * choice).  FD_EINVAL for another mode. */
 int fd_set_tiles(int32_t mode);
 
-/* Launch shape of the z-marching forward stencil kernel (fd_step_exchange,
- * and fd_step / fd_step_fused on grids that do not take the one-thread-per-point
- * kernel, see fd_set_tiles) over g, as the next such call would use it: out[0..3] =
- * x tiles, y tiles, z planes per block, z chunks (blocks = their product; a
- * tile is 64 x 32 points, or 64 x 16, see fd_set_tiles).  Host only, no device
- * call; FD_EINVAL for a bad grid or NULL out. */
+/* Launch shape of the z-marching forward stencil kernel of one float per lane
+ * (where a step over g takes it, see fd_set_tiles and fd_step_kernel) as the next
+ * such call would use it: out[0..3] = x tiles, y tiles, z planes per block, z
+ * chunks (blocks = their product; a tile is 64 x 32 points, or 64 x 16, see
+ * fd_set_tiles).  Host only, no device call; FD_EINVAL for a bad grid or NULL out. */
 int fd_step_launch(const fd_grid* g, int32_t out[4]);
+
+/* Which forward kernel a step over g takes, as the next call would choose it
+ * (process-wide fd_set_tiles mode included; volume arrays and face buffers
+ * assumed 16-byte aligned, as torch allocates them): with_faces != 0 for
+ * fd_step_exchange / fd_forward_run with all twelve face buffers, 0 for fd_step /
+ * fd_step_fused / fd_forward_run without faces (no receiver row in the kernel).
+ * out[0] = FD_KERNEL_*, out[1], out[2] = tile width and height in points (1 x 1:
+ * one thread per point), out[3] = z planes per block, out[4] = z chunks, out[5] =
+ * blocks (-1 for the one-thread-per-point kernel).  Host only; FD_EINVAL for a bad
+ * grid or NULL out. */
+enum {
+  FD_KERNEL_POINT = 0,        /* one thread per point (small grids, in cache)   */
+  FD_KERNEL_MARCH_64x32 = 1,  /* z-marching, one float per lane, 64 x 32 tiles  */
+  FD_KERNEL_MARCH_64x16 = 2,  /* the same with 64 x 16 tiles                    */
+  FD_KERNEL_WIDE = 3          /* z-marching, 16-byte lanes, 128 x 32 tiles      */
+};
+int fd_step_kernel(const fd_grid* g, int32_t with_faces, int32_t out[6]);
 
 /* ----------------------------------------------------------- model prep
  * (set-up, step S0; not on the per-step path).  The paper names the acoustic

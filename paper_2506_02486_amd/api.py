@@ -374,6 +374,19 @@ def step_launch(grid: Grid) -> dict:
     return {"tiles_x": tx, "tiles_y": ty, "kchunk": kc, "zchunks": zc, "blocks": tx * ty * zc}
 
 
+KERNEL_NAMES = {0: "point", 1: "march_64x32", 2: "march_64x16", 3: "wide_128x32"}
+
+
+def step_kernel(grid: Grid, faces: bool = False) -> dict:
+    """The forward kernel a step over ``grid`` takes (fd_step_kernel): ``faces`` for the
+    exchange step with all twelve face buffers, else the update without faces."""
+    out = (C.c_int32 * 6)()
+    check(lib().fd_step_kernel(grid.ref, int(bool(faces)), out), "fd_step_kernel")
+    kind, tx, ty, kc, zc, nb = out
+    return {"kernel": KERNEL_NAMES[kind], "tile": (tx, ty), "kchunk": kc, "zchunks": zc,
+            "blocks": nb}
+
+
 # ----------------------------------------------------------------- forward model
 
 class ReceiverPlane:

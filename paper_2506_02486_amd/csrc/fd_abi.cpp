@@ -204,6 +204,51 @@ int fd_step_launch(const fd_grid* g, int32_t out[4]) {
   return FD_OK;
 }
 
+int fd_step_kernel(const fd_grid* g, int32_t with_faces, int32_t out[6]) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!out) return fail(FD_EINVAL, "fd_step_kernel: out is NULL");
+  const Geo geo = make_geo(g);
+  int kind, o[4] = {0, 0, 0, 0}, tx = 1, ty = 1;
+  // the same choices as fd_step_exchange (all twelve faces) and fd_step_fused, with
+  // arrays and face buffers 16-byte aligned
+  const bool wide_ok = geo.sy % 4 == 0 && geo.sz % 4 == 0 && geo.org % 4 == 0;
+  // with faces: the x faces go inside the marching kernels where nx is a multiple of
+  // 64 (of 128 for 16-byte lanes); otherwise unpack, the update without faces, pack
+  const bool x_inside = with_faces && exchange_fits(geo);
+  const bool point = with_faces && point_exchange_pays(geo) ? true
+                     : x_inside                             ? false
+                                                            : point_kernel_pays(geo);
+  const bool wide_fits = wide_ok && (!x_inside || (geo.nx % 128 == 0 &&
+                                                   (long long)geo.ny * geo.nz * 16 < (1LL << 32)));
+  if (point) {
+    kind = FD_KERNEL_POINT;
+  } else if (forward_wide_tiles(geo) && wide_fits) {
+    kind = FD_KERNEL_WIDE;
+    wide_forward_shape(geo, o);
+    tx = 128;
+    ty = 32;
+  } else {
+    const bool small = forward_small_tiles(geo);
+    kind = small ? FD_KERNEL_MARCH_64x16 : FD_KERNEL_MARCH_64x32;
+    forward_launch_shape(geo, o);
+    tx = 64;
+    ty = small ? 16 : 32;
+  }
+  out[0] = kind;
+  out[1] = tx;
+  out[2] = ty;
+  if (kind == FD_KERNEL_POINT) {
+    out[3] = out[4] = 1;
+    out[5] = -1;
+  } else {
+    out[3] = o[2];  // planes per block
+    out[4] = o[3];  // z chunks
+    out[5] = o[0] * o[1] * o[3];
+  }
+  return FD_OK;
+}
+
 int fd_cfl_dt(const fd_grid* g, const float* v, double courant, int32_t* scratch_dev,
               double* vmax_host, double* dt_out, void* stream) {
   int rc = check_grid(g);

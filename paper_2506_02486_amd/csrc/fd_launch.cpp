@@ -102,9 +102,11 @@ bool forward_small_tiles(const Geo& g) {
 
 void set_tile_override(int mode) { g_tile_override.store(mode, std::memory_order_relaxed); }
 
-// Above this size a grid's arrays stream from HBM every step and the 16-byte-lane
-// kernel's wider, deeper loads pay.
-constexpr long long kWideGridPoints = 1LL << 24;
+// From about this size on the 16-byte-lane kernel's wider loads, more of them in
+// flight, pay (native loop, sponge 16, us per step, 64 x 32 marching kernel / one
+// thread per point / 16-byte lanes: 192^3 29.6 / 29.5 / 32.4, 200^3 40.7 / 41.9 /
+// 35.5, 256^3 56.4 / 89.1 / 49.8, 384^3 179.0 / 310.3 / 167.2).
+constexpr long long kWideGridPoints = 7500000;
 
 bool forward_wide_tiles(const Geo& g) {
   const int mode = g_tile_override.load(std::memory_order_relaxed);

@@ -2,7 +2,7 @@
 //
 // The same leapfrog update as the z-marching forward kernel of fd_stencil.hip
 // (same arithmetic, in the same order, so the same bits), for bandwidth-bound
-// grids whose rows are a multiple of 4 floats.  What differs is how a block
+// grids.  What differs is how a block
 // streams HBM: each lane owns 4 consecutive x points (16-byte loads and
 // stores), a row of 32 lanes covers 128 x points (512 bytes), and each thread
 // owns 2 consecutive y rows, so a thread has 6 independent 16-byte loads in
@@ -108,15 +108,24 @@ __global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
     return 4u * (unsigned)((yy + 4) * sy + (xx + 4));
   };
 
-  // ---- the thread's own rows (nx is a multiple of 4: a float4 is all interior,
-  // all halo or all outside)
+  // Rows need not be a multiple of 4 floats: the float4 that holds the last
+  // interior points of a row may also hold +x halo cells, and the one after it the
+  // rest of the halo and up to 3 cells past it (in the row's padding, or the next
+  // row's).  Loads whose float4 would hold nothing needed are clamped to the last
+  // float4 that holds a needed cell: in a y-halo row (whose +x halo cells are
+  // corners, never used) the one that ends at or before the halo's end, so that the
+  // last row of the last plane is never read past the array.
+  const int xcl_in = (nx + 3) & ~3;  // interior rows: the float4 holding cell nx + 3
+  const int xcl_halo = nx & ~3;      // y-halo rows
+  auto xcl = [&](int yy) { return yy < ny ? xcl_in : xcl_halo; };
+  // ---- the thread's own rows
   unsigned cb[RY];
-  bool cld[RY], act[RY];
+  bool act[RY], full[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     cb[r] = boff(x, yr + r);
-    cld[r] = (x < nx + 4) && (yr + r < ny + 4);
-    act[r] = (x < nx) && (yr + r < ny);
+    act[r] = (x < nx) && (yr + r < ny);  // some point of the float4 is stored
+    full[r] = (x + 4 <= nx) && (yr + r < ny);
   }
   // ---- the halo float4 this thread loads per plane.  Waves 0-3 (thread rows 0-7)
   // load the y halo (row tr of the 8: 4 above the tile, 4 below), wave 4 (thread
@@ -141,7 +150,7 @@ __global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
   }
   // a halo cell past the grid's halo is only read by points that are not stored:
   // load a clamped one instead
-  const unsigned h_off = boff(min(h_x, nx), min(h_y, ny + 3));
+  const unsigned h_off = boff(min(h_x, xcl(min(h_y, ny + 3))), min(h_y, ny + 3));
 
   const bool src_tile = p.si >= x0 && p.si < x0 + TX && p.sj >= y0 && p.sj < y0 + TY &&
                         p.sk >= kb && p.sk < ke;
@@ -183,8 +192,9 @@ __global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
   unsigned cbz[RY], cbp[RY];  // clamped: field (interior + halo), pointwise (interior)
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    cbz[r] = boff(min(x, nx), min(yr + r, ny + 3));
-    cbp[r] = boff(min(x, nx - 4), min(yr + r, ny - 1));
+    const int yz = min(yr + r, ny + 3);
+    cbz[r] = boff(min(x, xcl(yz)), yz);
+    cbp[r] = boff(min(x, (nx - 1) & ~3), min(yr + r, ny - 1));
   }
   auto zload = [&](int k, int r) -> f4 {
     return ld4(F0 + (long long)min(k, nz + 3) * szb, cbz[r]);
@@ -223,16 +233,16 @@ __global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
   for (int r = 0; r < RY; ++r) eyr[r] = 0.f;
   bool tile_sponge = false;
   if (SPONGE) {
-    if (x < nx) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) exc[e] = p.ex[x + e];
-    }
+    for (int e = 0; e < 4; ++e)
+      if (x + e < nx) exc[e] = p.ex[x + e];
     int any = 0;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       if (yr + r < ny) eyr[r] = p.ey[yr + r];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) any |= act[r] && (exc[e] != 0.f || eyr[r] != 0.f);
+      for (int e = 0; e < 4; ++e)
+        any |= (x + e < nx) && (yr + r < ny) && (exc[e] != 0.f || eyr[r] != 0.f);
     }
     tile_sponge = __syncthreads_or(any) != 0;
   }
@@ -315,10 +325,15 @@ __global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
         }
         v4[e] = v;
       }
-      if (act[r]) {
+      if (full[r]) {
         __builtin_nontemporal_store(v4, reinterpret_cast<f4*>(ok + cb[r]));
         if (XCH && sx_ptr)
           *reinterpret_cast<f4*>(sx_ptr + ((size_t)k * (size_t)ny + (size_t)(yr + r)) * 4) = v4;
+      } else if (act[r]) {  // the row's last points: x < nx < x + 4
+        float* d = reinterpret_cast<float*>(ok + cb[r]);
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          if (x + e < nx) __builtin_nontemporal_store(v4[e], d + e);
       }
     }
   };
@@ -365,11 +380,14 @@ bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
 }  // namespace
 
 bool wide_forward_fits(const Geo& g, const float* const arrays[4], const float* const faces[4]) {
-  if (g.nx % 4 || g.sy % 4 || g.sz % 4 || g.org % 4) return false;
+  // (a row's last float4 may end up to 3 cells past its +x halo: in the next row,
+  // which exists, since y-halo rows clamp theirs to end within the halo)
+  if (g.sy % 4 || g.sz % 4 || g.org % 4) return false;
   for (int i = 0; i < 4; ++i)
     if (!arrays[i] || !aligned16(arrays[i])) return false;
   if (faces) {
-    // a receive buffer cell is addressed by a 32-bit byte offset
+    // x faces are one float4 per row; a receive buffer cell is addressed by a
+    // 32-bit byte offset
     if (g.nx % TX || (long long)g.ny * g.nz * 16 >= (1LL << 32)) return false;
     for (int i = 0; i < 4; ++i)
       if (!faces[i] || !aligned16(faces[i])) return false;

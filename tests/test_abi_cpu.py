@@ -246,6 +246,25 @@ def test_step_launch_shape(L):
         assert launch(L, 512, 512, 512, tile_rows=16) == (256, 512)
     finally:
         assert L.fd_set_tiles(0) == 0
+    # which forward kernel a step takes (host only)
+    out = (C.c_int32 * 6)()
+    g = _lib.fd_grid()
+    for shape, faces, want in (((64, 64, 64), 0, 0), ((64, 64, 64), 1, 0), ((512, 512, 512), 1, 3),
+                               ((512, 512, 512), 0, 3), ((320, 320, 320), 1, 1),
+                               ((320, 320, 320), 0, 3), ((192, 192, 192), 0, 1),
+                               ((1024, 1024, 512), 1, 3)):
+        assert L.fd_grid_init(C.byref(g), *shape, 10.0, 10.0, 10.0) == 0
+        assert L.fd_step_kernel(C.byref(g), faces, out) == 0
+        assert out[0] == want, (shape, faces, list(out))
+        if want == 3:
+            assert (out[1], out[2]) == (128, 32) and out[5] == 256 or shape == (320, 320, 320)
+    assert L.fd_set_tiles(4) == 0
+    try:
+        assert L.fd_grid_init(C.byref(g), 64, 64, 64, 10.0, 10.0, 10.0) == 0
+        assert L.fd_step_kernel(C.byref(g), 0, out) == 0 and out[0] == 3
+    finally:
+        assert L.fd_set_tiles(0) == 0
+    assert L.fd_step_kernel(C.byref(g), 0, None) == _lib.FD_EINVAL
     for n in (102, 128, 192, 320, 384, 448):
         kc, blocks = launch(L, n, n, n)
         assert 400 <= blocks <= 512, (n, kc, blocks)

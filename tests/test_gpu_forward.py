@@ -143,16 +143,20 @@ def test_ragged_sponge_loopback_parity(shape):
     assert sim.n == 76
 
 
-@pytest.mark.parametrize("shape", [(256, 136, 72), (512, 512, 512)])
-def test_marching_exchange_kernel_100_steps_vs_oracle(shape):
+@pytest.mark.parametrize("shape,kernel", [((256, 136, 72), "march_64x32"),
+                                          ((260, 200, 150), "wide_128x32"),
+                                          ((512, 512, 512), "wide_128x32")])
+def test_marching_exchange_kernel_100_steps_vs_oracle(shape, kernel):
     """The benchmark's step path over 100 steps: fd_step_exchange with both face sets
     (loopback, periodic), sponge 16, Ricker source, centre x-line receivers, against the
-    FP64 oracle's periodic forward run.  Both shapes have nx a multiple of 64 and more
-    than 2^21 points, so every step runs the z-marching kernel with the x faces inside
-    (not the one-thread-per-point kernel); 256 x 136 x 72 adds a ragged last tile row
-    (136 = 4 x 32 + 8) and several z chunks, 512^3 is the benchmark's own grid."""
+    FP64 oracle's periodic forward run, for each z-marching kernel the automatic choice
+    takes: 256 x 136 x 72 the kernel of one float per lane with the x faces inside (a
+    ragged last tile row, 136 = 4 x 32 + 8, and several z chunks); 260 x 200 x 150 the
+    kernel of 16-byte lanes without faces inside (ragged x and y tiles, rows whose last
+    float4 holds one interior point); 512^3, the benchmark's own grid, the 16-byte-lane
+    kernel with the x faces inside."""
     nx, ny, nz = shape
-    assert nx % 64 == 0 and nx * ny * nz > (1 << 21)
+    assert api.step_kernel(api.Grid(nx, ny, nz), faces=True)["kernel"] == kernel
     nt, width = 100, 16
     v = smooth_velocity(nx, ny, nz, seed=2)
     src = center_source(nx, ny, nz)
@@ -185,16 +189,17 @@ def test_degenerate_small_grids(shape):
 
 
 @pytest.mark.parametrize("shape", [(128, 40, 45), (70, 33, 29), (192, 80, 64), (128, 64, 40),
-                                   (260, 36, 20), (256, 72, 30)])
+                                   (260, 36, 20), (256, 72, 30), (133, 21, 17), (135, 37, 12)])
 def test_results_independent_of_launch_shape(shape):
     """The kernel shape (fd_set_tiles: 64 x 32 or 64 x 16 tiles, one thread per point,
     which the automatic choice takes for the fused form on these grids, or 128 x 32 tiles
-    of 16-byte lanes where nx is a multiple of 4 -- ragged last x tiles of 64 and of 4
-    points, and with the x faces inside where nx is a multiple of 128) and the
-    z chunk (planes per block, fd_set_kchunk) change the launch, never the bits:
-    forward runs in the exchange and fused forms and both adjoint steps give the same
-    traces, fields and gradient accumulators in every shape, for chunks that end
-    inside, at and past the 9-plane unrolled loop, one plane and the whole depth."""
+    of 16-byte lanes -- ragged last x tiles of 64 and of 4 points, rows whose last float4
+    holds 1, 2 or 3 interior points, and with the x faces inside where nx is a multiple
+    of 128) and the z chunk (planes per block, fd_set_kchunk) change the launch, never
+    the bits: forward runs in the exchange and fused forms and both adjoint steps give
+    the same traces, fields and gradient accumulators in every shape, for chunks that end
+    inside, at and past the 9- and 10-plane unrolled loops, one plane and the whole
+    depth."""
     nx, ny, nz = shape
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
     geom = api.Geometry(src=(nx // 3, ny // 2, nz // 2), rec=receivers_xline(nx, ny // 3, nz // 3))
