@@ -7,16 +7,22 @@ centre, receivers on the centre x-line, the six faces packed and unpacked into
 contiguous buffers every step (loopback exchange) -- after W untimed warm-up steps,
 and prints one JSON line.
 
-A step is one pass of the per-step path: one fd_step_exchange -- the face halos of
-u^n read from the receive buffers (the loopback of the faces the previous step
-packed), the leapfrog update with the source term, and the six faces of u^{n+1}
-packed into the other face set, all in one kernel -- then record_receivers and the
-pointer rotation.  ``value`` is interior points x steps / wall time in Gpts/s with
-every array resident in HBM.  ``roofline`` rates that kernel by its algorithmic
-bytes (16 B per interior point: u^n, u^{n-1} and vdt2 read once, u^{n+1} written
-once; plus 4 B per face point read and 4 B per face point written) over its average
-launch time from HIP events on its own stream.  ``cpu_baseline`` times the FP64 CPU
-oracle on a bounded sample of the same workload.
+A step is one pass of the per-step path, the launches of fd_step_exchange: the y and
+z face halos of u^n unpacked from the receive buffers (the loopback of the faces the
+previous step packed); the stencil kernel, which reads the x face halos from their
+receive buffers, applies the leapfrog update with the source term and writes the x
+faces of u^{n+1} to the other face set; the y and z faces of u^{n+1} packed, with the
+receiver row in the same launch; then the pointer rotation.  ``value`` is interior
+points x steps / wall time in Gpts/s with every array resident in HBM.  ``roofline``
+rates the stencil kernel by its algorithmic bytes (16 B per interior point: u^n,
+u^{n-1} and vdt2 read once, u^{n+1} written once; plus 4 B per x-face point read and
+4 B written) over its average launch time from HIP events on its own stream.
+``cpu_baseline`` times the FP64 CPU oracle on a bounded sample of the same workload.
+
+Further legs in the same line (each skippable): ``serving`` (the continuous-batching
+shot server against the plain per-shot loop), ``small`` (64^3 parity configuration),
+``large`` (1024 x 1024 x 512, with its own roofline and CPU baseline), ``fwi`` (the
+256^3 FWI gradient, with its roofline against the gradient's algorithmic bytes).
 """
 from __future__ import annotations
 
@@ -33,7 +39,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
 METRIC = "Gpts/s + % HBM roofline; shots/s and p50/p99 latency vs plain per-shot loop"
-STENCIL_SRC = os.path.join(ROOT, "paper_2506_02486_amd", "csrc", "fd_stencil.hip")
+CSRC = os.path.join(ROOT, "paper_2506_02486_amd", "csrc")
+# source file of each forward kernel (the counter summary is valid for one version)
+KERNEL_SRC = {"wide_128x32": "fd_stencil4.hip", "march_64x32": "fd_stencil.hip",
+              "march_64x16": "fd_stencil.hip", "point": "fd_point.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fd_step_512_traffic.txt")
 
 
@@ -41,25 +50,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def stencil_hash() -> str:
-    """sha256[:16] of the stencil source's code, comments removed and whitespace
-    runs collapsed: an edit of comments keeps the counter summary valid, any change
-    of code voids it."""
-    src = open(STENCIL_SRC).read()
+def stencil_hash(kernel: str = "wide_128x32") -> str:
+    """sha256[:16] of the kernel's source code, comments removed and whitespace runs
+    collapsed: an edit of comments keeps the counter summary valid, any change of code
+    voids it."""
+    src = open(os.path.join(CSRC, KERNEL_SRC[kernel])).read()
     src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
     src = re.sub(r"//[^\n]*", " ", src)
     return hashlib.sha256(" ".join(src.split()).encode()).hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per fd_step launch from the committed counter summary, if it was
-    taken on the current stencil source; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(path: str, kernel: str):
+    """HBM bytes per stencil launch from a committed counter summary, if it was taken
+    on the current source of that kernel; else None."""
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m_h = re.search(r"stencil_source_sha256_16:\s*([0-9a-f]+)", txt)
     m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_h or not m_b or m_h.group(1) != stencil_hash():
+    if not m_h or not m_b or m_h.group(1) != stencil_hash(kernel):
         return None
     return float(m_b.group(1))
 
@@ -368,9 +377,13 @@ def small_exchange_bench(n=64, steps=200, repeats=5):
             "us_per_step": round(el * 1e6 / steps, 2)}
 
 
-def large_bench(steps=500, warmup=5):
-    """1024 x 1024 x 512 subdomain, sponge 16, Dirichlet halo, receivers on a 1024-point
-    line at z = 4: the same per-step path without the exchange."""
+def large_bench(steps=500, warmup=5, every=8, cpu=True, cpu_steps=10, vcache=None):
+    """1024 x 1024 x 512 subdomain (the large single-GPU configuration), smooth model
+    (seed 2), sponge 16, Dirichlet halo, Ricker at the centre, receivers on the
+    1024-point line y = 512, z = 4: the per-step path without the exchange (the fused
+    update with the source, then the receiver row), `steps` steps after `warmup`.
+    The stencil is bracketed with HIP events on every `every`-th step for its roofline
+    line; `cpu` also times the FP64 oracle on `cpu_steps` steps of the same grid."""
     import numpy as np
     import torch
 
@@ -378,52 +391,107 @@ def large_bench(steps=500, warmup=5):
     from workloads import center_source, receivers_xline, smooth_velocity
 
     nx, ny, nz = 1024, 1024, 512
-    log("large: generating the 1024x1024x512 model")
-    v = smooth_velocity(nx, ny, nz, seed=2)
+    if vcache and os.path.exists(vcache):
+        v = np.load(vcache)
+    else:
+        log("large: generating the 1024x1024x512 model")
+        v = smooth_velocity(nx, ny, nz, seed=2)
+        if vcache:
+            np.save(vcache, v)
     src = center_source(nx, ny, nz)
-    sim = api.Simulation(v, sponge_width=16,
-                         geom=api.Geometry(src=src, rec=receivers_xline(nx, 512, 4)))
-    del v
+    rec = receivers_xline(nx, 512, 4)
+    sim = api.Simulation(v, sponge_width=16, geom=api.Geometry(src=src, rec=rec))
     sim.run(warmup)
     g = sim.grid
+    kern = api.step_kernel(g, faces=False)
     w = api.ricker(steps, sim.dt, n0=sim.n)
     tr = torch.zeros((steps, sim.nrec), dtype=torch.float32, device="cuda")
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
+    ev = {s: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for s in range(0, steps, max(1, every))}
+    log(f"large: timing {steps} steps ({kern['kernel']} kernel)")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
-        ev[s][0].record()
+        if s in ev:
+            ev[s][0].record()
         api.step_fused(g, sim.u_prev, sim.u, sim.u_next, sim.vdt2, sim.sponge,
                        (src, float(w[s])), None)
-        ev[s][1].record()
+        if s in ev:
+            ev[s][1].record()
         api.record_receivers(g, sim.u_next, sim.rec_off, tr[s])
         sim.u_prev, sim.u, sim.u_next = sim.u, sim.u_next, sim.u_prev
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev.values()]))
     pts = nx * ny * nz
-    out = {"workload": "1024x1024x512 + radius-4 halo, smooth model, sponge 16, Dirichlet, "
-                       "1024 receivers at z=4", "steps": steps,
-           "Gpts_per_s": round(pts * steps / el / 1e9, 2),
-           "ms_per_step": round(el * 1e3 / steps, 4),
-           "stencil_ms": round(k_ms, 4),
-           "stencil_frac_of_8TBps": round(16.0 * pts / (k_ms / 1e3) / 8e12, 4)}
+    algo = 16.0 * pts  # u^n, u^{n-1}, vdt2 read once, u^{n+1} written once
+    achieved = algo / (k_ms / 1e3) / 1e9
+    finite = bool(torch.isfinite(g.interior(sim.u)).all().item())
+    dt = sim.dt
     del sim, tr
     torch.cuda.empty_cache()
+    traffic = read_traffic(os.path.join(ROOT, "profiles", "fd_step_large_traffic.txt"),
+                           kern["kernel"])
+    out = {"workload": "1024x1024x512 + radius-4 halo, smooth model (seed 2), sponge 16, "
+                       "Dirichlet halo, Ricker 15 Hz at the centre, 1024 receivers at y=512, z=4",
+           "steps": steps, "warmup": warmup,
+           "value": round(pts * steps / el / 1e9, 3), "unit": "Gpts/s",
+           "ms_per_step": round(el * 1e3 / steps, 4), "finite": finite,
+           "roofline": {"bound": "hbm",
+                        "kernel": f"{kern['kernel']} forward update with the source term "
+                                  f"({kern['tile'][0]} x {kern['tile'][1]} tiles, "
+                                  f"{kern['kchunk']} planes per block, {kern['blocks']} blocks)",
+                        "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                        "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                        "traffic": (round(traffic) if traffic is not None else None),
+                        "algorithmic_bytes_per_launch": algo,
+                        "avg_launch_ms": round(k_ms, 5)}}
+    if cpu:
+        log(f"large: CPU oracle baseline ({cpu_steps} steps after 1)")
+        out["cpu_baseline"] = cpu_baseline_dirichlet(v, dt, src, cpu_steps)
+    del v
     return out
+
+
+def cpu_baseline_dirichlet(v, dt, src, steps):
+    """FP64 oracle on a Dirichlet, sponge-16 grid: (time of 1+steps) - (time of 1)."""
+    import oracle
+
+    nz, ny, nx = v.shape
+    q = oracle.vdt2(v, dt)
+    eta = oracle.sponge_tables(nx, ny, nz, 16, float(v.max()), (10.0,) * 3, dt)
+    w = oracle.ricker(steps + 1, dt)
+    t0 = time.perf_counter()
+    oracle.forward(None, 1, dt, src=src, w=w[:1], eta=eta, q=q)
+    t1 = time.perf_counter()
+    oracle.forward(None, steps + 1, dt, src=src, w=w, eta=eta, q=q)
+    t2 = time.perf_counter()
+    per_step = ((t2 - t1) - (t1 - t0)) / steps
+    del q
+    pts = nx * ny * nz
+    return {"value": round(pts / per_step / 1e9, 5), "unit": "Gpts/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, the same {nx}x{ny}x{nz} sponge-16 Dirichlet grid and "
+                      f"source, {steps} steps (time of {steps + 1} steps minus 1 step, set-up "
+                      f"excluded); {per_step:.3f} s/step",
+            "host_cpu": host_cpu(), "host_nproc": os.cpu_count()}
 
 
 def fwi_bench(n=256, nt=1000, every=32):
     """FWI gradient w.r.t. squared slowness: n^3, nt steps, checkpoints every `every`
-    steps, observed data from a +5% Gaussian blob."""
+    steps (0: every state kept), sponge 16, source (n/2, n/2, 20), receivers on the
+    plane z = 20, observed data from a +5% Gaussian blob at the centre.  Roofline: the
+    algorithmic bytes of one gradient -- per point and step 16 B forward, 16 B
+    recomputed forward (none when every state is kept) and 28 B for the adjoint step
+    with the gradient fused (a^{n+1}, vdt2, a^{n+2}, u^n, g read, a^n and g written)
+    -- over the time of one gradient against 8 TB/s."""
     import numpy as np
     import torch
 
     from paper_2506_02486_amd import fwi
     from workloads import blob_perturbed, receivers_plane, smooth_velocity
 
-    log(f"fwi: {n}^3, {nt} steps")
+    log(f"fwi: {n}^3, {nt} steps, checkpoints every {every}")
     v0 = smooth_velocity(n, n, n, seed=2)
     vt = blob_perturbed(v0)
     dt = 0.4 * 10.0 / float(v0.max())
@@ -439,13 +507,19 @@ def fwi_bench(n=256, nt=1000, every=32):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     pts = n ** 3
-    # forward 16 B/pt/step, recompute 16 (none when every state is kept), adjoint 16 +
-    # gradient 16
-    algo = (16.0 + (16.0 if every else 0.0) + 32.0) * pts * nt
+    algo = (16.0 + (16.0 if every else 0.0) + 28.0) * pts * nt
     what = f"checkpoints every {every}" if every else "every state kept in HBM"
-    out = {"workload": f"FWI gradient {n}^3, {nt} steps, {what}, sponge 16",
-           "seconds_per_gradient": round(el, 4), "misfit": J,
-           "effective_GBps": round(algo / el / 1e9, 1),
+    achieved = algo / el / 1e9
+    out = {"workload": f"FWI gradient {n}^3, {nt} steps, {what}, sponge 16, source "
+                       f"({n // 2},{n // 2},20), receivers on the plane z=20, observed data "
+                       f"from a +5% Gaussian blob",
+           "value": round(el, 4), "unit": "s per gradient", "misfit": J,
+           "roofline": {"bound": "hbm", "kernel": "whole gradient (forward, recompute, "
+                                                  "adjoint and gradient kernels)",
+                        "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                        "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                        "algorithmic_bytes": algo,
+                        "roofline_seconds": round(algo / (PEAK_HBM_GBPS * 1e9), 4)},
            "finite": bool(torch.isfinite(g).all().item())}
     del prob, g, m0, mt, obs
     torch.cuda.empty_cache()
@@ -466,8 +540,11 @@ def main():
     ap.add_argument("--event-every", type=int, default=8,
                     help="bracket the stencil with HIP events on every N-th timed step")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--large", action="store_true", help="also time the 1024x1024x512 subdomain")
-    ap.add_argument("--fwi", action="store_true", help="also time the 256^3 FWI gradient")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1024x1024x512 leg")
+    ap.add_argument("--large-steps", type=int, default=500)
+    ap.add_argument("--vcache-large", default=None,
+                    help="optional .npy path to cache the 1024x1024x512 velocity model")
+    ap.add_argument("--no-fwi", action="store_true", help="skip the 256^3 FWI gradient legs")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^3 small-grid leg")
     ap.add_argument("--shots", type=int, default=256, help="shots in the serving stream")
     ap.add_argument("--vcache", default=None,
@@ -502,8 +579,10 @@ def main():
     if args.kchunk:
         api.set_kchunk(args.kchunk)
     g = sim.grid
+    kern = api.step_kernel(g, faces=True)
     K, W = args.steps, args.warmup
-    log(f"bench: dt={sim.dt:.6e} s, vmax={sim.vmax:.1f}; warm-up {W} steps")
+    log(f"bench: dt={sim.dt:.6e} s, vmax={sim.vmax:.1f}; {kern['kernel']} kernel; "
+        f"warm-up {W} steps")
     sim.run(W)
     torch.cuda.synchronize()
 
@@ -575,7 +654,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    traffic = read_traffic()
+    traffic = read_traffic(TRAFFIC_FILE, kern["kernel"])
     out = {
         "metric": METRIC,
         "value": round(gpts, 3),
@@ -601,9 +680,10 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "stencil of fd_step_exchange: stencil_kernel<64,8,4,FWD,sponge,source,"
-                      "early-halo,x-exchange> (update + source, x faces received and sent "
-                      "in the same kernel)",
+            "kernel": f"stencil of fd_step_exchange: {kern['kernel']} kernel "
+                      f"({kern['tile'][0]} x {kern['tile'][1]} tiles, {kern['kchunk']} planes "
+                      f"per block, {kern['blocks']} blocks; update + source, x faces received "
+                      f"and sent in the same kernel)",
             "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
@@ -637,9 +717,10 @@ def main():
     if not args.no_small:
         out["small"] = small_bench()
         out["small_exchange"] = small_exchange_bench()
-    if args.large:
-        out["large"] = large_bench()
-    if args.fwi:
+    if not args.no_large:
+        out["large"] = large_bench(steps=args.large_steps, cpu=not args.no_cpu_baseline,
+                                   vcache=args.vcache_large)
+    if not args.no_fwi:
         out["fwi"] = fwi_bench()
         # the same gradient keeping all 1000 states in HBM (89 GB): no recompute
         out["fwi_all_states"] = fwi_bench(every=0)
