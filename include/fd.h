@@ -184,6 +184,21 @@ int fd_step_kernel(const fd_grid* g, int32_t with_faces, int32_t out[6]);
 int fd_cfl_dt(const fd_grid* g, const float* v, double courant, int32_t* scratch_dev,
               double* vmax_host, double* dt_out, void* stream);
 
+/* fd_cfl_dt without the caller's workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation): the two result slots live in the library's own static
+ * device array (256 bytes per device, 64 int32 of which this call uses 2; no grid
+ * size needs more, so none is refused for lack of room), which each device that
+ * runs the library holds until the process ends.  No device or host memory is
+ * allocated: the array's device address is looked up once per device, on the
+ * first call made with that device current.  The slots are reset by a kernel at
+ * every call.  All calls on one device share them: calls that overlap in time on
+ * one device (several host threads, several streams) race and must be
+ * serialised by the caller.  Same results, synchronisation and errors as
+ * fd_cfl_dt (FD_EDEVICE if the array cannot be looked up). */
+int fd_cfl_dt_static(const fd_grid* g, const float* v, double courant, double* vmax_host,
+                     double* dt_out, void* stream);
+
 /* vdt2 = (v*dt)^2, evaluated in FP64 and rounded to FP32, on every point of
  * the padded box [-4,n+4)^3 of vdt2: the interior from v's interior, each
  * face halo from the periodic image of the interior (i mod n), edges and

@@ -78,6 +78,7 @@ SIGNATURES = {
     "fd_step_kernel": (C.c_int, [_G, C.c_int32, C.POINTER(C.c_int32)]),
     "fd_set_tiles": (C.c_int, [_i32]),
     "fd_cfl_dt": (C.c_int, [_G, _P, _f64, _P, C.POINTER(_f64), C.POINTER(_f64), _P]),
+    "fd_cfl_dt_static": (C.c_int, [_G, _P, _f64, C.POINTER(_f64), C.POINTER(_f64), _P]),
     "fd_prepare_vdt2": (C.c_int, [_G, _P, _P, _f64, _P]),
     "fd_prepare_vdt2_m": (C.c_int, [_G, _P, _P, _f64, _P]),
     "fd_sponge_eta_max": (_f64, [_f64, _f64, _f64, _i32, _f64]),

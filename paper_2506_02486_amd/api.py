@@ -122,6 +122,17 @@ def cfl_dt(grid: Grid, v: torch.Tensor, courant: float = COURANT, stream=None):
     return dt.value, vmax.value
 
 
+def cfl_dt_static(grid: Grid, v: torch.Tensor, courant: float = COURANT, stream=None):
+    """cfl_dt through fd_cfl_dt_static: no workspace, nothing allocated (the library's
+    static result slots; calls overlapping on one device race)."""
+    grid.check(v, "v")
+    vmax = C.c_double()
+    dt = C.c_double()
+    check(lib().fd_cfl_dt_static(grid.ref, v.data_ptr(), courant, C.byref(vmax), C.byref(dt),
+                                 _stream(stream)), "fd_cfl_dt_static")
+    return dt.value, vmax.value
+
+
 def prepare_vdt2(grid: Grid, v: torch.Tensor, vdt2: torch.Tensor, dt: float, stream=None):
     grid.check(v, "v")
     grid.check(vdt2, "vdt2")

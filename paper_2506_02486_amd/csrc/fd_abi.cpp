@@ -249,12 +249,11 @@ int fd_step_kernel(const fd_grid* g, int32_t with_faces, int32_t out[6]) {
   return FD_OK;
 }
 
-int fd_cfl_dt(const fd_grid* g, const float* v, double courant, int32_t* scratch_dev,
-              double* vmax_host, double* dt_out, void* stream) {
-  int rc = check_grid(g);
-  if (rc) return rc;
-  if (!v || !scratch_dev) return fail(FD_EINVAL, "fd_cfl_dt: NULL array");
-  if (!finite_pos(courant)) return fail(FD_EINVAL, "fd_cfl_dt: courant must be > 0");
+namespace {
+// fd_cfl_dt with its result slots at scratch_dev (two int32 of device memory)
+int cfl_dt_with(const fd_grid* g, const float* v, double courant, int32_t* scratch_dev,
+                double* vmax_host, double* dt_out, void* stream) {
+  int rc = FD_OK;
   hipStream_t s = as_stream(stream);
   rc = check_hip(launch_vmax(make_geo(g), v, scratch_dev, s), "vmax launch");
   if (rc) return rc;
@@ -275,6 +274,28 @@ int fd_cfl_dt(const fd_grid* g, const float* v, double courant, int32_t* scratch
   if (vmax_host) *vmax_host = vmax;
   if (dt_out) *dt_out = courant * dmin / (double)vmax;
   return FD_OK;
+}
+}  // namespace
+
+int fd_cfl_dt(const fd_grid* g, const float* v, double courant, int32_t* scratch_dev,
+              double* vmax_host, double* dt_out, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!v || !scratch_dev) return fail(FD_EINVAL, "fd_cfl_dt: NULL array");
+  if (!finite_pos(courant)) return fail(FD_EINVAL, "fd_cfl_dt: courant must be > 0");
+  return cfl_dt_with(g, v, courant, scratch_dev, vmax_host, dt_out, stream);
+}
+
+int fd_cfl_dt_static(const fd_grid* g, const float* v, double courant, double* vmax_host,
+                     double* dt_out, void* stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!v) return fail(FD_EINVAL, "fd_cfl_dt_static: NULL array");
+  if (!finite_pos(courant)) return fail(FD_EINVAL, "fd_cfl_dt_static: courant must be > 0");
+  int32_t* slots = nullptr;  // the library's own static slots on the current device
+  rc = check_hip(cfl_scratch(&slots), "fd_cfl_dt_static: static scratch lookup");
+  if (rc) return rc;
+  return cfl_dt_with(g, v, courant, slots, vmax_host, dt_out, stream);
 }
 
 int fd_prepare_vdt2(const fd_grid* g, const float* v, float* vdt2, double dt, void* stream) {

@@ -2,6 +2,7 @@
 // source injection, receiver sampling, adjoint residual scatter, model prep
 // (vdt2 and max velocity) and the gradient's change of variable.
 #include <algorithm>
+#include <mutex>
 
 #include "fd_internal.h"
 
@@ -464,6 +465,34 @@ hipError_t launch_scatter_add_scaled(const Geo& g, float* a, const int64_t* off,
   hipLaunchKernelGGL(scatter_add_scaled_kernel, dim3((n + BS - 1) / BS), dim3(BS), 0, s, g, a,
                      off, vals, q, ex, ey, ez, n);
   return hipGetLastError();
+}
+
+// ---- allocation-free max(v): the result slots live in a file-scope device array.
+// Each device that runs the library holds its own copy until the process ends; its
+// address is looked up once per device (hipGetSymbolAddress, with that device
+// current) and only that address is handed to kernels and copies.  Every call on a
+// device shares its copy: calls that overlap in time on one device race.
+namespace {
+static __device__ __align__(256) int32_t scratch[kCflScratchInts];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t cfl_scratch(int32_t** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<int32_t*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace fd

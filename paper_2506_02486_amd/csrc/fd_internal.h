@@ -163,6 +163,11 @@ hipError_t launch_vmax_view(int nx, int ny, int nz, const float* v, long long vs
                             long long vsz, int32_t* out, hipStream_t s);
 // dst[i] = 0 for i < n
 hipError_t launch_zero(float* dst, long long n, hipStream_t s);
+// Device address of the calling thread's current device's copy of the library's
+// static max(v) result slots (kCflScratchInts int32, of which launch_vmax uses 2);
+// looked up once per device.
+constexpr int kCflScratchInts = 64;
+hipError_t cfl_scratch(int32_t** out);
 
 // The forward step with the x faces exchanged inside the stencil kernel: u's
 // x-face halos are read from rin[0] (-x) and rin[1] (+x) (halo_unpack layout
