@@ -177,7 +177,7 @@ def host_cpu() -> str:
 
 
 def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.0,
-                  warm=16, load=2.0, caps=(16_000_000,)):
+                  warm=16, load=2.0, buddy=False):
     """Poisson stream of shots of uneven size: the batching server against the plain
     per-shot loop (same kernels, one shot at a time, arrival order)."""
     import threading
@@ -233,10 +233,10 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
     # --- batching server, once per admission policy
     pct = lambda x, q: round(float(np.percentile(np.array(x), q)), 4)  # noqa: E731
 
-    def run_server(cap):
-        log(f"serving: batching server (max_active_points {cap})")
+    def run_server(allocator):
+        log(f"serving: batching server ({allocator} arena)")
         srv = serving.ShotServer(int(arena_gb * (1 << 30)), max_slots=max_slots,
-                                 max_active_points=cap)
+                                 allocator=allocator)
         ids = [None] * nshots
         t_arr = [0] * nshots
 
@@ -267,7 +267,7 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
         srv.close()
         lat_s = [(r[2][2] - t_arr[i]) / 1e9 for i, r in enumerate(res)]
         span_s = (max(r[2][2] for r in res) - min(t_arr)) / 1e9
-        return {"max_active_points": cap,
+        return {"allocator": allocator,
                 "shots_per_s": round(nshots / span_s, 3), "p50_s": pct(lat_s, 50),
                 "p99_s": pct(lat_s, 99), "Gpts_per_s": round(pts / span_s / 1e9, 2),
                 "speedup_shots_per_s": round(span_p / span_s, 3),
@@ -285,11 +285,11 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
         "max_slots": max_slots,
         "arena_GB": arena_gb,
     }
-    # "server": admission by slots and memory only; "server_capped": also waits while
-    # the running shots hold `cap` points (about what fills the device alone)
-    out["server"] = run_server(0)
-    for cap in caps:
-        out["server_capped"] = run_server(cap)
+    # the server's default policy (shots join while fewer than 16.8M points run), first
+    # fit arena; optionally the same with the buddy arena
+    out["server"] = run_server("first_fit")
+    if buddy:
+        out["server_buddy"] = run_server("buddy")
     return out
 
 
@@ -709,11 +709,11 @@ def main():
     del sim, traces
     torch.cuda.empty_cache()
     if not args.no_serving:
-        out["serving"] = serving_bench(nshots=args.shots)  # throughput: arrivals at 2x
+        out["serving"] = serving_bench(nshots=args.shots, buddy=True)  # arrivals at 2x
         # latency: arrivals at half the plain loop's service rate, a quarter of the shots
         out["serving_latency"] = serving_bench(nshots=max(16, args.shots // 4), load=0.5)
         # small shots, which leave the device part idle when run one at a time
-        out["serving_small"] = serving_bench(nshots=args.shots, lo=48, hi=128, caps=())
+        out["serving_small"] = serving_bench(nshots=args.shots, lo=48, hi=128)
     if not args.no_small:
         out["small"] = small_bench()
         out["small_exchange"] = small_exchange_bench()

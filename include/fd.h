@@ -483,14 +483,24 @@ int fd_grad_finalize_scaled(const fd_grid* g, const float* g_b, const float* vdt
  * global segment with a linear-heap or buddy allocator) and a bounded number
  * of concurrently active units of work (Sec. 3.2, MAX_ACTIVE_STREAMS).
  * S8/S9: a server that runs many independent forward-modelling shots of
- * different grid sizes at once.  Shots are admitted in submission order
- * (strict FIFO) while a slot is free and the shot's footprint fits in the
- * caller's device arena; every active shot then advances one time step per
- * batched launch (one kernel over the tiles of all active grids, each shot
- * at its own step, followed by one batched receiver kernel), so shots that
- * arrive while others run share the device.  Finished shots' traces are
- * copied to pinned host memory on a copy stream and their arena block is
- * freed.  Each shot is the forward model of fd_step_fused with Dirichlet
+ * different grid sizes at once.  In submission order (strict FIFO), a shot's
+ * footprint is carved from the caller's device arena as soon as it fits (at most
+ * four shots ahead of those running) and its admission work -- zeroing, the
+ * max(v) reduction and stability check, vdt2, sponge and receiver tables -- runs
+ * asynchronously on a stream of a bounded pool (at most four streams, created
+ * when first needed, reused when idle, half of the finished ones synchronised and
+ * released when the bound is reached), overlapping the steps of running shots.
+ * A shot joins the batched step when a slot is free and the activation policy
+ * lets it (fd_server_set_admission), as soon as its admission work is enqueued:
+ * the compute stream waits for that work, not the host.  Where the sponge's design
+ * velocity is known without max(v) (sponge_vmax given, or no sponge), all of it is
+ * enqueued at once and the stability check follows when max(v) reaches the host:
+ * a shot found unstable then leaves the step and ends with FD_EINVAL.  Every active shot
+ * advances one time step per batched step (one launch per kernel family over the
+ * tiles of its grids, each shot at its own step, then one batched receiver
+ * launch), so shots that arrive while others run share the device.  Finished
+ * shots' traces are copied to pinned host memory on a copy stream and their arena
+ * block is freed.  Each shot is the forward model of fd_step_fused with Dirichlet
  * halos, a quadratic sponge of `sponge_width` cells (reflection 1e-3) and a
  * Ricker source; its traces are bitwise those of the same shot run alone
  * through fd_step_fused + record_receivers with the same dt and sponge. */
@@ -547,15 +557,26 @@ int shot_submit(void* srv, const fd_shot_desc* d, int64_t* shot_id);
  * FD_EDEVICE or FD_ECANCELED.  FD_ENOTFOUND for an unknown or already
  * collected id.  Thread-safe. */
 int shot_poll(void* srv, int64_t shot_id, float* traces_host, size_t cap, int64_t t_ns[3]);
-/* Admission control: the next queued shot (FIFO) is admitted only while the
- * running shots hold fewer than max_active_points interior points (0, the
- * default: no limit besides slots, arena and tile table).  A shot is always
- * admitted when none runs.  Fewer shots at once finish each sooner once they
- * fill the device; more keep small shots from leaving it idle.  FD_EINVAL for
- * a NULL server or a negative limit.  Thread-safe. */
+/* Activation policy: which prepared shot joins the batched step.  Shots join in
+ * submission order (the next one waits for those before it), only with a free slot
+ * and tile-table room, and while the running shots hold fewer interior points than
+ * the fill: with max_active_points = 0 (the default) 256 x 128 x 32 x 8 =
+ * 8,388,608, the points that give each of the 256 CUs one 128 x 32 tile of 8
+ * z planes (a grid that fills the device runs alone and finishes sooner; smaller
+ * grids share it); with max_active_points > 0 that many.  A shot always joins when
+ * none runs.  FD_EINVAL for a NULL server or a negative limit.  Thread-safe. */
 int fd_server_set_admission(void* srv, int64_t max_active_points);
-/* Counts of queued, running, finished-but-uncollected shots, and batched
- * steps launched so far (4 int64).  Thread-safe. */
+/* Allocator of the shots' blocks in the arena (the paper's global segment carved by
+ * a linear-heap or a buddy allocator, Sec. 3.1): FD_ARENA_FIRST_FIT (the default:
+ * lowest hole that fits, neighbours merged on release) or FD_ARENA_BUDDY (binary
+ * buddy blocks of a power of two times 256 bytes; a shot then takes its footprint
+ * rounded up to such a block).  Only before the first shot_submit (FD_EINVAL
+ * after, or for another kind).  Thread-safe. */
+enum { FD_ARENA_FIRST_FIT = 0, FD_ARENA_BUDDY = 1 };
+int fd_server_set_allocator(void* srv, int32_t kind);
+/* Counts of waiting (queued or being prepared), running (in the batched step or
+ * copying out), finished-but-uncollected shots, and batched steps launched so far
+ * (4 int64).  Thread-safe. */
 int fd_server_stats(void* srv, int64_t out[4]);
 /* Stop the progress thread: queued and running shots finish as
  * FD_ECANCELED; finished shots stay collectable by shot_poll; later submits

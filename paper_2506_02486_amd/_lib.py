@@ -19,6 +19,8 @@ FD_ENOMEM = -12
 FD_EINVAL = -22
 FD_ECANCELED = -125
 FD_HALO = 4
+FD_ARENA_FIRST_FIT = 0
+FD_ARENA_BUDDY = 1
 
 
 class fd_grid(C.Structure):
@@ -114,6 +116,7 @@ SIGNATURES = {
     "shot_submit": (C.c_int, [_P, C.POINTER(fd_shot_desc), C.POINTER(_i64)]),
     "shot_poll": (C.c_int, [_P, _i64, _P, C.c_size_t, C.POINTER(_i64)]),
     "fd_server_set_admission": (C.c_int, [_P, _i64]),
+    "fd_server_set_allocator": (C.c_int, [_P, C.c_int32]),
     "fd_server_stats": (C.c_int, [_P, C.POINTER(_i64)]),
     "fd_server_shutdown": (C.c_int, [_P]),
     "fd_server_destroy": (C.c_int, [_P]),

@@ -148,6 +148,30 @@ bool receiver_plane_pays(const Geo& g);
 void forward_launch_shape(const Geo& g, int out[4]);
 // Tile size (x, y) of the batched kernel; returns threads per block.
 int batch_tile_shape(int* tx, int* ty);
+// Tile size (x, y) of the batched kernel of 16-byte lanes; returns the waves of a
+// CU's residency one block takes (for choose_kchunk).
+int batch4_tile_shape(int* tx, int* ty);
+// One step of up to kWideMulti grids in one launch of the 16-byte-lane kernel, their
+// parameters passed in the kernel arguments (each grid as fd_step_fused with its source
+// term steps it; same bits; one z chunk for all from the launch model).
+constexpr int kWideMulti = 8;
+struct WideStep {
+  Geo g;
+  Coef c;
+  const float* up;
+  const float* u;
+  float* un;
+  const float* q;
+  const float* ex;
+  const float* ey;
+  const float* ez;
+  fd_source src;
+};
+hipError_t launch_wide_multi(const WideStep* steps, int n, hipStream_t s);
+// One time step of every shot listed in the tile table, by the 16-byte-lane kernel
+// (same bits as the other kernels; no receiver row in the kernel).
+hipError_t launch_batched4(const BatchShot* shots, const int4* tiles, int ntiles,
+                           const BatchStep& a, hipStream_t s);
 // One time step of every shot listed in the tile table (entries: slot, bx, by, bz).
 hipError_t launch_batched(const BatchShot* shots, const int4* tiles, int ntiles,
                           const BatchStep& a, hipStream_t s);

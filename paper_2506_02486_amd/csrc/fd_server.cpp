@@ -1,23 +1,33 @@
 // fd_server.cpp -- continuous-batching server for independent forward shots.
 //
-// One progress thread per server owns the device work:
-//   admit   : strict FIFO; the head shot enters when a slot is free and a
-//             first-fit search of the arena finds its footprint.  Admission
-//             zeroes its wavefields, reduces max(v) (checking stability),
-//             builds vdt2 from the caller's velocity view and uploads sponge
-//             tables and receiver offsets, all on the server's own admission
-//             stream (its host waits never drain the steps queued on the
-//             compute stream), then writes the shot's entry of the slot table.
-//   step    : one batched stencil launch over the tile table of all active
-//             shots (each at its own step n, its source amplitude w[n] passed
-//             by value), which also writes the trace rows of shots whose
-//             receivers lie on one z plane; then one batched receiver launch
-//             for the other shots with receivers.
-//   retire  : a shot that reached nt has its traces copied to pinned host
-//             memory on the copy stream; when that copy has landed the shot
-//             is done and its arena block is released.
-// At most kInflight steps are queued ahead of the device.  The arena, the
-// streams and all device memory are the caller's; the server only carves.
+// One progress thread per server owns the device work.  A shot moves through:
+//   queued  : submitted, waiting in strict FIFO order;
+//   staging : its arena block is reserved (first fit or buddy, one caller-owned
+//             arena: the paper's global segment, Sec. 3.1) and its admission work
+//             runs asynchronously on a stream of a bounded pool (lazy creation,
+//             reuse, MAX_ACTIVE_STREAMS with partial synchronisation, Sec. 3.2):
+//             phase 1 zeroes its wavefields and reduces max(v) into its block;
+//             phase 2, once the maximum is on the host (stability checked), builds
+//             vdt2 from the caller's velocity view and uploads sponge tables,
+//             receiver offsets and a receiver-plane map; at most kPrepareAhead
+//             shots are staging or staged at once, so their admission overlaps
+//             the steps of the running shots;
+//   staged  : ready, waiting to join the batched step;
+//   active  : in a slot: every active shot advances one time step per batched
+//             step, each at its own step n (u^n in arr[n % 3]);
+//   draining: all steps done, traces copying to pinned host memory;
+//   done    : collected by shot_poll.
+// Activation (strict FIFO) needs a free slot and tile-table room, and fewer points
+// running than the fill (kFillPoints by default, else the caller's cap): a grid that
+// fills the device runs alone, smaller grids share it.
+// A batched step is one launch per kernel family over a tile table of every active
+// shot (grids of at least 7.5M points: 16-byte lanes, 128 x 32 tiles; smaller: one
+// float per lane, 64 x 32 tiles, which also writes the trace rows of shots whose
+// receivers share one plane), each family with the z chunk the launch model picks
+// for its shots, then one batched receiver launch for the other shots.
+// At most kEventEvery * kInflight steps are queued ahead of the device.  The arena,
+// compute and copy streams and all device memory are the caller's; the server only
+// carves.
 #include <math.h>
 #include <string.h>
 
@@ -34,24 +44,37 @@
 
 #include "fd_arena.h"
 #include "fd_internal.h"
+#include "fd_stream_pool.h"
 
 namespace fd {
 namespace {
 
 constexpr size_t kAlign = 256;
 // The progress thread runs at most kEventEvery * kInflight batched steps ahead of
-// the device.  It records a throttle event once per kEventEvery steps, not every
-// step: each default event between two launches left the device idle ~5.5 us
-// (kernel trace of lone 192^3 shots: 27 us steps)
-constexpr int kInflight = 2;
-constexpr int kEventEvery = 4;
+// the device: enough that a lone small grid's short steps (10 us at 128^3) never
+// wait for the thread to wake, few enough that a shot that becomes ready joins within
+// a few milliseconds.  It records a throttle event once per kEventEvery steps, not
+// every step: each event between two launches leaves the device idle ~4.7 us even
+// without the system-scope release (kernel trace of lone shots of the 128..384^3
+// mix: one event per 8 steps cost 0.5 ms of a 30 ms shot)
+constexpr int kInflight = 4;
+constexpr int kEventEvery = 32;
 constexpr int kTileCap = 1 << 16;   // tile-table entries
-// z planes per tile-table entry counted against kTileCap at admission.  The table
-// itself uses the z chunk the stencil's launch model picks for the active shots
-// together (a lone 128^3 shot: 2 planes, 512 blocks; 32 shots of the 128..384^3
-// mix: tens of planes), within kTileCap entries.
+// z planes per tile-table entry counted against kTileCap at activation (64 x 32
+// tiles: the larger count of the two families).  The table itself uses the z chunk
+// the launch model picks for the active shots of each family, within kTileCap.
 constexpr int kServeKchunk = 24;
 constexpr double kSpongeR = 1e-3;
+constexpr int kPrepareAhead = 4;      // shots staging or staged at once
+constexpr int kAdmitStreams = 4;      // bound of the admission stream pool
+// Activation fills the device: the running shots are enough for it when they give
+// every CU one 128 x 32 tile of 8 planes (the z chunk whose 8-plane z halo is as deep
+// as the chunk itself): 256 x 4096 x 8 points.  Measured against the plain loop on
+// the Poisson streams of the 128..384^3 mix (throughput at 2x its rate, p50 at 0.5x)
+// and of the 48..128^3 mix: 8.4M points 1.000x / 41.0 ms / 1.56x; 16.8M 1.002x /
+// 44.6 ms / 1.52x; 4.2M 0.996x / 40.9 ms / 1.42x; one shot at a time 0.995x / 41.0 ms /
+// 0.95x (plain: 39.8 ms).
+constexpr long long kFillPoints = 256LL * 128 * 32 * 8;
 
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
@@ -61,11 +84,19 @@ int64_t now_ns() {
       .count();
 }
 
+struct HipStreams {  // stream operations of the admission pool
+  using Stream = hipStream_t;
+  bool create(Stream* s) { return hipStreamCreateWithFlags(s, hipStreamNonBlocking) == hipSuccess; }
+  bool done(Stream s) { return hipStreamQuery(s) != hipErrorNotReady; }
+  void sync(Stream s) { (void)hipStreamSynchronize(s); }
+  void destroy(Stream s) { (void)hipStreamDestroy(s); }
+};
+
 // Layout of one shot's arena block.
 struct ShotLayout {
   fd_grid g;
   int64_t elems;
-  size_t vol, sponge, rec, traces, rmap, total;  // byte offsets and total
+  size_t vol, sponge, rec, traces, rmap, vm, total;  // byte offsets and total
   int tiles;
 };
 
@@ -90,7 +121,8 @@ int layout_for(const fd_shot_desc* d, ShotLayout* L) {
   L->traces = L->rec + align_up(8 * (size_t)std::max(d->nrec, 1));
   L->rmap = L->traces + align_up(4 * (size_t)d->nt * (size_t)std::max(d->nrec, 1));
   // receiver plane map (receivers on one z plane), nx * ny int32
-  L->total = L->rmap + (d->nrec > 0 ? align_up(4 * (size_t)d->nx * (size_t)d->ny) : 0);
+  L->vm = L->rmap + (d->nrec > 0 ? align_up(4 * (size_t)d->nx * (size_t)d->ny) : 0);
+  L->total = L->vm + kAlign;  // two int32: max and min of v
   int tx, ty;
   batch_tile_shape(&tx, &ty);
   const long long t = (long long)((d->nx + tx - 1) / tx) * ((d->ny + ty - 1) / ty) *
@@ -99,11 +131,18 @@ int layout_for(const fd_shot_desc* d, ShotLayout* L) {
   return FD_OK;
 }
 
+// Staging: the admission work waits for max(v) on the host before building the model
+// (the sponge is designed for the shot's own maximum); Issued: all admission work is
+// enqueued, the shot may join the step (the compute stream then waits for that work),
+// its stability check may still be pending; Staged: all admission work has finished.
+enum class State { Queued, Staging, Issued, Staged, Active, Draining, Done };
+
 struct Shot {
   int64_t id = 0;
   fd_shot_desc d{};
   std::vector<int32_t> rec;
   ShotLayout L{};
+  State state = State::Queued;
   int status = FD_EAGAIN;     // final code once finished
   bool finished = false;
   int64_t t_submit = 0, t_admit = 0, t_done = 0;
@@ -115,6 +154,17 @@ struct Shot {
   float* host = nullptr;      // pinned traces
   size_t host_cap = 0;        // floats
   hipEvent_t copied = nullptr;
+  // admission
+  hipStream_t as = nullptr;   // pool stream of its admission work
+  hipEvent_t ev = nullptr;    // end of the current admission phase
+  float* stage = nullptr;     // pinned: max/min of v, then the tables to upload
+  size_t stage_cap = 0;       // floats
+  bool wide = false;          // 16-byte-lane family
+  int plane_k = -1;           // receivers on one z plane (else -1)
+  bool check_pending = false; // max(v) not yet checked for stability
+  int abort_code = FD_OK;     // an active shot removed before its end ends with this
+  Geo geo{};
+  Coef coef{};
 };
 
 struct Server {
@@ -123,210 +173,197 @@ struct Server {
   int max_slots = 0;
   int device = 0;
   hipStream_t cs = nullptr, xs = nullptr;
-  hipStream_t as = nullptr;  // admission work (always the server's own)
   bool own_cs = false, own_xs = false;
-  std::unique_ptr<Arena> arena;
-  // device tables (head of the arena), the host master slot table and two
-  // pinned staging sets used in turn, so that rebuilding the tables never waits
-  // for the copy of the previous upload
+  std::unique_ptr<ArenaAllocator> arena;
+  int arena_kind = FD_ARENA_FIRST_FIT;
+  bool submitted = false;  // the allocator can no longer change
+  std::unique_ptr<StreamPool<HipStreams>> pool;
+  // device tables (head of the arena), the host master slot table and two pinned
+  // staging sets used in turn, so that rebuilding the tables never waits for the
+  // copy of the previous upload
   BatchShot* d_shots = nullptr;
-  int4* d_tiles = nullptr;
+  int4* d_tiles = nullptr;  // the 64 x 32 family's entries, then the 16-byte-lane family's
   int* d_slots = nullptr;
-  int32_t* d_scratch = nullptr;
   std::vector<BatchShot> shots_host;
   BatchShot* h_shots[2] = {};
   int4* h_tiles[2] = {};
   int* h_slots[2] = {};
   hipEvent_t table_ev[2] = {};
   int stage = 0;
-  int32_t* h_scratch = nullptr;
-  float* h_stage = nullptr;   // sponge and receiver upload staging
-  size_t h_stage_cap = 0;
   hipEvent_t step_ev[kInflight] = {};
-  int ntiles = 0, nactive = 0, max_nrec = 0;
+  int ntiles = 0, ntiles4 = 0, nactive = 0, max_nrec = 0;
+  // a family with one active shot steps it with the single-grid launch instead (the
+  // kernels and launch shape the same grid takes alone; the batched kernels' per-block
+  // look-up of its tile and shot costs 5-9% of a short step)
+  Shot* direct[2] = {nullptr, nullptr};
+  bool direct_rows[2] = {false, false};  // the direct launch writes the receiver row
+  // 2..kWideMulti shots of the 16-byte-lane family: one launch with their parameters
+  // in the kernel arguments (no tile table, no per-block look-up)
+  std::vector<Shot*> multi;
   bool table_dirty = false;
   // shared state
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Shot*> queue;
+  std::deque<Shot*> queue;  // queued
+  std::deque<Shot*> prep;   // staging or staged, in submission order
   std::map<int64_t, std::unique_ptr<Shot>> shots;
   std::vector<Shot*> slots;
   std::vector<Shot*> draining;
   std::vector<std::pair<size_t, float*>> pinned_pool;
   int64_t next_id = 1;
   int64_t steps = 0;
-  int64_t max_points = 0;  // admission waits while the slots hold this many points
+  int64_t max_points = 0;  // > 0: activation waits while the slots hold this many points
   int queued = 0, running = 0, finished = 0;
   bool stopping = false, stopped = false;
   std::thread th;
 };
 
-// ---- pinned trace buffers (reused: hipHostFree can stall the device)
-float* take_pinned(Server* S, size_t floats) {
+// ---- pinned host buffers (reused: hipHostFree can stall the device)
+float* take_pinned(Server* S, size_t floats, size_t* cap) {
+  size_t best = S->pinned_pool.size();
   for (size_t i = 0; i < S->pinned_pool.size(); ++i)
-    if (S->pinned_pool[i].first >= floats) {
-      float* p = S->pinned_pool[i].second;
-      S->pinned_pool.erase(S->pinned_pool.begin() + i);
-      return p;
-    }
+    if (S->pinned_pool[i].first >= floats &&
+        (best == S->pinned_pool.size() || S->pinned_pool[i].first < S->pinned_pool[best].first))
+      best = i;
+  if (best < S->pinned_pool.size()) {
+    float* p = S->pinned_pool[best].second;
+    *cap = S->pinned_pool[best].first;
+    S->pinned_pool.erase(S->pinned_pool.begin() + best);
+    return p;
+  }
   void* p = nullptr;
-  if (hipHostMalloc(&p, std::max<size_t>(floats, 1) * 4, hipHostMallocDefault) != hipSuccess)
-    return nullptr;
+  *cap = std::max<size_t>(floats, 1);
+  if (hipHostMalloc(&p, *cap * 4, hipHostMallocDefault) != hipSuccess) return nullptr;
   return static_cast<float*>(p);
 }
-void give_pinned(Server* S, float* p, size_t floats) {
-  if (p) S->pinned_pool.emplace_back(std::max<size_t>(floats, 1), p);
+void give_pinned(Server* S, float* p, size_t cap) {
+  if (p) S->pinned_pool.emplace_back(cap, p);
 }
 
 void finish_locked(Server* S, Shot* s, int code) {
   s->status = code;
   s->finished = true;
+  s->state = State::Done;
   s->t_done = now_ns();
   S->finished++;
 }
 
-// Device-side admission of `s` into `slot` with its arena block at s->off.
-// Runs on the progress thread without the lock.  Returns FD_OK or the code
-// the shot ends with.
-int admit_device(Server* S, Shot* s, int slot) {
+float* shot_vol(Server* S, const Shot* s, int i) {
+  return reinterpret_cast<float*>(S->base + s->off + (size_t)i * align_up(s->L.elems * 4));
+}
+char* shot_at(Server* S, const Shot* s, size_t field) { return S->base + s->off + field; }
+
+// Stability of the shot's time step for the max(v) its admission work copied to
+// the staging buffer.  FD_OK or FD_EINVAL.
+int check_vmax(const Shot* s) {
   const fd_shot_desc& d = s->d;
-  const ShotLayout& L = s->L;
-  char* blk = S->base + s->off;
-  float* vol[4];
-  for (int i = 0; i < 4; ++i) vol[i] = reinterpret_cast<float*>(blk + i * align_up(L.elems * 4));
-  float* sp = reinterpret_cast<float*>(blk + L.sponge);
-  int64_t* rec = reinterpret_cast<int64_t*>(blk + L.rec);
-  float* tr = reinterpret_cast<float*>(blk + L.traces);
-  int32_t* rmap = reinterpret_cast<int32_t*>(blk + L.rmap);
-  const Geo geo = make_geo(&L.g);
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_zero(vol[i], L.elems, S->as);
-  if (e == hipSuccess)
-    e = launch_vmax_view(d.nx, d.ny, d.nz, d.v_dev, d.v_ystride, d.v_zstride, S->d_scratch, S->as);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(S->h_scratch, S->d_scratch, 8, hipMemcpyDeviceToHost, S->as);
-  if (e == hipSuccess) e = hipStreamSynchronize(S->as);
-  if (e != hipSuccess) return check_hip(e, "shot admission");
   float vmax, vmin;
-  memcpy(&vmax, &S->h_scratch[0], 4);
-  memcpy(&vmin, &S->h_scratch[1], 4);
+  memcpy(&vmax, &s->stage[0], 4);
+  memcpy(&vmin, &s->stage[1], 4);
   if (!(isfinite(vmax) && vmax > 0.f && vmin > 0.f))
     return fail(FD_EINVAL, "shot %lld: velocity must be finite and > 0", (long long)s->id);
   const double inv2 = 1.0 / (d.dx * d.dx) + 1.0 / (d.dy * d.dy) + 1.0 / (d.dz * d.dz);
   if ((double)vmax * d.dt * sqrt(symbol_at_nyquist() * inv2) > 2.0)
     return fail(FD_EINVAL, "shot %lld: dt %g is unstable for max(v) %g", (long long)s->id, d.dt,
                 (double)vmax);
-  e = launch_prepare_vdt2_view(geo, d.v_dev, d.v_ystride, d.v_zstride, vol[3], d.dt, S->as);
-  if (e != hipSuccess) return check_hip(e, "shot vdt2");
-  // sponge tables and receiver offsets through the pinned staging buffer
-  const size_t need = (size_t)(d.nx + d.ny + d.nz) + 2 + 2 * (size_t)std::max(d.nrec, 1) +
-                      (d.nrec > 0 ? (size_t)d.nx * (size_t)d.ny : 0);
-  if (need > S->h_stage_cap) {
-    if (S->h_stage) (void)hipHostFree(S->h_stage);
-    S->h_stage = nullptr;
-    if (hipHostMalloc((void**)&S->h_stage, need * 4, hipHostMallocDefault) != hipSuccess)
-      return fail(FD_ENOMEM, "shot: pinned staging allocation failed");
-    S->h_stage_cap = need;
-  }
-  const double vdesign = d.sponge_vmax > 0 ? d.sponge_vmax : (double)vmax;
+  return FD_OK;
+}
+
+// The model on the shot's admission stream: vdt2 from the caller's velocity view, and
+// (host) sponge tables for the design velocity vdesign, receiver offsets and plane
+// map into the staging buffer, uploaded; then the admission event.
+hipError_t admit_model(Server* S, Shot* s, double vdesign) {
+  const fd_shot_desc& d = s->d;
+  const ShotLayout& L = s->L;
+  const Geo geo = make_geo(&L.g);
+  hipError_t e = launch_prepare_vdt2_view(geo, d.v_dev, d.v_ystride, d.v_zstride,
+                                          shot_vol(S, s, 3), d.dt, s->as);
+  if (e != hipSuccess) return e;
+  // staging layout (floats): [2: max/min] [nx+ny+nz: sponge] [pad to even]
+  // [2*nrec: int64 offsets] [nx*ny: int32 plane map]
+  float* h = s->stage + 2;
   const int n3[3] = {d.nx, d.ny, d.nz};
   const double d3[3] = {d.dx, d.dy, d.dz};
-  float* h = S->h_stage;
   for (int a = 0; a < 3; ++a) {
     const double emax = fd_sponge_eta_max(vdesign, d3[a], d.dt, d.sponge_width, kSpongeR);
     fd_sponge_profile(h, n3[a], d.sponge_width, emax < 0 ? 0.0 : emax);
     h += n3[a];
   }
-  int64_t* hrec = reinterpret_cast<int64_t*>(S->h_stage + (d.nx + d.ny + d.nz + 1) / 2 * 2);
+  int64_t* hrec = reinterpret_cast<int64_t*>(s->stage + 2 + (d.nx + d.ny + d.nz + 1) / 2 * 2);
   if (d.nrec > 0) fd_receiver_offsets(&L.g, s->rec.data(), d.nrec, hrec);
-  e = hipMemcpyAsync(sp, S->h_stage, 4 * (size_t)(d.nx + d.ny + d.nz), hipMemcpyHostToDevice,
-                     S->as);
+  e = hipMemcpyAsync(shot_at(S, s, L.sponge), s->stage + 2, 4 * (size_t)(d.nx + d.ny + d.nz),
+                     hipMemcpyHostToDevice, s->as);
   if (e == hipSuccess && d.nrec > 0)
-    e = hipMemcpyAsync(rec, hrec, 8 * (size_t)d.nrec, hipMemcpyHostToDevice, S->as);
-  // receivers on one plane: the batched kernel writes their rows (no record launch)
-  int32_t plane_k = -1;
+    e = hipMemcpyAsync(shot_at(S, s, L.rec), hrec, 8 * (size_t)d.nrec, hipMemcpyHostToDevice,
+                       s->as);
+  // receivers on one plane: the 64 x 32 kernels write their rows themselves
+  s->plane_k = -1;
   if (d.nrec > 0) {
     int32_t* hmap = reinterpret_cast<int32_t*>(hrec + d.nrec);
-    if (fd_receiver_plane_map(&L.g, s->rec.data(), d.nrec, hmap, &plane_k) != FD_OK) plane_k = -1;
-    if (e == hipSuccess && plane_k >= 0)
-      e = hipMemcpyAsync(rmap, hmap, 4 * (size_t)d.nx * (size_t)d.ny, hipMemcpyHostToDevice,
-                         S->as);
+    if (fd_receiver_plane_map(&L.g, s->rec.data(), d.nrec, hmap, &s->plane_k) != FD_OK)
+      s->plane_k = -1;
+    if (e == hipSuccess && s->plane_k >= 0)
+      e = hipMemcpyAsync(shot_at(S, s, L.rmap), hmap, 4 * (size_t)d.nx * (size_t)d.ny,
+                         hipMemcpyHostToDevice, s->as);
   }
-  // the staging buffer is reused, and the compute stream may use the shot from
-  // its next step on: all of the shot's admission work has finished after this
-  if (e == hipSuccess) e = hipStreamSynchronize(S->as);
-  if (e != hipSuccess) return check_hip(e, "shot upload");
-  BatchShot& b = S->shots_host[slot];
-  b.g = geo;
-  b.c = make_coef(&L.g);
-  for (int i = 0; i < 3; ++i) b.arr[i] = vol[i];
-  b.q = vol[3];
-  b.ex = sp;
-  b.ey = sp + d.nx;
-  b.ez = sp + d.nx + d.ny;
-  b.si = d.src[0];
-  b.sj = d.src[1];
-  b.sk = d.src[2];
-  b.kchunk = kServeKchunk;
-  b.rec = rec;
-  b.traces = tr;
-  b.nrec = d.nrec;
-  b.rk = plane_k;
-  b.rmap = plane_k >= 0 ? rmap : nullptr;
+  if (e == hipSuccess) e = hipEventRecord(s->ev, s->as);
   s->w.resize(d.nt);
   fd_ricker(s->w.data(), d.nt, 0, d.dt, d.f0, d.t0);
-  return FD_OK;
+  s->wide = forward_wide_tiles(geo);
+  return e;
 }
 
-// Rebuild and upload the tile table, slot list and slot table.
-hipError_t upload_tables(Server* S) {
-  const int st = S->stage ^= 1;
-  // the upload before the previous one used this staging set; it has landed
-  hipError_t e = hipEventSynchronize(S->table_ev[st]);
+// The admission work that needs nothing from the host, on the shot's pool stream:
+// zero the three wavefields, reduce max(v) and min(v) into the block and copy them to
+// the staging buffer; when the sponge's design velocity is known without that
+// maximum (given, or no sponge), also the model (admit_model), so the shot can join
+// the step at once, its stability checked when the maximum arrives.  *whole tells
+// which.
+hipError_t admit_start(Server* S, Shot* s, bool* whole) {
+  const fd_shot_desc& d = s->d;
+  int32_t* vm = reinterpret_cast<int32_t*>(shot_at(S, s, s->L.vm));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_zero(shot_vol(S, s, i), s->L.elems, s->as);
+  if (e == hipSuccess)
+    e = launch_vmax_view(d.nx, d.ny, d.nz, d.v_dev, d.v_ystride, d.v_zstride, vm, s->as);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->stage, vm, 8, hipMemcpyDeviceToHost, s->as);
+  *whole = d.sponge_width == 0 || d.sponge_vmax > 0;
   if (e != hipSuccess) return e;
-  int4* h_tiles = S->h_tiles[st];
-  int* h_slots = S->h_slots[st];
-  memcpy(S->h_shots[st], S->shots_host.data(), sizeof(BatchShot) * S->max_slots);
-  int nt = 0, na = 0, mr = 0;
-  int tx, ty;
-  const int wpb = batch_tile_shape(&tx, &ty) / 64;  // waves per block
-  // one z chunk for all active shots, chosen by the stencil's launch-time model
-  // within kTileCap entries (a chunk of kServeKchunk planes always fits)
-  std::vector<long long> xy;
-  std::vector<int> nzs;
-  for (const Shot* s : S->slots)
-    if (s) {
-      xy.push_back((long long)((s->d.nx + tx - 1) / tx) * ((s->d.ny + ty - 1) / ty));
-      nzs.push_back(s->d.nz);
-    }
-  const int kc = xy.empty() ? kServeKchunk
-                            : choose_kchunk(xy.data(), nzs.data(), (int)xy.size(), wpb, 0, kTileCap);
-  for (int slot = 0; slot < S->max_slots; ++slot) {
-    Shot* s = S->slots[slot];
-    if (!s) continue;
-    if (s->d.nrec > 0 && !S->shots_host[slot].rmap) {  // rows left to batched_record
-      h_slots[na++] = slot;
-      mr = std::max(mr, s->d.nrec);
-    }
-    const int bxn = (s->d.nx + tx - 1) / tx, byn = (s->d.ny + ty - 1) / ty;
-    const int bzn = (s->d.nz + kc - 1) / kc;
-    S->h_shots[st][slot].kchunk = kc;
-    for (int bz = 0; bz < bzn; ++bz)
-      for (int by = 0; by < byn; ++by)
-        for (int bx = 0; bx < bxn; ++bx) h_tiles[nt++] = make_int4(slot, bx, by, bz);
-  }
-  S->ntiles = nt;
-  S->nactive = na;
-  S->max_nrec = mr;
-  e = hipMemcpyAsync(S->d_shots, S->h_shots[st], sizeof(BatchShot) * S->max_slots,
-                     hipMemcpyHostToDevice, S->cs);
-  if (e == hipSuccess && nt)
-    e = hipMemcpyAsync(S->d_tiles, h_tiles, sizeof(int4) * nt, hipMemcpyHostToDevice, S->cs);
-  if (e == hipSuccess && na)
-    e = hipMemcpyAsync(S->d_slots, h_slots, sizeof(int) * na, hipMemcpyHostToDevice, S->cs);
-  if (e == hipSuccess) e = hipEventRecord(S->table_ev[st], S->cs);
-  S->table_dirty = false;
-  return e;
+  if (*whole) return admit_model(S, s, d.sponge_width ? d.sponge_vmax : 0.0);
+  return hipEventRecord(s->ev, s->as);
+}
+
+// Staging floats a shot needs (see admit_model).
+size_t stage_floats(const fd_shot_desc& d) {
+  return 2 + (size_t)(d.nx + d.ny + d.nz + 1) / 2 * 2 + 2 * (size_t)std::max(d.nrec, 0) +
+         (d.nrec > 0 ? (size_t)d.nx * (size_t)d.ny : 0);
+}
+
+// The slot-table entry of an activated shot.
+void fill_slot(Server* S, Shot* s, int slot) {
+  const ShotLayout& L = s->L;
+  BatchShot& b = S->shots_host[slot];
+  s->geo = make_geo(&L.g);
+  s->coef = make_coef(&L.g);
+  b.g = s->geo;
+  b.c = s->coef;
+  for (int i = 0; i < 3; ++i) b.arr[i] = shot_vol(S, s, i);
+  b.q = shot_vol(S, s, 3);
+  float* sp = reinterpret_cast<float*>(shot_at(S, s, L.sponge));
+  b.ex = sp;
+  b.ey = sp + s->d.nx;
+  b.ez = sp + s->d.nx + s->d.ny;
+  b.si = s->d.src[0];
+  b.sj = s->d.src[1];
+  b.sk = s->d.src[2];
+  b.kchunk = kServeKchunk;
+  b.rec = reinterpret_cast<int64_t*>(shot_at(S, s, L.rec));
+  b.traces = reinterpret_cast<float*>(shot_at(S, s, L.traces));
+  b.nrec = s->d.nrec;
+  // the 16-byte-lane kernel leaves every receiver row to the batched receiver launch
+  const bool in_kernel = s->plane_k >= 0 && !s->wide;
+  b.rk = in_kernel ? s->plane_k : -1;
+  b.rmap = in_kernel ? reinterpret_cast<int32_t*>(shot_at(S, s, L.rmap)) : nullptr;
 }
 
 int tiles_in_use(Server* S) {
@@ -343,48 +380,329 @@ long long points_in_use(Server* S) {
   return p;
 }
 
+// Whether the head staged shot may join the active ones now: while the running
+// shots hold fewer points than the fill (a shot always joins when none runs).
+bool activation_pays(Server* S) {
+  bool any = false;
+  for (const Shot* s : S->slots) any = any || s != nullptr;
+  if (!any) return true;
+  return points_in_use(S) < (S->max_points > 0 ? S->max_points : kFillPoints);
+}
+
+// Rebuild and upload the tile tables, slot list and slot table.
+hipError_t upload_tables(Server* S) {
+  const int st = S->stage ^= 1;
+  // the upload before the previous one used this staging set; it has landed
+  hipError_t e = hipEventSynchronize(S->table_ev[st]);
+  if (e != hipSuccess) return e;
+  int4* h_tiles = S->h_tiles[st];
+  int* h_slots = S->h_slots[st];
+  memcpy(S->h_shots[st], S->shots_host.data(), sizeof(BatchShot) * S->max_slots);
+  int na = 0, mr = 0;
+  int counts[2] = {0, 0};
+  // each family: one z chunk for its shots from the launch model, within the table
+  // (a chunk of the deepest grid's depth always fits: activation keeps the tiles of
+  // kServeKchunk-plane chunks within kTileCap)
+  int kc[2] = {kServeKchunk, kServeKchunk};
+  int tws[2][2];
+  int wpb[2];
+  wpb[0] = batch_tile_shape(&tws[0][0], &tws[0][1]) / 64;
+  wpb[1] = batch4_tile_shape(&tws[1][0], &tws[1][1]);
+  std::vector<long long> xy[2];
+  std::vector<int> nzs[2];
+  long long least[2] = {0, 0};  // entries at one chunk per grid
+  int fam[2] = {0, 0};
+  for (int f = 0; f < 2; ++f) S->direct[f] = nullptr;
+  for (Shot* s : S->slots)
+    if (s) {
+      ++fam[s->wide ? 1 : 0];
+      S->direct[s->wide ? 1 : 0] = s;
+    }
+  S->multi.clear();
+  if (fam[1] >= 2 && fam[1] <= kWideMulti)
+    for (Shot* s : S->slots)
+      if (s && s->wide) S->multi.push_back(s);
+  for (int f = 0; f < 2; ++f) {
+    if (fam[f] != 1) S->direct[f] = nullptr;
+    S->direct_rows[f] = false;
+    if (const Shot* s = S->direct[f])  // as fd_forward_run samples a lone grid
+      S->direct_rows[f] = f == 0 && s->plane_k >= 0 &&
+                          (point_kernel_pays(s->geo) || receiver_plane_pays(s->geo));
+  }
+  for (const Shot* s : S->slots)
+    if (s && s != S->direct[s->wide ? 1 : 0] && !(s->wide && !S->multi.empty())) {
+      const int f = s->wide ? 1 : 0;
+      xy[f].push_back((long long)((s->d.nx + tws[f][0] - 1) / tws[f][0]) *
+                      ((s->d.ny + tws[f][1] - 1) / tws[f][1]));
+      nzs[f].push_back(s->d.nz);
+      least[f] += xy[f].back();
+    }
+  // the 16-byte-lane family first, leaving the other at least one chunk per grid
+  long long budget = kTileCap - least[0];
+  for (int f = 1; f >= 0; --f) {
+    if (xy[f].empty()) continue;
+    kc[f] = choose_kchunk(xy[f].data(), nzs[f].data(), (int)xy[f].size(), wpb[f], 0, budget);
+    long long used = 0;
+    for (size_t i = 0; i < xy[f].size(); ++i) used += xy[f][i] * ((nzs[f][i] + kc[f] - 1) / kc[f]);
+    budget = kTileCap - used;
+  }
+  int nt = 0;
+  for (int f = 0; f < 2; ++f) {
+    for (int slot = 0; slot < S->max_slots; ++slot) {
+      Shot* s = S->slots[slot];
+      if (!s || (int)s->wide != f) continue;
+      // rows left to the batched receiver launch: all of the 16-byte-lane family,
+      // and of the other those whose step does not write them
+      const bool in_kernel = f == 0 && (s == S->direct[0] ? S->direct_rows[0]
+                                                          : S->shots_host[slot].rmap != nullptr);
+      if (s->d.nrec > 0 && !in_kernel) {
+        h_slots[na++] = slot;
+        mr = std::max(mr, s->d.nrec);
+      }
+      if (s == S->direct[f] || (f == 1 && !S->multi.empty())) continue;
+      const int bxn = (s->d.nx + tws[f][0] - 1) / tws[f][0];
+      const int byn = (s->d.ny + tws[f][1] - 1) / tws[f][1];
+      const int bzn = (s->d.nz + kc[f] - 1) / kc[f];
+      S->h_shots[st][slot].kchunk = kc[f];
+      for (int bz = 0; bz < bzn; ++bz)
+        for (int by = 0; by < byn; ++by)
+          for (int bx = 0; bx < bxn; ++bx) {
+            if (nt >= kTileCap) return hipErrorInvalidValue;  // (the budget above prevents it)
+            h_tiles[nt++] = make_int4(slot, bx, by, bz);
+          }
+    }
+    counts[f] = nt - (f ? counts[0] : 0);
+  }
+  S->ntiles = counts[0];
+  S->ntiles4 = counts[1];
+  S->nactive = na;
+  S->max_nrec = mr;
+  e = hipMemcpyAsync(S->d_shots, S->h_shots[st], sizeof(BatchShot) * S->max_slots,
+                     hipMemcpyHostToDevice, S->cs);
+  if (e == hipSuccess && nt)
+    e = hipMemcpyAsync(S->d_tiles, h_tiles, sizeof(int4) * nt, hipMemcpyHostToDevice, S->cs);
+  if (e == hipSuccess && na)
+    e = hipMemcpyAsync(S->d_slots, h_slots, sizeof(int) * na, hipMemcpyHostToDevice, S->cs);
+  if (e == hipSuccess) e = hipEventRecord(S->table_ev[st], S->cs);
+  S->table_dirty = false;
+  return e;
+}
+
+// One step of a lone shot of its family by the single-grid launch (as fd_forward_run
+// steps it: the one-thread-per-point kernel on small grids, the marching kernels
+// above; with `rows` the receiver row is written by the same launch).
+hipError_t step_direct(Server* S, Shot* s, bool rows) {
+  const int n = s->n;
+  float* arr[3];
+  for (int i = 0; i < 3; ++i) arr[i] = shot_vol(S, s, i);
+  const float* q = shot_vol(S, s, 3);
+  const float* sp = reinterpret_cast<const float*>(shot_at(S, s, s->L.sponge));
+  const float* ex = sp;
+  const float* ey = sp + s->d.nx;
+  const float* ez = sp + s->d.nx + s->d.ny;
+  const fd_source src{s->d.src[0], s->d.src[1], s->d.src[2], s->w[n]};
+  RecPlane rp{nullptr, -1, nullptr};
+  if (rows) {
+    rp.map = reinterpret_cast<const int32_t*>(shot_at(S, s, s->L.rmap));
+    rp.k = s->plane_k;
+    rp.row = reinterpret_cast<float*>(shot_at(S, s, s->L.traces)) + (size_t)n * s->d.nrec;
+  }
+  const float* up = arr[(n + 2) % 3];
+  const float* u = arr[n % 3];
+  float* un = arr[(n + 1) % 3];
+  if (s->wide)
+    return launch_forward_wide(s->geo, s->coef, up, u, un, q, ex, ey, ez, &src, nullptr, nullptr,
+                               S->cs);
+  if (point_kernel_pays(s->geo))
+    return launch_step_point(s->geo, s->coef, up, u, un, q, ex, ey, ez, &src, rows ? &rp : nullptr,
+                             S->cs);
+  return launch_step(s->geo, s->coef, up, u, un, q, ex, ey, ez, &src, S->cs, rows ? &rp : nullptr);
+}
+
+// One step of the 16-byte-lane family's shots in one launch, their parameters in the
+// kernel arguments.
+hipError_t step_multi(Server* S) {
+  WideStep w[kWideMulti];
+  int n = 0;
+  for (Shot* s : S->multi) {
+    const int k = s->n;
+    float* arr[3];
+    for (int i = 0; i < 3; ++i) arr[i] = shot_vol(S, s, i);
+    const float* sp = reinterpret_cast<const float*>(shot_at(S, s, s->L.sponge));
+    WideStep& x = w[n++];
+    x.g = s->geo;
+    x.c = s->coef;
+    x.up = arr[(k + 2) % 3];
+    x.u = arr[k % 3];
+    x.un = arr[(k + 1) % 3];
+    x.q = shot_vol(S, s, 3);
+    x.ex = sp;
+    x.ey = sp + s->d.nx;
+    x.ez = sp + s->d.nx + s->d.ny;
+    x.src = fd_source{s->d.src[0], s->d.src[1], s->d.src[2], s->w[k]};
+  }
+  return launch_wide_multi(w, n, S->cs);
+}
+
+// Release a shot's block and admission resources (nothing of the shot's may still
+// run: its admission event was seen or its stream synchronised, and no queued step
+// uses it).
+void drop_prepared(Server* S, Shot* s) {
+  if (s->has_block) S->arena->release(s->off, s->L.total);
+  s->has_block = false;
+  give_pinned(S, s->stage, s->stage_cap);
+  s->stage = nullptr;
+  if (s->ev) (void)hipEventDestroy(s->ev);
+  s->ev = nullptr;
+}
+
 void progress(Server* S) {
   const hipError_t dev = hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
   // without its device the thread can run nothing: every shot fails with FD_EDEVICE
   int fatal = dev == hipSuccess ? FD_OK : check_hip(dev, "server thread: hipSetDevice");
   while (!S->stopping) {
-    // ---- admission (strict FIFO)
-    while (!S->queue.empty() && fatal == FD_OK) {
+    bool busy = false;  // admission work in flight: poll again soon
+    // ---- stage: reserve blocks and start admission work, in FIFO order
+    while (!S->queue.empty() && fatal == FD_OK && (int)S->prep.size() < kPrepareAhead) {
       Shot* s = S->queue.front();
+      size_t off;
+      if (!S->arena->alloc(s->L.total, &off)) break;
+      S->queue.pop_front();
+      S->queued--;  // counted again below while it waits for a slot
+      s->off = off;
+      s->has_block = true;
+      S->prep.push_back(s);
+      s->stage = take_pinned(S, stage_floats(s->d), &s->stage_cap);
+      lk.unlock();
+      int rc = FD_OK;
+      if (!s->stage) rc = fail(FD_ENOMEM, "shot: pinned staging allocation failed");
+      hipError_t e = hipSuccess;
+      bool whole = false;
+      if (rc == FD_OK) e = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
+      if (rc == FD_OK && e == hipSuccess && !S->pool->acquire(&s->as))
+        e = hipErrorOutOfMemory;
+      if (rc == FD_OK && e == hipSuccess) e = admit_start(S, s, &whole);
+      if (rc == FD_OK && e != hipSuccess) rc = check_hip(e, "shot admission");
+      if (rc != FD_OK && s->as) (void)hipStreamSynchronize(s->as);
+      lk.lock();
+      S->queued++;
+      s->state = whole ? State::Issued : State::Staging;
+      s->check_pending = true;
+      if (rc != FD_OK) {
+        S->prep.pop_back();
+        S->queued--;
+        drop_prepared(S, s);
+        finish_locked(S, s, rc);
+        if (rc == FD_EDEVICE) fatal = rc;
+      }
+    }
+    // ---- admission work that has finished
+    for (size_t i = 0; i < S->prep.size();) {
+      Shot* s = S->prep[i];
+      if (s->state != State::Staging && s->state != State::Issued) { ++i; continue; }
+      const hipError_t q = hipEventQuery(s->ev);
+      if (q == hipErrorNotReady) { busy = true; ++i; continue; }
+      int rc = q == hipSuccess ? FD_OK : check_hip(q, "shot admission");
+      if (rc == FD_OK && s->check_pending) {
+        rc = check_vmax(s);
+        s->check_pending = false;
+      }
+      if (rc == FD_OK && s->state == State::Staging) {  // the model needs the maximum
+        float vmax;
+        memcpy(&vmax, &s->stage[0], 4);
+        lk.unlock();
+        const hipError_t e = admit_model(S, s, (double)vmax);
+        lk.lock();
+        if (e == hipSuccess) {
+          s->state = State::Issued;
+          busy = true;
+          ++i;
+          continue;
+        }
+        rc = check_hip(e, "shot admission");
+        (void)hipStreamSynchronize(s->as);  // nothing of the shot's may still run
+      }
+      if (rc == FD_OK) {  // all admission work has landed
+        s->state = State::Staged;
+        give_pinned(S, s->stage, s->stage_cap);
+        s->stage = nullptr;
+        (void)hipEventDestroy(s->ev);
+        s->ev = nullptr;
+        ++i;
+        continue;
+      }
+      S->prep.erase(S->prep.begin() + i);
+      S->queued--;
+      drop_prepared(S, s);
+      s->t_admit = now_ns();
+      finish_locked(S, s, rc);
+      if (rc == FD_EDEVICE) fatal = rc;
+      S->cv.notify_all();
+    }
+    // ---- active shots whose admission work was still running when they joined
+    for (int slot = 0; slot < S->max_slots; ++slot) {
+      Shot* s = S->slots[slot];
+      if (!s || !s->ev) continue;
+      const hipError_t q = hipEventQuery(s->ev);
+      if (q == hipErrorNotReady) continue;
+      int rc = q == hipSuccess ? FD_OK : check_hip(q, "shot admission");
+      if (rc == FD_OK && s->check_pending) rc = check_vmax(s);
+      s->check_pending = false;
+      give_pinned(S, s->stage, s->stage_cap);
+      s->stage = nullptr;
+      (void)hipEventDestroy(s->ev);
+      s->ev = nullptr;
+      if (rc == FD_OK) continue;
+      // unstable (or failed): leave the step; its block is released once the steps
+      // already queued with it have run
+      S->slots[slot] = nullptr;
+      S->table_dirty = true;
+      s->abort_code = rc;
+      s->state = State::Draining;
+      hipError_t r = hipEventCreateWithFlags(&s->copied, hipEventDisableTiming);
+      if (r == hipSuccess) r = hipEventRecord(s->copied, S->cs);
+      if (r != hipSuccess) {
+        (void)hipStreamSynchronize(S->cs);
+        if (s->copied) (void)hipEventDestroy(s->copied);
+        s->copied = nullptr;
+        S->arena->release(s->off, s->L.total);
+        s->has_block = false;
+        S->running--;
+        finish_locked(S, s, rc);
+        continue;
+      }
+      S->draining.push_back(s);
+      if (rc == FD_EDEVICE) fatal = rc;
+    }
+    // ---- activate prepared shots (strict FIFO)
+    while (!S->prep.empty() && fatal == FD_OK &&
+           (S->prep.front()->state == State::Staged || S->prep.front()->state == State::Issued)) {
+      Shot* s = S->prep.front();
       int slot = -1;
       for (int i = 0; i < S->max_slots; ++i)
         if (!S->slots[i]) { slot = i; break; }
       if (slot < 0) break;
       if (tiles_in_use(S) + s->L.tiles > kTileCap) break;
-      if (S->max_points > 0 && points_in_use(S) >= S->max_points) break;
-      size_t off;
-      if (!S->arena->alloc(s->L.total, &off)) break;
-      S->queue.pop_front();
-      S->queued--;
-      s->off = off;
-      s->has_block = true;
-      s->slot = slot;
-      S->slots[slot] = s;  // reserve
-      lk.unlock();
-      int rc = admit_device(S, s, slot);
-      lk.lock();
-      s->t_admit = now_ns();
-      if (rc == FD_OK) {
-        s->host_cap = (size_t)s->d.nt * (size_t)s->d.nrec;
-        s->host = take_pinned(S, s->host_cap);
-        if (!s->host) rc = fail(FD_ENOMEM, "shot: pinned trace buffer allocation failed");
-      }
-      if (rc != FD_OK) {
-        S->slots[slot] = nullptr;
-        S->arena->release(s->off, s->L.total);
-        s->has_block = false;
-        give_pinned(S, s->host, s->host_cap);
+      if (!activation_pays(S)) break;
+      size_t cap = 0;
+      s->host_cap = (size_t)s->d.nt * (size_t)s->d.nrec;
+      s->host = take_pinned(S, s->host_cap, &cap);
+      if (!s->host) break;  // retried on the next pass
+      // admission work still running: the compute stream waits for it, not the host
+      if (s->ev && hipStreamWaitEvent(S->cs, s->ev, 0) != hipSuccess) {
+        give_pinned(S, s->host, cap);
         s->host = nullptr;
-        finish_locked(S, s, rc);
-        if (rc == FD_EDEVICE) fatal = rc;
-        continue;
+        break;
       }
+      S->prep.pop_front();
+      S->queued--;
+      s->t_admit = now_ns();
+      s->host_cap = cap;
+      s->slot = slot;
+      S->slots[slot] = s;
+      fill_slot(S, s, slot);
+      s->state = State::Active;
       S->running++;
       S->table_dirty = true;
     }
@@ -398,7 +716,7 @@ void progress(Server* S) {
       (void)hipEventDestroy(s->copied);
       s->copied = nullptr;
       S->running--;
-      finish_locked(S, s, q == hipSuccess ? FD_OK : FD_EDEVICE);
+      finish_locked(S, s, q != hipSuccess ? FD_EDEVICE : s->abort_code);
       S->draining.erase(S->draining.begin() + i);
       S->cv.notify_all();
     }
@@ -412,10 +730,23 @@ void progress(Server* S) {
     bool any = false;
     for (Shot* s : S->slots) any = any || s != nullptr;
     if (!any || fatal != FD_OK) {
-      if (S->draining.empty())
+      // nothing to step: wait for the oldest admission phase in flight (the shot that
+      // joins next), else for a copy, a submission or a short timeout
+      hipEvent_t wait_ev = nullptr;
+      for (Shot* s : S->prep)
+        if (s->state == State::Staging || s->state == State::Issued) {
+          wait_ev = s->ev;
+          break;
+        }
+      if (wait_ev && fatal == FD_OK) {
+        lk.unlock();
+        (void)hipEventSynchronize(wait_ev);
+        lk.lock();
+      } else if (busy || !S->draining.empty()) {
+        S->cv.wait_for(lk, std::chrono::microseconds(20));
+      } else {
         S->cv.wait_for(lk, std::chrono::milliseconds(2));
-      else
-        S->cv.wait_for(lk, std::chrono::microseconds(200));
+      }
       continue;
     }
     // ---- one batched step of every active shot
@@ -437,7 +768,17 @@ void progress(Server* S) {
     if (step % kEventEvery == 0 && grp >= kInflight)
       e = hipEventSynchronize(S->step_ev[grp % kInflight]);
     if (e == hipSuccess && dirty) e = upload_tables(S);
-    if (e == hipSuccess) e = launch_batched(S->d_shots, S->d_tiles, S->ntiles, a, S->cs);
+    for (int f = 0; f < 2 && e == hipSuccess; ++f) {
+      if (Shot* s = S->direct[f]) {
+        e = step_direct(S, s, S->direct_rows[f]);
+      } else if (f == 0) {
+        e = launch_batched(S->d_shots, S->d_tiles, S->ntiles, a, S->cs);
+      } else if (!S->multi.empty()) {
+        e = step_multi(S);
+      } else {
+        e = launch_batched4(S->d_shots, S->d_tiles + S->ntiles, S->ntiles4, a, S->cs);
+      }
+    }
     if (e == hipSuccess)
       e = launch_batched_record(S->d_shots, S->d_slots, S->nactive, S->max_nrec, a, S->cs);
     if (e == hipSuccess && step % kEventEvery == kEventEvery - 1)
@@ -465,14 +806,15 @@ void progress(Server* S) {
       if (s->n < s->d.nt) continue;
       S->slots[slot] = nullptr;
       S->table_dirty = true;
+      s->state = State::Draining;
       hipError_t r = hipEventCreateWithFlags(&s->copied, hipEventDisableTiming);
       hipEvent_t stepped = nullptr;
       if (r == hipSuccess) r = hipEventCreateWithFlags(&stepped, hipEventDisableTiming);
       if (r == hipSuccess) r = hipEventRecord(stepped, S->cs);
       if (r == hipSuccess) r = hipStreamWaitEvent(S->xs, stepped, 0);
-      if (r == hipSuccess && s->host_cap)
-        r = hipMemcpyAsync(s->host, reinterpret_cast<char*>(S->base) + s->off + s->L.traces,
-                           4 * s->host_cap, hipMemcpyDeviceToHost, S->xs);
+      if (r == hipSuccess && s->d.nrec > 0)
+        r = hipMemcpyAsync(s->host, shot_at(S, s, s->L.traces),
+                           4 * (size_t)s->d.nt * (size_t)s->d.nrec, hipMemcpyDeviceToHost, S->xs);
       if (r == hipSuccess) r = hipEventRecord(s->copied, S->xs);
       if (stepped) (void)hipEventDestroy(stepped);
       if (r != hipSuccess) {
@@ -490,6 +832,7 @@ void progress(Server* S) {
   // let queued device work finish before the caller frees anything
   (void)hipStreamSynchronize(S->cs);
   (void)hipStreamSynchronize(S->xs);
+  S->pool->sync_all();
 }
 
 void stop_server(Server* S) {
@@ -506,11 +849,16 @@ void stop_server(Server* S) {
     S->queued--;
   }
   S->queue.clear();
+  for (Shot* s : S->prep) {  // their admission streams were synchronised
+    drop_prepared(S, s);
+    S->queued--;
+    finish_locked(S, s, FD_ECANCELED);
+  }
+  S->prep.clear();
   for (int slot = 0; slot < S->max_slots; ++slot)
     if (Shot* s = S->slots[slot]) {
       S->slots[slot] = nullptr;
-      if (s->has_block) S->arena->release(s->off, s->L.total);
-      s->has_block = false;
+      drop_prepared(S, s);  // the block, and admission resources still held
       S->running--;
       finish_locked(S, s, FD_ECANCELED);
     }
@@ -521,7 +869,7 @@ void stop_server(Server* S) {
     if (s->has_block) S->arena->release(s->off, s->L.total);
     s->has_block = false;
     S->running--;
-    finish_locked(S, s, landed ? FD_OK : FD_EDEVICE);
+    finish_locked(S, s, landed ? s->abort_code : FD_EDEVICE);
   }
   S->draining.clear();
   S->stopped = true;
@@ -549,8 +897,7 @@ int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t ma
   if (max_slots < 1 || max_slots > MAX_BATCH_SLOTS)
     return fail(FD_EINVAL, "fd_server_create: max_slots must be in 1..%d", MAX_BATCH_SLOTS);
   const size_t head = align_up(sizeof(BatchShot) * MAX_BATCH_SLOTS) +
-                      align_up(sizeof(int4) * kTileCap) + align_up(sizeof(int) * MAX_BATCH_SLOTS) +
-                      align_up(8);
+                      align_up(sizeof(int4) * kTileCap) + align_up(sizeof(int) * MAX_BATCH_SLOTS);
   if (arena_bytes < head + kAlign)
     return fail(FD_ENOMEM, "fd_server_create: arena of %zu bytes is too small", arena_bytes);
   std::unique_ptr<Server> S(new Server());
@@ -563,14 +910,13 @@ int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t ma
   p += align_up(sizeof(int4) * kTileCap);
   S->d_slots = reinterpret_cast<int*>(p);
   p += align_up(sizeof(int) * MAX_BATCH_SLOTS);
-  S->d_scratch = reinterpret_cast<int32_t*>(p);
-  p += align_up(8);
   S->base = p;  // shot blocks live after the tables
-  S->bytes = arena_bytes - head;
-  S->arena.reset(new Arena(S->bytes / kAlign * kAlign));
+  S->bytes = (arena_bytes - head) / kAlign * kAlign;
+  S->arena.reset(new Arena(S->bytes));
   S->slots.assign(max_slots, nullptr);
   int rc = check_hip(hipGetDevice(&S->device), "fd_server_create");
   if (rc) return rc;
+  S->pool.reset(new StreamPool<HipStreams>(HipStreams{}, kAdmitStreams));
   hipError_t e = hipSuccess;
   S->cs = reinterpret_cast<hipStream_t>(compute_stream);
   S->xs = reinterpret_cast<hipStream_t>(copy_stream);
@@ -582,7 +928,6 @@ int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t ma
     e = hipStreamCreateWithFlags(&S->xs, hipStreamNonBlocking);
     S->own_xs = e == hipSuccess;
   }
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->as, hipStreamNonBlocking);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) {
     e = hipHostMalloc((void**)&S->h_shots[i], sizeof(BatchShot) * MAX_BATCH_SLOTS,
                       hipHostMallocDefault);
@@ -594,7 +939,6 @@ int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t ma
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->table_ev[i], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(S->table_ev[i], S->cs);
   }
-  if (e == hipSuccess) e = hipHostMalloc((void**)&S->h_scratch, 8, hipHostMallocDefault);
   // throttle events only tell how far the device got; without the system-scope
   // release (an L2 write-back) an event between two steps costs no idle time
   for (int i = 0; i < kInflight && e == hipSuccess; ++i)
@@ -610,6 +954,21 @@ int fd_server_create(void** srv, void* arena_dev, size_t arena_bytes, int32_t ma
   Server* raw = S.release();
   raw->th = std::thread(progress, raw);
   *srv = raw;
+  return FD_OK;
+}
+
+int fd_server_set_allocator(void* srv, int32_t kind) {
+  Server* S = static_cast<Server*>(srv);
+  if (!S) return fail(FD_EINVAL, "fd_server_set_allocator: NULL server");
+  if (kind != FD_ARENA_FIRST_FIT && kind != FD_ARENA_BUDDY)
+    return fail(FD_EINVAL, "fd_server_set_allocator: kind %d is not FD_ARENA_FIRST_FIT or "
+                           "FD_ARENA_BUDDY", kind);
+  std::lock_guard<std::mutex> g(S->mu);
+  if (S->submitted)
+    return fail(FD_EINVAL, "fd_server_set_allocator: shots were submitted already");
+  if (kind == FD_ARENA_BUDDY) S->arena.reset(new BuddyArena(S->bytes, kAlign));
+  else S->arena.reset(new Arena(S->bytes));
+  S->arena_kind = kind;
   return FD_OK;
 }
 
@@ -636,15 +995,23 @@ int shot_submit(void* srv, const fd_shot_desc* d, int64_t* shot_id) {
     if (i < 0 || i >= d->nx || j < 0 || j >= d->ny || k < 0 || k >= d->nz)
       return fail(FD_EINVAL, "shot_submit: receiver %d outside the interior", r);
   }
-  if (L.total > S->bytes || L.tiles > kTileCap)
-    return fail(FD_ENOMEM, "shot_submit: footprint %zu bytes can never fit the arena (%zu)",
-                L.total, S->bytes);
   s->d = *d;
   s->d.rec_ijk_host = nullptr;
   s->L = L;
   s->t_submit = now_ns();
   std::lock_guard<std::mutex> g(S->mu);
+  // a buddy block is the footprint rounded up to a power of two times 256 bytes
+  size_t need = L.total;
+  if (S->arena_kind == FD_ARENA_BUDDY) {
+    size_t b = kAlign;
+    while (b < need) b <<= 1;
+    need = b;
+  }
+  if (need > S->bytes || L.tiles > kTileCap)
+    return fail(FD_ENOMEM, "shot_submit: footprint %zu bytes can never fit the arena (%zu)",
+                need, S->bytes);
   if (S->stopping) return fail(FD_ECANCELED, "shot_submit: server is shut down");
+  S->submitted = true;
   s->id = S->next_id++;
   *shot_id = s->id;
   S->queue.push_back(s.get());
@@ -663,7 +1030,8 @@ int shot_poll(void* srv, int64_t shot_id, float* traces_host, size_t cap, int64_
   Shot* s = it->second.get();
   if (!s->finished) return FD_EAGAIN;
   if (traces_host && s->host && s->status == FD_OK)
-    memcpy(traces_host, s->host, 4 * std::min(cap, s->host_cap));
+    memcpy(traces_host, s->host,
+           4 * std::min(cap, (size_t)s->d.nt * (size_t)std::max(s->d.nrec, 0)));
   if (t_ns) {
     t_ns[0] = s->t_submit;
     t_ns[1] = s->t_admit;
@@ -711,21 +1079,24 @@ int fd_server_destroy(void* srv) {
   Server* S = static_cast<Server*>(srv);
   if (!S) return fail(FD_EINVAL, "fd_server_destroy: NULL server");
   stop_server(S);
-  for (auto& kv : S->shots) give_pinned(S, kv.second->host, kv.second->host_cap);
+  for (auto& kv : S->shots) {
+    give_pinned(S, kv.second->host, kv.second->host_cap);
+    kv.second->host = nullptr;
+    give_pinned(S, kv.second->stage, kv.second->stage_cap);
+    kv.second->stage = nullptr;
+  }
   for (auto& pb : S->pinned_pool) (void)hipHostFree(pb.second);
-  if (S->h_stage) (void)hipHostFree(S->h_stage);
   for (int i = 0; i < 2; ++i) {
     if (S->h_shots[i]) (void)hipHostFree(S->h_shots[i]);
     if (S->h_tiles[i]) (void)hipHostFree(S->h_tiles[i]);
     if (S->h_slots[i]) (void)hipHostFree(S->h_slots[i]);
     if (S->table_ev[i]) (void)hipEventDestroy(S->table_ev[i]);
   }
-  if (S->h_scratch) (void)hipHostFree(S->h_scratch);
   for (int i = 0; i < kInflight; ++i)
     if (S->step_ev[i]) (void)hipEventDestroy(S->step_ev[i]);
+  S->pool.reset();  // synchronises and destroys the admission streams
   if (S->own_cs) (void)hipStreamDestroy(S->cs);
   if (S->own_xs) (void)hipStreamDestroy(S->xs);
-  if (S->as) (void)hipStreamDestroy(S->as);
   delete S;
   return FD_OK;
 }

@@ -36,6 +36,7 @@
 // One block per CU (more than 128 VGPRs per lane): 256 blocks fill the chip.
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "fd_internal.h"
@@ -83,15 +84,13 @@ __device__ __forceinline__ f4 ld4_nt(const char* base, unsigned boff) {
   return __builtin_nontemporal_load(reinterpret_cast<const f4*>(base + boff));
 }
 
+// The work of one block: tile (bx, by) of the x-y plane, z chunk bz, of the grid
+// and operands p describes.
 template <bool SPONGE, bool FUSE, bool XCH>
-__global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
+__device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const int by,
+                                               const int bz) {
   __shared__ __attribute__((aligned(16))) float sm[2][LY * LX];
 
-  const int logical = remap_block4(blockIdx.x, gridDim.x);
-  const int bx = logical % p.tiles_x;
-  const int rest = logical / p.tiles_x;
-  const int by = rest % p.tiles_y;
-  const int bz = rest / p.tiles_y;
   const int lx = threadIdx.x;
   const int tr = threadIdx.y;
   const int nx = p.g.nx, ny = p.g.ny, nz = p.g.nz;
@@ -362,6 +361,66 @@ __global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
 }
 
 template <bool SPONGE, bool FUSE, bool XCH>
+__global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
+  const int logical = remap_block4(blockIdx.x, gridDim.x);
+  const int bx = logical % p.tiles_x;
+  const int rest = logical / p.tiles_x;
+  stencil4_block<SPONGE, FUSE, XCH>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
+}
+
+// Many grids in one launch: block b runs tile tiles[remap(b)] = (slot, bx, by, bz) of
+// shot `slot` at its own step a.n[slot] (u^n in arr[n % 3]) with source amplitude
+// a.w[slot]; every point runs exactly the code of stencil4_kernel.
+__global__ void __launch_bounds__(LANES * TROWS) batched4_kernel(const BatchShot* __restrict__ shots,
+                                                                 const int4* __restrict__ tiles,
+                                                                 BatchStep a) {
+  const int4 t = tiles[remap_block4(blockIdx.x, gridDim.x)];
+  const BatchShot& b = shots[t.x];
+  const int n = a.n[t.x];
+  P4 p;
+  p.g = b.g;
+  p.c = b.c;
+  p.u = b.arr[n % 3];
+  p.up = b.arr[(n + 2) % 3];
+  p.q = b.q;
+  p.un = b.arr[(n + 1) % 3];
+  p.ex = b.ex;
+  p.ey = b.ey;
+  p.ez = b.ez;
+  p.tiles_x = 0;
+  p.tiles_y = 0;
+  p.kchunk = b.kchunk;
+  p.si = b.si;
+  p.sj = b.sj;
+  p.sk = b.sk;
+  p.sw = a.w[t.x];
+  p.rin[0] = p.rin[1] = nullptr;
+  p.sout[0] = p.sout[1] = nullptr;
+  stencil4_block<true, true, false>(p, t.y, t.z, t.w);
+}
+
+// Up to kWideMulti grids in one launch, their parameters in the kernel arguments:
+// grid i owns blocks [start[i], start[i+1]) (tiles in the order of stencil4_kernel);
+// a block finds its grid by comparing uniform values, with no memory look-up before
+// its first loads.
+struct MultiArgs {
+  int n;
+  int start[kWideMulti + 1];
+  P4 grid[kWideMulti];
+};
+
+__global__ void __launch_bounds__(LANES * TROWS) multi4_kernel(MultiArgs A) {
+  const int b = remap_block4(blockIdx.x, gridDim.x);
+  int i = 0;
+  while (i + 1 < A.n && b >= A.start[i + 1]) ++i;
+  const P4& p = A.grid[i];
+  const int t = b - A.start[i];
+  const int bx = t % p.tiles_x;
+  const int rest = t / p.tiles_x;
+  stencil4_block<true, true, false>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
+}
+
+template <bool SPONGE, bool FUSE, bool XCH>
 hipError_t launch4(P4 p, hipStream_t st) {
   // one block per CU: its 8 waves take a CU's share of 16 (more than 128 VGPRs)
   const LaunchShape sh = stencil_shape(p.g, TX, TY, 16);
@@ -393,6 +452,64 @@ bool wide_forward_fits(const Geo& g, const float* const arrays[4], const float* 
       if (!faces[i] || !aligned16(faces[i])) return false;
   }
   return true;
+}
+
+int batch4_tile_shape(int* tx, int* ty) {
+  *tx = TX;
+  *ty = TY;
+  return 16;  // one block per CU: a CU's share of 16 waves
+}
+
+hipError_t launch_batched4(const BatchShot* shots, const int4* tiles, int ntiles,
+                           const BatchStep& a, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batched4_kernel, dim3((unsigned)ntiles), dim3(LANES, TROWS), 0, s, shots,
+                     tiles, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_multi(const WideStep* steps, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n > kWideMulti) return hipErrorInvalidValue;
+  // one z chunk for all the grids, from the launch model over them
+  long long xy[kWideMulti];
+  int nz[kWideMulti];
+  for (int i = 0; i < n; ++i) {
+    xy[i] = (long long)((steps[i].g.nx + TX - 1) / TX) * ((steps[i].g.ny + TY - 1) / TY);
+    nz[i] = steps[i].g.nz;
+  }
+  const int kc = choose_kchunk(xy, nz, n, 16, 0, 0x7fffffffLL);
+  MultiArgs A;
+  A.n = n;
+  A.start[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    const WideStep& w = steps[i];
+    P4& p = A.grid[i];
+    p = P4{};
+    p.g = w.g;
+    p.c = w.c;
+    p.u = w.u;
+    p.up = w.up;
+    p.q = w.q;
+    p.un = w.un;
+    p.ex = w.ex;
+    p.ey = w.ey;
+    p.ez = w.ez;
+    p.tiles_x = (w.g.nx + TX - 1) / TX;
+    p.tiles_y = (w.g.ny + TY - 1) / TY;
+    p.kchunk = std::min(kc, w.g.nz);
+    p.si = w.src.i;
+    p.sj = w.src.j;
+    p.sk = w.src.k;
+    p.sw = w.src.w;
+    const long long blocks =
+        (long long)p.tiles_x * p.tiles_y * ((w.g.nz + p.kchunk - 1) / p.kchunk);
+    if ((long long)A.start[i] + blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    A.start[i + 1] = A.start[i] + (int)blocks;
+  }
+  for (int i = n + 1; i <= kWideMulti; ++i) A.start[i] = A.start[n];
+  hipLaunchKernelGGL(multi4_kernel, dim3((unsigned)A.start[n]), dim3(LANES, TROWS), 0, s, A);
+  return hipGetLastError();
 }
 
 void wide_forward_shape(const Geo& g, int out[4]) {

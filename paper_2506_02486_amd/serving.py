@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import api
-from ._lib import FD_EAGAIN, FD_ENOTFOUND, FD_OK, check, fd_shot_desc, lib
+from ._lib import FD_ARENA_BUDDY, FD_EAGAIN, FD_ENOTFOUND, FD_OK, check, fd_shot_desc, lib
 
 
 class Shot:
@@ -69,7 +69,9 @@ class ShotServer:
     """Submit shots from any thread; poll for (code, traces (nt, nrec), t_ns)."""
 
     def __init__(self, arena_bytes: int, max_slots: int = 32, device="cuda",
-                 max_active_points: int = 0):
+                 max_active_points: int = 0, allocator: str = "first_fit"):
+        if allocator not in ("first_fit", "buddy"):
+            raise ValueError("allocator must be 'first_fit' or 'buddy'")
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         self.cs = torch.cuda.Stream(device=device)
         self.xs = torch.cuda.Stream(device=device)
@@ -79,11 +81,15 @@ class ShotServer:
               "fd_server_create")
         self.h = h
         self._shots: dict[int, Shot] = {}
+        if allocator == "buddy":
+            check(lib().fd_server_set_allocator(self.h, FD_ARENA_BUDDY), "fd_server_set_allocator")
         if max_active_points:
             self.set_admission(max_active_points)
 
     def set_admission(self, max_active_points: int):
-        """Admit queued shots only while the running ones hold fewer points (0: no limit)."""
+        """Activation policy: 0 (default) the launch model's (a shot joins the running
+        ones when together they stream faster per point); > 0 join while the running
+        shots hold fewer points than this."""
         check(lib().fd_server_set_admission(self.h, int(max_active_points)),
               "fd_server_set_admission")
 

@@ -1,11 +1,13 @@
 """GPU tests of the continuous-batching shot server (S8, S9).
 
 Every shot's traces from the batched server must be bitwise equal to the same shot run
-alone through fd_step_fused + record_receivers (the batched kernel runs the same
+alone through fd_step_fused + record_receivers (the batched kernels run the same
 per-point code); the smallest shots are also checked against the FP64 oracle
 (relative L2 <= 1e-4).  Admission is checked under an arena that holds only a few
-shots and under a cap on the points running at once, and the error paths
-(oversize, unknown id, unstable dt, shutdown) end as documented.
+shots, with the buddy allocator, with many more shots than slots and admission
+streams, under a cap on the points running at once and under the default launch-model
+policy, with both kernel families in one step, and the error paths (oversize, unknown
+id, unstable dt, shutdown, allocator change after submit) end as documented.
 """
 import numpy as np
 import pytest
@@ -183,6 +185,19 @@ def test_error_paths(model):
         unstable = serving.Shot(vd[:20, :20, :20], 10, 1.2 * 0.45286 * 10.0 / vmax, (5, 5, 5))
         code, tr, _ = srv.wait(srv.submit(unstable))
         assert code == _lib.FD_EINVAL and tr is None
+        # with the sponge's design velocity given (or no sponge) the shot may join the
+        # step before its stability check: found unstable it leaves the step, and a
+        # shot running with it keeps its bits
+        dt_bad = 1.2 * 0.45286 * 10.0 / vmax
+        bad = [serving.Shot(vd[:20, :20, :20], 300, dt_bad, (5, 5, 5), sponge_width=4,
+                            sponge_vmax=vmax),
+               serving.Shot(vd[:20, :20, :20], 300, dt_bad, (5, 5, 5), sponge_width=0)]
+        good = make_shots(model, 1, nt=40, seed=31)[0]
+        ids = [srv.submit(bad[0]), srv.submit(good), srv.submit(bad[1])]
+        res = [srv.wait(i) for i in ids]
+        assert res[0][0] == _lib.FD_EINVAL and res[0][1] is None
+        assert res[2][0] == _lib.FD_EINVAL and res[2][1] is None
+        assert res[1][0] == _lib.FD_OK and same_bits(res[1][1], solo(good))
         ok = serving.Shot(vd[:20, :20, :20], 10, dt, (5, 5, 5), np.array([[1, 1, 1]], np.int32))
         sid = srv.submit(ok)
         assert srv.wait(sid)[0] == _lib.FD_OK
@@ -198,3 +213,95 @@ def test_error_paths(model):
         with pytest.raises(_lib.FDError) as e:
             srv.submit(ok)
         assert e.value.code == _lib.FD_ECANCELED
+
+
+def test_buddy_allocator_mix_equals_solo(model):
+    shots = make_shots(model, 8, seed=21)
+    with serving.ShotServer(3 << 30, max_slots=4, allocator="buddy") as srv:
+        ids = [srv.submit(s) for s in shots]
+        res = [srv.wait(i) for i in ids]
+        with pytest.raises(_lib.FDError) as e:  # the allocator is fixed once shots came
+            _lib.check(_lib.lib().fd_server_set_allocator(srv.h, _lib.FD_ARENA_FIRST_FIT),
+                       "fd_server_set_allocator")
+        assert e.value.code == _lib.FD_EINVAL
+    for shot, (code, tr, t) in zip(shots, res):
+        assert code == _lib.FD_OK
+        assert same_bits(tr, solo(shot))
+    with pytest.raises(ValueError):
+        serving.ShotServer(1 << 20, allocator="slab")
+
+
+def test_many_shots_few_slots_and_admission_streams(model):
+    """40 short shots through 2 slots: admission work of up to four shots ahead runs on
+    the bounded stream pool (reused, partially synchronised) while others step; strict
+    FIFO activation and every trace equal to its solo run."""
+    shots = make_shots(model, 40, lo=16, hi=40, nt=6, width=4, seed=17)
+    with serving.ShotServer(2 << 30, max_slots=2) as srv:
+        ids = [srv.submit(s) for s in shots]
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert st == {"queued": 0, "running": 0, "finished": 0, "steps": st["steps"]}
+    admits = [r[2][1] for r in res]
+    assert admits == sorted(admits)
+    for shot, (code, tr, _) in zip(shots, res):
+        assert code == _lib.FD_OK
+        assert same_bits(tr, solo(shot))
+
+
+def test_both_kernel_families_in_one_step():
+    """A grid of at least 7.5M points (the 16-byte-lane kernel, its receiver rows from
+    the batched receiver launch) running in the same steps as small grids (the 64 x 32
+    kernel, rows in the kernel); and every shot forced onto the 16-byte-lane family
+    (fd_set_tiles(4)): traces equal to the solo runs bit for bit."""
+    v = smooth_velocity(200, 200, 192, seed=2, sigma=4.0)  # the 10 small grids fit inside
+    vd = torch.from_numpy(v).cuda()
+    dt = ora.cfl_dt(v, 10.0)
+    vmax = float(v.max())
+
+    def shot(nx, ny, nz, src):
+        return serving.Shot(vd[:nz, :ny, :nx], 12, dt, src, receivers_xline(nx, ny // 2, 4),
+                            sponge_width=8, sponge_vmax=vmax)
+
+    mix = [shot(40, 36, 30, (20, 18, 15)), shot(200, 200, 192, (100, 90, 96)),
+           shot(52, 47, 33, (26, 23, 16)), shot(37, 61, 29, (18, 30, 14))]
+    many = [shot(20 + 3 * i, 18 + 2 * i, 12 + i, (9, 8, 6)) for i in range(10)]
+    assert api.step_kernel(api.Grid(200, 200, 192))["kernel"] == "wide_128x32"
+    # automatic: one grid of each family; forced onto 16-byte lanes: the four grids in
+    # one launch with their parameters as kernel arguments, then ten grids, more than
+    # such a launch carries, through the tile table
+    for tiles, shots in ((0, mix), (4, mix), (4, many)):
+        api.set_tiles(tiles)
+        try:
+            with serving.ShotServer(4 << 30, max_slots=16, max_active_points=1 << 40) as srv:
+                ids = [srv.submit(s) for s in shots]
+                res = [srv.wait(i) for i in ids]
+                st = srv.stats()
+            # they ran together (the point cap lets every one join): fewer steps than shots
+            # times steps
+            assert st["steps"] < sum(s.nt for s in shots)
+            for s, (code, tr, _) in zip(shots, res):
+                assert code == _lib.FD_OK
+                assert same_bits(tr, solo(s))
+        finally:
+            api.set_tiles(0)
+
+
+def test_default_policy_runs_device_filling_grids_alone():
+    """Under the default policy (join while fewer than 16.8M points run), grids that each
+    fill the device (400 x 400 x 200: 32M points) are activated one after the other,
+    each when the one before has finished, while small grids share the steps
+    (test_mix_equals_solo_bitwise_and_overlaps)."""
+    v = smooth_velocity(400, 400, 200, seed=2, sigma=4.0)
+    vd = torch.from_numpy(v).cuda()
+    dt = ora.cfl_dt(v, 10.0)
+    shots = [serving.Shot(vd, 15, dt, (200, 200, 100 + i), receivers_xline(400, 200, 4),
+                          sponge_width=16, sponge_vmax=float(v.max())) for i in range(3)]
+    with serving.ShotServer(10 << 30, max_slots=8) as srv:
+        ids = [srv.submit(s) for s in shots]
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert all(r[0] == _lib.FD_OK for r in res)
+    admits = [r[2][1] for r in res]
+    assert admits == sorted(admits)
+    assert st["steps"] == sum(s.nt for s in shots)  # never two of them in one step
+    assert same_bits(res[1][1], solo(shots[1]))
