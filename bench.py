@@ -177,9 +177,11 @@ def host_cpu() -> str:
 
 
 def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.0,
-                  warm=16, load=2.0, buddy=False):
+                  warm=16, load=2.0, reps=3, buddy=False):
     """Poisson stream of shots of uneven size: the batching server against the plain
-    per-shot loop (same kernels, one shot at a time, arrival order)."""
+    per-shot loop (same kernels, one shot at a time, arrival order), each run `reps`
+    times, alternately, on the same arrivals; reported per run, as the mean, and as
+    the spread (max - min) of the runs."""
     import threading
 
     import numpy as np
@@ -212,29 +214,24 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
     arr = poisson_arrivals(nshots, lam, seed=4)
     pts = float(sum(np.prod(s.shape) for s in shots)) * nt
     log(f"serving: plain service rate {mu:.2f} shots/s, arrivals at {lam:.2f} shots/s")
-
-    # --- plain loop, in arrival order
-    log("serving: plain loop")
+    pct = lambda x, q: float(np.percentile(np.array(x), q))  # noqa: E731
     plain_tr = {}
-    lat_p = []
-    base = time.monotonic()
-    for i, s in enumerate(shots):
-        wait = base + arr[i] - time.monotonic()
-        if wait > 0:
-            time.sleep(wait)
-        tr = plain.run(s)
-        lat_p.append(time.monotonic() - (base + arr[i]))
-        if i < 8:
-            plain_tr[i] = tr
-    span_p = time.monotonic() - base
-    del plain
-    torch.cuda.empty_cache()
 
-    # --- batching server, once per admission policy
-    pct = lambda x, q: round(float(np.percentile(np.array(x), q)), 4)  # noqa: E731
+    def run_plain():
+        lat = []
+        base = time.monotonic()
+        for i, s in enumerate(shots):
+            wait = base + arr[i] - time.monotonic()
+            if wait > 0:
+                time.sleep(wait)
+            tr = plain.run(s)
+            lat.append(time.monotonic() - (base + arr[i]))
+            if i < 8:
+                plain_tr[i] = tr
+        span = time.monotonic() - base
+        return {"shots_per_s": nshots / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99)}
 
     def run_server(allocator):
-        log(f"serving: batching server ({allocator} arena)")
         srv = serving.ShotServer(int(arena_gb * (1 << 30)), max_slots=max_slots,
                                  allocator=allocator)
         ids = [None] * nshots
@@ -265,31 +262,57 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
         th.join()
         steps = srv.stats()["steps"]
         srv.close()
-        lat_s = [(r[2][2] - t_arr[i]) / 1e9 for i, r in enumerate(res)]
-        span_s = (max(r[2][2] for r in res) - min(t_arr)) / 1e9
-        return {"allocator": allocator,
-                "shots_per_s": round(nshots / span_s, 3), "p50_s": pct(lat_s, 50),
-                "p99_s": pct(lat_s, 99), "Gpts_per_s": round(pts / span_s / 1e9, 2),
-                "speedup_shots_per_s": round(span_p / span_s, 3),
+        lat = [(r[2][2] - t_arr[i]) / 1e9 for i, r in enumerate(res)]
+        span = (max(r[2][2] for r in res) - min(t_arr)) / 1e9
+        return {"shots_per_s": nshots / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
                 "batched_steps": steps, "all_ok": all(r[0] == 0 for r in res),
                 "traces_bitwise_equal_first8": all(np.array_equal(res[i][1], plain_tr[i])
                                                    for i in plain_tr)}
 
+    def summary(runs):
+        out = {}
+        for k in ("shots_per_s", "p50_s", "p99_s"):
+            x = [r[k] for r in runs]
+            out[k] = round(float(np.mean(x)), 4)
+            out[k + "_runs"] = [round(v, 4) for v in x]
+            out[k + "_spread"] = round(float(max(x) - min(x)), 4)
+        out["Gpts_per_s"] = round(pts * out["shots_per_s"] / nshots / 1e9, 2)
+        return out
+
+    runs_p, runs_s = [], []
+    for rep in range(reps):
+        log(f"serving: plain loop (run {rep + 1} of {reps})")
+        runs_p.append(run_plain())
+        log(f"serving: batching server (run {rep + 1} of {reps})")
+        runs_s.append(run_server("first_fit"))
+    del plain
+    torch.cuda.empty_cache()
+    p, srv = summary(runs_p), summary(runs_s)
+    srv["batched_steps"] = runs_s[-1]["batched_steps"]
+    srv["all_ok"] = all(r["all_ok"] for r in runs_s)
+    srv["traces_bitwise_equal_first8"] = all(r["traces_bitwise_equal_first8"] for r in runs_s)
+    srv["speedup_shots_per_s"] = round(srv["shots_per_s"] / p["shots_per_s"], 4)
+    # the server's gain over the plain loop against the larger run-to-run spread
+    srv["gain_shots_per_s"] = round(srv["shots_per_s"] - p["shots_per_s"], 4)
+    srv["spread_shots_per_s"] = max(p["shots_per_s_spread"], srv["shots_per_s_spread"])
     out = {
         "workload": f"{nshots} shots, grids uniform in [{lo},{hi}]^3 (seed 3), {nt} steps, "
                     f"sponge 16, Ricker 15 Hz, x-line receivers, Poisson arrivals at "
-                    f"{load:g}x the plain loop's service rate (seed 4)",
+                    f"{load:g}x the plain loop's service rate (seed 4); {reps} runs of each, "
+                    f"alternating",
         "arrival_rate": round(lam, 3),
-        "plain_loop": {"shots_per_s": round(nshots / span_p, 3), "p50_s": pct(lat_p, 50),
-                       "p99_s": pct(lat_p, 99), "Gpts_per_s": round(pts / span_p / 1e9, 2)},
+        "plain_loop": p,
+        "server": srv,
         "max_slots": max_slots,
         "arena_GB": arena_gb,
     }
-    # the server's default policy (shots join while fewer than 16.8M points run), first
-    # fit arena; optionally the same with the buddy arena
-    out["server"] = run_server("first_fit")
-    if buddy:
-        out["server_buddy"] = run_server("buddy")
+    if buddy:  # the same with the buddy arena, one run
+        log("serving: batching server (buddy arena)")
+        b = run_server("buddy")
+        out["server_buddy"] = {"shots_per_s": round(b["shots_per_s"], 3),
+                               "p50_s": round(b["p50_s"], 4), "p99_s": round(b["p99_s"], 4),
+                               "all_ok": b["all_ok"],
+                               "traces_bitwise_equal_first8": b["traces_bitwise_equal_first8"]}
     return out
 
 

@@ -559,12 +559,15 @@ int shot_submit(void* srv, const fd_shot_desc* d, int64_t* shot_id);
 int shot_poll(void* srv, int64_t shot_id, float* traces_host, size_t cap, int64_t t_ns[3]);
 /* Activation policy: which prepared shot joins the batched step.  Shots join in
  * submission order (the next one waits for those before it), only with a free slot
- * and tile-table room, and while the running shots hold fewer interior points than
- * the fill: with max_active_points = 0 (the default) 256 x 128 x 32 x 8 =
- * 8,388,608, the points that give each of the 256 CUs one 128 x 32 tile of 8
- * z planes (a grid that fills the device runs alone and finishes sooner; smaller
- * grids share it); with max_active_points > 0 that many.  A shot always joins when
- * none runs.  FD_EINVAL for a NULL server or a negative limit.  Thread-safe. */
+ * and tile-table room.  Shots of one batched step advance in lockstep, so joining a
+ * running shot trades its latency for throughput.  With max_active_points = 0 (the
+ * default) a shot joins if the interior points of the running shots and its own stay
+ * within the fill, 256 x 128 x 32 x 8 = 8,388,608 (each of the 256 CUs one 128 x 32
+ * tile of 8 z planes: grids that together leave the device short of work), or, while
+ * more shots wait behind it (a backlog), within 3 times that (one launch of two
+ * mid-size grids beats two launches); with max_active_points > 0 if they
+ * stay within that many.  A shot always joins when none runs.  FD_EINVAL for a NULL
+ * server or a negative limit.  Thread-safe. */
 int fd_server_set_admission(void* srv, int64_t max_active_points);
 /* Allocator of the shots' blocks in the arena (the paper's global segment carved by
  * a linear-heap or a buddy allocator, Sec. 3.1): FD_ARENA_FIRST_FIT (the default:

@@ -619,9 +619,12 @@ static hipError_t forward_steps(const fd_grid* g, fd_run* run, int nsend, int ns
     } else {
       const RecPlane rp{run->rec_map, run->rec_k, row};
       // the one-thread-per-point kernel takes the row at the cost of one map load
-      // per thread of the plane (128^3, sponge: 12.6 -> 10.1 us per step)
+      // per thread of the plane (128^3, sponge: 12.6 -> 10.1 us per step); the
+      // 16-byte-lane kernel loads its map entries before it marches
+      const float* const arrs[4] = {up, u, un, run->vdt2};
       const bool in_kernel = run->rec_map && run->nrec > 0 && !nsend &&
-                             (receiver_plane_pays(geo) || point_kernel_pays(geo));
+                             (receiver_plane_pays(geo) || point_kernel_pays(geo) ||
+                              wide_takes_step(geo, arrs));
       if (nsend) e = launch_unpack(geo, u, recv, s);
       if (e == hipSuccess)
         e = forward_update(geo, c, up, u, un, run->vdt2, ex, ey, ez, sp_src, s,

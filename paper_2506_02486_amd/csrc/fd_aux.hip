@@ -213,41 +213,57 @@ __global__ void __launch_bounds__(BS) scatter_add_kernel(float* a, const int64_t
   if (r < n) atomicAdd(a + off[r], vals[r]);
 }
 
-// One thread per element of the padded box [-4,n+4)^3, one block row per
-// (j,k) line: interior from v, face halo from the periodic image, edges 0.
-// v0 points at interior (0,0,0) of the input, which has its own strides.
+// One thread per element of the padded box [-4,n+4)^3 in each of PREP_K planes,
+// one block row per (j, k-group): interior from v, face halo from the periodic image,
+// edges 0.  v0 points at interior (0,0,0) of the input, which has its own strides.
+// The PREP_K planes' loads are issued before any store, so that a thread keeps
+// several loads in flight (one per thread left the 224 MB read of a 384^3 model
+// latency-bound at about 3 TB/s).
+constexpr int PREP_K = 4;
+
+__device__ __forceinline__ int wrap_index(int a, int n) {
+  int c = a < 0 ? a + n : (a >= n ? a - n : a);
+  // a face halo wider than the axis wraps more than once
+  while (c < 0) c += n;
+  while (c >= n) c -= n;
+  return c;
+}
+
 __global__ void __launch_bounds__(BS) prep_vdt2_kernel(Geo g, const float* __restrict__ v0,
                                                        long long vsy, long long vsz,
                                                        float* __restrict__ q, double dt,
                                                        bool from_m) {
-  const int jj = blockIdx.y - 4;  // j in [-4, ny+4)
-  const int kk = blockIdx.z - 4;  // k in [-4, nz+4)
+  const int jj = blockIdx.y - 4;                  // j in [-4, ny+4)
+  const int k0 = (int)blockIdx.z * PREP_K - 4;    // first k of the group, in [-4, nz+4)
+  const int oj = (jj < 0) + (jj >= g.ny);
+  const int cj = wrap_index(jj, g.ny);
   for (int ii = (int)(blockIdx.x * BS + threadIdx.x) - 4; ii < g.nx + 4; ii += gridDim.x * BS) {
     const int oi = (ii < 0) + (ii >= g.nx);
-    const int oj = (jj < 0) + (jj >= g.ny);
-    const int ok = (kk < 0) + (kk >= g.nz);
-    float val = 0.f;
-    if (oi + oj + ok <= 1) {
-      const int si = ii < 0 ? ii + g.nx : (ii >= g.nx ? ii - g.nx : ii);
-      const int sj = jj < 0 ? jj + g.ny : (jj >= g.ny ? jj - g.ny : jj);
-      const int sk = kk < 0 ? kk + g.nz : (kk >= g.nz ? kk - g.nz : kk);
-      // a face halo wider than the axis wraps more than once
-      int ci = si, cj = sj, ck = sk;
-      while (ci < 0) ci += g.nx;
-      while (ci >= g.nx) ci -= g.nx;
-      while (cj < 0) cj += g.ny;
-      while (cj >= g.ny) cj -= g.ny;
-      while (ck < 0) ck += g.nz;
-      while (ck >= g.nz) ck -= g.nz;
-      const float vin = v0[(long long)ck * vsz + (long long)cj * vsy + ci];
-      if (from_m) {
-        val = (float)(dt * dt / (double)vin);
-      } else {
-        const double vv = (double)vin * dt;
-        val = (float)(vv * vv);
-      }
+    const int ci = wrap_index(ii, g.nx);
+    float vin[PREP_K];
+    bool use[PREP_K];
+#pragma unroll
+    for (int t = 0; t < PREP_K; ++t) {
+      const int kk = k0 + t;
+      const int ok = (kk < 0) + (kk >= g.nz);
+      use[t] = kk < g.nz + 4 && oi + oj + ok <= 1;
+      vin[t] = use[t] ? v0[(long long)wrap_index(kk, g.nz) * vsz + (long long)cj * vsy + ci] : 0.f;
     }
-    q[at(g, ii, jj, kk)] = val;
+#pragma unroll
+    for (int t = 0; t < PREP_K; ++t) {
+      const int kk = k0 + t;
+      if (kk >= g.nz + 4) break;
+      float val = 0.f;
+      if (use[t]) {
+        if (from_m) {
+          val = (float)(dt * dt / (double)vin[t]);
+        } else {
+          const double vv = (double)vin[t] * dt;
+          val = (float)(vv * vv);
+        }
+      }
+      q[at(g, ii, jj, kk)] = val;
+    }
   }
 }
 
@@ -267,24 +283,52 @@ __device__ __forceinline__ int wave_min(int v) {
   return v;
 }
 
+// max and min of v (as float bit patterns: positive floats order as integers) over
+// an nx x ny x nz view.  A block takes VMAX_LINES x-lines at a time (their row bases
+// are uniform: no per-element division), so that a thread has VMAX_LINES loads in
+// flight; lines past the last repeat the last one (no effect on max or min).  One
+// atomic pair per block.
+constexpr int VMAX_LINES = 8;
+
 __global__ void __launch_bounds__(BS) vmax_kernel(int nx, int ny, int nz,
                                                   const float* __restrict__ v0, long long vsy,
                                                   long long vsz, int32_t* out) {
   const long long nline = (long long)ny * nz;
   int mx = 0, mn = 0x7f800000;
-  for (long long line = blockIdx.x; line < nline; line += gridDim.x) {
-    const int j = (int)(line % ny);
-    const int k = (int)(line / ny);
-    const float* row = v0 + (long long)k * vsz + (long long)j * vsy;
+  for (long long l0 = (long long)blockIdx.x * VMAX_LINES; l0 < nline;
+       l0 += (long long)gridDim.x * VMAX_LINES) {
+    const float* row[VMAX_LINES];
+#pragma unroll
+    for (int u = 0; u < VMAX_LINES; ++u) {
+      const long long line = min(l0 + u, nline - 1);
+      const long long k = line / ny;
+      row[u] = v0 + k * vsz + (line - k * ny) * vsy;
+    }
     for (int i = threadIdx.x; i < nx; i += BS) {
-      const int bits = __float_as_int(row[i]);
-      mx = max(mx, bits);
-      mn = min(mn, bits);
+      int bits[VMAX_LINES];
+#pragma unroll
+      for (int u = 0; u < VMAX_LINES; ++u) bits[u] = __float_as_int(row[u][i]);
+#pragma unroll
+      for (int u = 0; u < VMAX_LINES; ++u) {
+        mx = max(mx, bits[u]);
+        mn = min(mn, bits[u]);
+      }
     }
   }
   mx = wave_max(mx);
   mn = wave_min(mn);
+  __shared__ int red[2][BS / 64];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    red[0][w] = mx;
+    red[1][w] = mn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < BS / 64; ++i) {
+      mx = max(mx, red[0][i]);
+      mn = min(mn, red[1][i]);
+    }
     atomicMax(out, mx);
     atomicMin(out + 1, mn);
   }
@@ -410,16 +454,17 @@ hipError_t launch_scatter_add(float* a, const int64_t* off, const float* vals, i
 hipError_t launch_prepare_vdt2(const Geo& g, const float* v, float* q, double dt, bool from_m,
                                hipStream_t s) {
   const unsigned bx = blocks_for(g.nx + 8, 64);
-  hipLaunchKernelGGL(prep_vdt2_kernel, dim3(bx, g.ny + 8, g.nz + 8), dim3(BS), 0, s, g,
-                     v + g.org, (long long)g.sy, (long long)g.sz, q, dt, from_m);
+  hipLaunchKernelGGL(prep_vdt2_kernel, dim3(bx, g.ny + 8, (g.nz + 8 + PREP_K - 1) / PREP_K),
+                     dim3(BS), 0, s, g, v + g.org, (long long)g.sy, (long long)g.sz, q, dt,
+                     from_m);
   return hipGetLastError();
 }
 
 hipError_t launch_prepare_vdt2_view(const Geo& g, const float* v, long long vsy, long long vsz,
                                     float* q, double dt, hipStream_t s) {
   const unsigned bx = blocks_for(g.nx + 8, 64);
-  hipLaunchKernelGGL(prep_vdt2_kernel, dim3(bx, g.ny + 8, g.nz + 8), dim3(BS), 0, s, g, v, vsy,
-                     vsz, q, dt, false);
+  hipLaunchKernelGGL(prep_vdt2_kernel, dim3(bx, g.ny + 8, (g.nz + 8 + PREP_K - 1) / PREP_K),
+                     dim3(BS), 0, s, g, v, vsy, vsz, q, dt, false);
   return hipGetLastError();
 }
 
@@ -442,7 +487,9 @@ hipError_t launch_vmax_view(int nx, int ny, int nz, const float* v, long long vs
   hipLaunchKernelGGL(vmax_init_kernel, dim3(1), dim3(64), 0, s, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(vmax_kernel, dim3(2048), dim3(BS), 0, s, nx, ny, nz, v, vsy, vsz, out);
+  const long long groups = ((long long)ny * nz + VMAX_LINES - 1) / VMAX_LINES;
+  const unsigned nb = (unsigned)std::min<long long>(std::max<long long>(groups, 1), 1024);
+  hipLaunchKernelGGL(vmax_kernel, dim3(nb), dim3(BS), 0, s, nx, ny, nz, v, vsy, vsz, out);
   return hipGetLastError();
 }
 

@@ -17,14 +17,17 @@
 //             step, each at its own step n (u^n in arr[n % 3]);
 //   draining: all steps done, traces copying to pinned host memory;
 //   done    : collected by shot_poll.
-// Activation (strict FIFO) needs a free slot and tile-table room, and fewer points
-// running than the fill (kFillPoints by default, else the caller's cap): a grid that
-// fills the device runs alone, smaller grids share it.
-// A batched step is one launch per kernel family over a tile table of every active
-// shot (grids of at least 7.5M points: 16-byte lanes, 128 x 32 tiles; smaller: one
-// float per lane, 64 x 32 tiles, which also writes the trace rows of shots whose
-// receivers share one plane), each family with the z chunk the launch model picks
-// for its shots, then one batched receiver launch for the other shots.
+// Activation (strict FIFO) needs a free slot and tile-table room, and the points of
+// the running shots and the new one within the fill (kFillPoints; kBacklogPoints
+// while more shots wait; else the caller's cap): a grid that fills the device runs
+// alone, grids that are small together share it.
+// A batched step advances every active shot by one launch: a lone shot by the
+// kernel its grid takes alone; several, if one of them is a grid of at least 7.5M
+// points, all by the 16-byte-lane kernel (128 x 32 tiles; up to kWideMulti grids with
+// their parameters in the kernel arguments, more through a tile table), else by the
+// one-float-per-lane kernel over a tile table (64 x 32 tiles).  Both write the trace
+// rows of shots whose receivers share one plane; one batched receiver launch takes
+// the others.
 // At most kEventEvery * kInflight steps are queued ahead of the device.  The arena,
 // compute and copy streams and all device memory are the caller's; the server only
 // carves.
@@ -75,6 +78,13 @@ constexpr int kAdmitStreams = 4;      // bound of the admission stream pool
 // 44.6 ms / 1.52x; 4.2M 0.996x / 40.9 ms / 1.42x; one shot at a time 0.995x / 41.0 ms /
 // 0.95x (plain: 39.8 ms).
 constexpr long long kFillPoints = 256LL * 128 * 32 * 8;
+// Under a backlog the running shots may hold up to this many points.  One launch of
+// two mid-size grids beats two launches (336 x 150 x 174 twice: 59.0 us against 2 x
+// 32.8; 256^3 twice: 90.6 against 2 x 47.8), of a large and a small grid it does not
+// (384^3 and 256^3: 222 us against 162 + 48).  Throughput at twice the plain loop's
+// rate on the 128..384^3 mix, with this cap on all steps: 8.4M points 1.006x, 16.8M
+// 1.009x, 25.2M 1.020x, 33.6M 1.016x, 67.1M 0.916x.
+constexpr long long kBacklogPoints = 3 * kFillPoints;
 
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
@@ -159,7 +169,8 @@ struct Shot {
   hipEvent_t ev = nullptr;    // end of the current admission phase
   float* stage = nullptr;     // pinned: max/min of v, then the tables to upload
   size_t stage_cap = 0;       // floats
-  bool wide = false;          // 16-byte-lane family
+  bool wide = false;          // a grid the 16-byte-lane kernel steps when alone
+  bool in_wide = false;       // stepped by the 16-byte-lane kernels now
   int plane_k = -1;           // receivers on one z plane (else -1)
   bool check_pending = false; // max(v) not yet checked for stability
   int abort_code = FD_OK;     // an active shot removed before its end ends with this
@@ -296,7 +307,7 @@ hipError_t admit_model(Server* S, Shot* s, double vdesign) {
   if (e == hipSuccess && d.nrec > 0)
     e = hipMemcpyAsync(shot_at(S, s, L.rec), hrec, 8 * (size_t)d.nrec, hipMemcpyHostToDevice,
                        s->as);
-  // receivers on one plane: the 64 x 32 kernels write their rows themselves
+  // receivers on one plane: the stencil kernels write their rows themselves
   s->plane_k = -1;
   if (d.nrec > 0) {
     int32_t* hmap = reinterpret_cast<int32_t*>(hrec + d.nrec);
@@ -322,8 +333,8 @@ hipError_t admit_model(Server* S, Shot* s, double vdesign) {
 hipError_t admit_start(Server* S, Shot* s, bool* whole) {
   const fd_shot_desc& d = s->d;
   int32_t* vm = reinterpret_cast<int32_t*>(shot_at(S, s, s->L.vm));
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_zero(shot_vol(S, s, i), s->L.elems, s->as);
+  // the three wavefields are adjacent in the block: one launch zeroes them
+  hipError_t e = launch_zero(shot_vol(S, s, 0), (long long)(shot_vol(S, s, 3) - shot_vol(S, s, 0)), s->as);
   if (e == hipSuccess)
     e = launch_vmax_view(d.nx, d.ny, d.nz, d.v_dev, d.v_ystride, d.v_zstride, vm, s->as);
   if (e == hipSuccess) e = hipMemcpyAsync(s->stage, vm, 8, hipMemcpyDeviceToHost, s->as);
@@ -360,8 +371,8 @@ void fill_slot(Server* S, Shot* s, int slot) {
   b.rec = reinterpret_cast<int64_t*>(shot_at(S, s, L.rec));
   b.traces = reinterpret_cast<float*>(shot_at(S, s, L.traces));
   b.nrec = s->d.nrec;
-  // the 16-byte-lane kernel leaves every receiver row to the batched receiver launch
-  const bool in_kernel = s->plane_k >= 0 && !s->wide;
+  // receivers on one plane: the batched stencil kernels write their rows
+  const bool in_kernel = s->plane_k >= 0;
   b.rk = in_kernel ? s->plane_k : -1;
   b.rmap = in_kernel ? reinterpret_cast<int32_t*>(shot_at(S, s, L.rmap)) : nullptr;
 }
@@ -380,13 +391,22 @@ long long points_in_use(Server* S) {
   return p;
 }
 
-// Whether the head staged shot may join the active ones now: while the running
-// shots hold fewer points than the fill (a shot always joins when none runs).
-bool activation_pays(Server* S) {
+// Whether shot s (the head of the staged shots) may join the active ones now (a shot
+// always joins when none runs).  Shots of one batched launch advance one step per
+// launch, in lockstep, so a grid that joins a smaller running one slows it to its
+// own pace: that trades the running shots' latency for throughput.  With a caller's
+// cap: when their points and its own stay within it.  By default: within the fill
+// (grids that together still leave the device short of work), or, while more shots
+// wait behind s (a backlog, where throughput decides), within kBacklogPoints.
+bool activation_pays(Server* S, const Shot* s) {
   bool any = false;
-  for (const Shot* s : S->slots) any = any || s != nullptr;
+  for (const Shot* r : S->slots) any = any || r != nullptr;
   if (!any) return true;
-  return points_in_use(S) < (S->max_points > 0 ? S->max_points : kFillPoints);
+  const long long after = points_in_use(S) + (long long)s->d.nx * s->d.ny * s->d.nz;
+  if (S->max_points > 0) return after <= S->max_points;
+  if (after <= kFillPoints) return true;
+  const bool backlog = S->prep.size() > 1 || !S->queue.empty();
+  return backlog && after <= kBacklogPoints;
 }
 
 // Rebuild and upload the tile tables, slot list and slot table.
@@ -412,26 +432,34 @@ hipError_t upload_tables(Server* S) {
   std::vector<int> nzs[2];
   long long least[2] = {0, 0};  // entries at one chunk per grid
   int fam[2] = {0, 0};
+  // the family of every active shot: where one of them is a grid for the 16-byte-lane
+  // kernel, all of them are stepped by it (one launch of all the grids: a smaller
+  // grid's tiles fill the launch of a larger one; every kernel gives the same bits),
+  // else by the one-float-per-lane kernels
+  bool any_wide = false;
+  for (const Shot* s : S->slots) any_wide = any_wide || (s && s->wide);
+  for (Shot* s : S->slots)
+    if (s) s->in_wide = any_wide;
   for (int f = 0; f < 2; ++f) S->direct[f] = nullptr;
   for (Shot* s : S->slots)
     if (s) {
-      ++fam[s->wide ? 1 : 0];
-      S->direct[s->wide ? 1 : 0] = s;
+      ++fam[s->in_wide ? 1 : 0];
+      S->direct[s->in_wide ? 1 : 0] = s;
     }
   S->multi.clear();
   if (fam[1] >= 2 && fam[1] <= kWideMulti)
     for (Shot* s : S->slots)
-      if (s && s->wide) S->multi.push_back(s);
+      if (s && s->in_wide) S->multi.push_back(s);
   for (int f = 0; f < 2; ++f) {
     if (fam[f] != 1) S->direct[f] = nullptr;
     S->direct_rows[f] = false;
     if (const Shot* s = S->direct[f])  // as fd_forward_run samples a lone grid
-      S->direct_rows[f] = f == 0 && s->plane_k >= 0 &&
-                          (point_kernel_pays(s->geo) || receiver_plane_pays(s->geo));
+      S->direct_rows[f] = s->plane_k >= 0 &&
+                          (f == 1 || point_kernel_pays(s->geo) || receiver_plane_pays(s->geo));
   }
   for (const Shot* s : S->slots)
-    if (s && s != S->direct[s->wide ? 1 : 0] && !(s->wide && !S->multi.empty())) {
-      const int f = s->wide ? 1 : 0;
+    if (s && s != S->direct[s->in_wide ? 1 : 0] && !(s->in_wide && !S->multi.empty())) {
+      const int f = s->in_wide ? 1 : 0;
       xy[f].push_back((long long)((s->d.nx + tws[f][0] - 1) / tws[f][0]) *
                       ((s->d.ny + tws[f][1] - 1) / tws[f][1]));
       nzs[f].push_back(s->d.nz);
@@ -450,11 +478,12 @@ hipError_t upload_tables(Server* S) {
   for (int f = 0; f < 2; ++f) {
     for (int slot = 0; slot < S->max_slots; ++slot) {
       Shot* s = S->slots[slot];
-      if (!s || (int)s->wide != f) continue;
-      // rows left to the batched receiver launch: all of the 16-byte-lane family,
-      // and of the other those whose step does not write them
-      const bool in_kernel = f == 0 && (s == S->direct[0] ? S->direct_rows[0]
-                                                          : S->shots_host[slot].rmap != nullptr);
+      if (!s || (int)s->in_wide != f) continue;
+      // rows left to the batched receiver launch: those of shots whose step does not
+      // write them (receivers not on one plane, or a lone small grid whose direct
+      // launch leaves them out)
+      const bool in_kernel = s == S->direct[f] ? S->direct_rows[f]
+                                               : S->shots_host[slot].rmap != nullptr;
       if (s->d.nrec > 0 && !in_kernel) {
         h_slots[na++] = slot;
         mr = std::max(mr, s->d.nrec);
@@ -510,9 +539,9 @@ hipError_t step_direct(Server* S, Shot* s, bool rows) {
   const float* up = arr[(n + 2) % 3];
   const float* u = arr[n % 3];
   float* un = arr[(n + 1) % 3];
-  if (s->wide)
+  if (s->in_wide)
     return launch_forward_wide(s->geo, s->coef, up, u, un, q, ex, ey, ez, &src, nullptr, nullptr,
-                               S->cs);
+                               S->cs, rows ? &rp : nullptr);
   if (point_kernel_pays(s->geo))
     return launch_step_point(s->geo, s->coef, up, u, un, q, ex, ey, ez, &src, rows ? &rp : nullptr,
                              S->cs);
@@ -540,6 +569,10 @@ hipError_t step_multi(Server* S) {
     x.ey = sp + s->d.nx;
     x.ez = sp + s->d.nx + s->d.ny;
     x.src = fd_source{s->d.src[0], s->d.src[1], s->d.src[2], s->w[k]};
+    if (s->plane_k >= 0)
+      x.rec = RecPlane{reinterpret_cast<const int32_t*>(shot_at(S, s, s->L.rmap)), s->plane_k,
+                       reinterpret_cast<float*>(shot_at(S, s, s->L.traces)) +
+                           (size_t)k * s->d.nrec};
   }
   return launch_wide_multi(w, n, S->cs);
 }
@@ -684,7 +717,7 @@ void progress(Server* S) {
         if (!S->slots[i]) { slot = i; break; }
       if (slot < 0) break;
       if (tiles_in_use(S) + s->L.tiles > kTileCap) break;
-      if (!activation_pays(S)) break;
+      if (!activation_pays(S, s)) break;
       size_t cap = 0;
       s->host_cap = (size_t)s->d.nt * (size_t)s->d.nrec;
       s->host = take_pinned(S, s->host_cap, &cap);

@@ -674,10 +674,10 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
                        float* un, const float* q, const float* ex, const float* ey,
                        const float* ez, const fd_source* src, hipStream_t s,
                        const RecPlane* rp) {
-  if (!(rp && rp->map) && forward_wide_tiles(g)) {
+  if (!(rp && rp->map && rp->add)) {
     const float* const arr[4] = {up, u, un, q};
-    if (wide_forward_fits(g, arr, nullptr))
-      return launch_forward_wide(g, c, up, u, un, q, ex, ey, ez, src, nullptr, nullptr, s);
+    if (wide_takes_step(g, arr))
+      return launch_forward_wide(g, c, up, u, un, q, ex, ey, ez, src, nullptr, nullptr, s, rp);
   }
   Params p = base_params(g, c, ex, ey, ez);
   if (rp && rp->map) {

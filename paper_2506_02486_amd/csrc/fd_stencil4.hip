@@ -69,6 +69,11 @@ struct P4 {
   float sw;
   const float* rin[2];  // XCH: -x / +x receive buffers
   float* sout[2];       // XCH: -x / +x send buffers
+  // FUSE, not XCH: receivers on plane rk (rk < 0: none): rmap[j * nx + i] is the receiver
+  // index of point (i, j, rk) or -1, and rrow[r] takes u^{n+1} there
+  const int32_t* rmap;
+  int rk;
+  float* rrow;
 };
 
 __device__ __forceinline__ int remap_block4(int bid, int nb) {
@@ -245,6 +250,23 @@ __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const 
     }
     tile_sponge = __syncthreads_or(any) != 0;
   }
+  // ---- receiver indices of the thread's points, if the chunk holds the receiver
+  // plane (loaded here, long before that plane is stored, so that its stores wait
+  // for nothing).  Not in the exchange form, whose receiver row is taken where the
+  // faces are packed.
+  const bool rec_chunk = FUSE && !XCH && p.rk >= kb && p.rk < ke;
+  int rix[RY][4];
+#pragma unroll
+  for (int r = 0; r < RY; ++r)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rix[r][e] = -1;
+  if (rec_chunk) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (x + e < nx && yr + r < ny) rix[r][e] = p.rmap[(long long)(yr + r) * nx + x + e];
+  }
   const Coef& c = p.c;
   auto iter = [&](auto pos, const int k) {
     constexpr int P = decltype(pos)::value;
@@ -324,6 +346,11 @@ __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const 
         }
         v4[e] = v;
       }
+      if (rec_chunk && k == p.rk) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (rix[r][e] >= 0) p.rrow[rix[r][e]] = v4[e];
+      }
       if (full[r]) {
         __builtin_nontemporal_store(v4, reinterpret_cast<f4*>(ok + cb[r]));
         if (XCH && sx_ptr)
@@ -396,6 +423,9 @@ __global__ void __launch_bounds__(LANES * TROWS) batched4_kernel(const BatchShot
   p.sw = a.w[t.x];
   p.rin[0] = p.rin[1] = nullptr;
   p.sout[0] = p.sout[1] = nullptr;
+  p.rmap = b.rmap;
+  p.rk = b.rmap ? b.rk : -1;
+  p.rrow = b.traces + (size_t)n * (size_t)b.nrec;
   stencil4_block<true, true, false>(p, t.y, t.z, t.w);
 }
 
@@ -454,6 +484,10 @@ bool wide_forward_fits(const Geo& g, const float* const arrays[4], const float* 
   return true;
 }
 
+bool wide_takes_step(const Geo& g, const float* const arrays[4]) {
+  return forward_wide_tiles(g) && wide_forward_fits(g, arrays, nullptr);
+}
+
 int batch4_tile_shape(int* tx, int* ty) {
   *tx = TX;
   *ty = TY;
@@ -502,6 +536,9 @@ hipError_t launch_wide_multi(const WideStep* steps, int n, hipStream_t s) {
     p.sj = w.src.j;
     p.sk = w.src.k;
     p.sw = w.src.w;
+    p.rmap = w.rec.map;
+    p.rk = w.rec.map ? w.rec.k : -1;
+    p.rrow = w.rec.row;
     const long long blocks =
         (long long)p.tiles_x * p.tiles_y * ((w.g.nz + p.kchunk - 1) / p.kchunk);
     if ((long long)A.start[i] + blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
@@ -523,7 +560,7 @@ void wide_forward_shape(const Geo& g, int out[4]) {
 hipError_t launch_forward_wide(const Geo& g, const Coef& c, const float* up, const float* u,
                                float* un, const float* q, const float* ex, const float* ey,
                                const float* ez, const fd_source* src, const float* const rin[2],
-                               float* const sout[2], hipStream_t s) {
+                               float* const sout[2], hipStream_t s, const RecPlane* rp) {
   P4 p{};
   p.g = g;
   p.c = c;
@@ -536,6 +573,12 @@ hipError_t launch_forward_wide(const Geo& g, const Coef& c, const float* up, con
   p.ez = ez;
   p.si = p.sj = p.sk = -1;
   p.sw = 0.f;
+  p.rk = -1;
+  if (rp && rp->map) {
+    p.rmap = rp->map;
+    p.rk = rp->k;
+    p.rrow = rp->row;
+  }
   if (src) {
     p.si = src->i;
     p.sj = src->j;
@@ -554,7 +597,7 @@ hipError_t launch_forward_wide(const Geo& g, const Coef& c, const float* up, con
     if (sponge) return launch4<true, true, true>(p, s);
     return launch4<false, true, true>(p, s);
   }
-  if (src) {
+  if (src || p.rmap) {
     if (sponge) return launch4<true, true, false>(p, s);
     return launch4<false, true, false>(p, s);
   }

@@ -34,11 +34,13 @@ class StreamPool {
   // A stream for new work, counted active until a partial synchronisation releases
   // it: an idle stream if there is one (reuse); else a new one while fewer than the
   // bound exist (lazy creation); else partial synchronisation -- of the active
-  // streams whose work has completed, the older half (rounded up) is synchronised
-  // and released to the idle list and the oldest of them handed out; if none has
-  // completed, the oldest active stream is synchronised (this call then waits for
-  // its work) and handed out.  *created and *synced (may be NULL) report what the
-  // call did.  Returns false only if a stream could not be created.
+  // streams whose work has completed, the older half (rounded up) is released to
+  // the idle list and the oldest of them handed out (done() has already shown their
+  // work complete: they need no wait); if none has completed, the oldest active
+  // stream is synchronised (this call then waits for its work) and handed out.
+  // *created and *synced (may be NULL) report what the call did: *synced is the
+  // number of streams released.  Returns false only if a stream could not be
+  // created.
   bool acquire(Stream* out, bool* created = nullptr, int* synced = nullptr) {
     if (created) *created = false;
     if (synced) *synced = 0;
@@ -85,7 +87,8 @@ class StreamPool {
 
  private:
   // Release the older half (rounded up) of the completed active streams; if none
-  // has completed, wait for the oldest.  Returns the number released.
+  // has completed, wait for the oldest (the only case that calls sync).  Returns
+  // the number released.
   int partial_sync() {
     std::vector<size_t> done;
     for (size_t i = 0; i < active_.size(); ++i)
@@ -93,6 +96,7 @@ class StreamPool {
     std::vector<size_t> take;
     if (done.empty()) {
       take.push_back(0);
+      ops_.sync(active_[0]);
     } else {
       const size_t half = (done.size() + 1) / 2;
       take.assign(done.begin(), done.begin() + half);
@@ -101,7 +105,6 @@ class StreamPool {
     size_t t = 0;
     for (size_t i = 0; i < active_.size(); ++i) {
       if (t < take.size() && take[t] == i) {
-        ops_.sync(active_[i]);
         idle_.push_back(active_[i]);
         ++t;
       } else {

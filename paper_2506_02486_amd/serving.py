@@ -87,9 +87,11 @@ class ShotServer:
             self.set_admission(max_active_points)
 
     def set_admission(self, max_active_points: int):
-        """Activation policy: 0 (default) the launch model's (a shot joins the running
-        ones when together they stream faster per point); > 0 join while the running
-        shots hold fewer points than this."""
+        """Activation policy (fd_server_set_admission): 0 (default) a shot joins the
+        running ones when their interior points and its own stay within 8,388,608
+        (one 128 x 32 tile of 8 planes per CU), or within 3 times that while more
+        shots wait behind it; > 0 when they stay within this many.  A shot always
+        joins when none runs."""
         check(lib().fd_server_set_admission(self.h, int(max_active_points)),
               "fd_server_set_admission")
 

@@ -221,7 +221,9 @@ static void test_pool() {
             CHECK(std::find(pool.active_streams().begin(), pool.active_streams().end(),
                             completed[i]) != pool.active_streams().end());
         }
-        CHECK(st.syncs - syncs_before == synced);
+        // only a wait for the oldest stream synchronises; completed ones are released
+        CHECK(st.syncs - syncs_before ==
+              (idle == 0 && (int)act.size() >= bound && completed.empty() ? 1 : 0));
         CHECK(pool.active() <= bound && pool.live() <= bound);
         CHECK(pool.active_streams().back() == s);
         st.done_at[s] = st.now + (long)(rng() % 20);  // new work on it

@@ -326,13 +326,23 @@ def test_resume_is_bitwise():
 
 @pytest.mark.parametrize("shape,tiles", [((64, 64, 64), 0), ((70, 33, 29), 1), ((70, 33, 29), 2),
                                          ((256, 100, 48), 0), ((128, 64, 40), 1),
-                                         ((70, 33, 29), 3)])
+                                         ((70, 33, 29), 3), ((70, 33, 29), 4),
+                                         ((256, 100, 48), 4), ((135, 37, 12), 4),
+                                         ((260, 200, 150), 0)])
 @pytest.mark.parametrize("faces", [0, 1, 2])
 def test_receiver_plane_in_stencil_matches_separate_record(shape, tiles, faces):
     """fd_forward_run with a receiver plane map (the stencil launch writes the trace
     row where no faces are packed) gives the bits of the separate receiver launch,
-    for Dirichlet runs (faces=0) and the loopback exchange in both forms."""
+    for Dirichlet runs (faces=0) and the loopback exchange in both forms; with tile
+    mode 4 and on the 7.8M-point grid the Dirichlet steps take the 16-byte-lane
+    kernel, which loads its receiver map entries before it marches."""
     nx, ny, nz = shape
+    if faces == 0 and (tiles == 4 or nx * ny * nz > 7_500_000):
+        api.set_tiles(tiles)
+        try:
+            assert api.step_kernel(api.Grid(nx, ny, nz), faces=False)["kernel"] == "wide_128x32"
+        finally:
+            api.set_tiles(0)
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
     rng = np.random.default_rng(11)
     pts = rng.choice(nx * ny, size=min(700, nx * ny), replace=False)
