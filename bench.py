@@ -229,7 +229,8 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
             if i < 8:
                 plain_tr[i] = tr
         span = time.monotonic() - base
-        return {"shots_per_s": nshots / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99)}
+        return {"shots_per_s": nshots / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
+                "lat": lat}
 
     def run_server(allocator):
         srv = serving.ShotServer(int(arena_gb * (1 << 30)), max_slots=max_slots,
@@ -265,7 +266,7 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
         lat = [(r[2][2] - t_arr[i]) / 1e9 for i, r in enumerate(res)]
         span = (max(r[2][2] for r in res) - min(t_arr)) / 1e9
         return {"shots_per_s": nshots / span, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99),
-                "batched_steps": steps, "all_ok": all(r[0] == 0 for r in res),
+                "lat": lat, "batched_steps": steps, "all_ok": all(r[0] == 0 for r in res),
                 "traces_bitwise_equal_first8": all(np.array_equal(res[i][1], plain_tr[i])
                                                    for i in plain_tr)}
 
@@ -295,6 +296,11 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
     # the server's gain over the plain loop against the larger run-to-run spread
     srv["gain_shots_per_s"] = round(srv["shots_per_s"] - p["shots_per_s"], 4)
     srv["spread_shots_per_s"] = max(p["shots_per_s_spread"], srv["shots_per_s_spread"])
+    # per shot, server latency minus plain-loop latency on the same arrivals (paired
+    # over the runs): robust where the latency distribution is sparse at its median
+    diff = [b - a for rp, rs in zip(runs_p, runs_s) for a, b in zip(rp["lat"], rs["lat"])]
+    srv["paired_latency_diff_median_s"] = round(float(np.median(diff)), 5)
+    srv["paired_latency_diff_mean_s"] = round(float(np.mean(diff)), 5)
     out = {
         "workload": f"{nshots} shots, grids uniform in [{lo},{hi}]^3 (seed 3), {nt} steps, "
                     f"sponge 16, Ricker 15 Hz, x-line receivers, Poisson arrivals at "
@@ -733,8 +739,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_serving:
         out["serving"] = serving_bench(nshots=args.shots, buddy=True)  # arrivals at 2x
-        # latency: arrivals at half the plain loop's service rate, a quarter of the shots
-        out["serving_latency"] = serving_bench(nshots=max(16, args.shots // 4), load=0.5)
+        # latency: arrivals at half the plain loop's service rate, half as many shots
+        out["serving_latency"] = serving_bench(nshots=max(16, args.shots // 2), load=0.5)
         # small shots, which leave the device part idle when run one at a time
         out["serving_small"] = serving_bench(nshots=args.shots, lo=48, hi=128)
     if not args.no_small:

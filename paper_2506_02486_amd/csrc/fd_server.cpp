@@ -167,6 +167,8 @@ struct Shot {
   // admission
   hipStream_t as = nullptr;   // pool stream of its admission work
   hipEvent_t ev = nullptr;    // end of the current admission phase
+  hipEvent_t mev = nullptr;   // end of the model's uploads, before the stability check
+                              // of the same phase (NULL: ev ends both)
   float* stage = nullptr;     // pinned: max/min of v, then the tables to upload
   size_t stage_cap = 0;       // floats
   bool wide = false;          // a grid the 16-byte-lane kernel steps when alone
@@ -282,8 +284,8 @@ int check_vmax(const Shot* s) {
 
 // The model on the shot's admission stream: vdt2 from the caller's velocity view, and
 // (host) sponge tables for the design velocity vdesign, receiver offsets and plane
-// map into the staging buffer, uploaded; then the admission event.
-hipError_t admit_model(Server* S, Shot* s, double vdesign) {
+// map into the staging buffer, uploaded; then event `end`.
+hipError_t admit_model(Server* S, Shot* s, double vdesign, hipEvent_t end) {
   const fd_shot_desc& d = s->d;
   const ShotLayout& L = s->L;
   const Geo geo = make_geo(&L.g);
@@ -317,7 +319,7 @@ hipError_t admit_model(Server* S, Shot* s, double vdesign) {
       e = hipMemcpyAsync(shot_at(S, s, L.rmap), hmap, 4 * (size_t)d.nx * (size_t)d.ny,
                          hipMemcpyHostToDevice, s->as);
   }
-  if (e == hipSuccess) e = hipEventRecord(s->ev, s->as);
+  if (e == hipSuccess) e = hipEventRecord(end, s->as);
   s->w.resize(d.nt);
   fd_ricker(s->w.data(), d.nt, 0, d.dt, d.f0, d.t0);
   s->wide = forward_wide_tiles(geo);
@@ -326,22 +328,34 @@ hipError_t admit_model(Server* S, Shot* s, double vdesign) {
 
 // The admission work that needs nothing from the host, on the shot's pool stream:
 // zero the three wavefields, reduce max(v) and min(v) into the block and copy them to
-// the staging buffer; when the sponge's design velocity is known without that
-// maximum (given, or no sponge), also the model (admit_model), so the shot can join
-// the step at once, its stability checked when the maximum arrives.  *whole tells
-// which.
+// the staging buffer.  When the sponge's design velocity is known without that
+// maximum (given, or no sponge), the model (admit_model) comes first, ending with
+// event mev, so that the shot can join the step as soon as its model has landed, its
+// stability checked when the maximum arrives (event ev); else the maximum comes
+// first (ev) and the host builds the model from it.  *whole tells which.
 hipError_t admit_start(Server* S, Shot* s, bool* whole) {
   const fd_shot_desc& d = s->d;
   int32_t* vm = reinterpret_cast<int32_t*>(shot_at(S, s, s->L.vm));
+  *whole = d.sponge_width == 0 || d.sponge_vmax > 0;
   // the three wavefields are adjacent in the block: one launch zeroes them
   hipError_t e = launch_zero(shot_vol(S, s, 0), (long long)(shot_vol(S, s, 3) - shot_vol(S, s, 0)), s->as);
+  if (e == hipSuccess && *whole) {
+    e = hipEventCreateWithFlags(&s->mev, hipEventDisableTiming);
+    if (e == hipSuccess) e = admit_model(S, s, d.sponge_width ? d.sponge_vmax : 0.0, s->mev);
+  }
   if (e == hipSuccess)
     e = launch_vmax_view(d.nx, d.ny, d.nz, d.v_dev, d.v_ystride, d.v_zstride, vm, s->as);
   if (e == hipSuccess) e = hipMemcpyAsync(s->stage, vm, 8, hipMemcpyDeviceToHost, s->as);
-  *whole = d.sponge_width == 0 || d.sponge_vmax > 0;
   if (e != hipSuccess) return e;
-  if (*whole) return admit_model(S, s, d.sponge_width ? d.sponge_vmax : 0.0);
   return hipEventRecord(s->ev, s->as);
+}
+
+// Destroy the admission events of a shot whose admission work has all landed (or
+// whose stream was synchronised).
+void drop_events(Shot* s) {
+  if (s->ev) (void)hipEventDestroy(s->ev);
+  if (s->mev) (void)hipEventDestroy(s->mev);
+  s->ev = s->mev = nullptr;
 }
 
 // Staging floats a shot needs (see admit_model).
@@ -585,8 +599,7 @@ void drop_prepared(Server* S, Shot* s) {
   s->has_block = false;
   give_pinned(S, s->stage, s->stage_cap);
   s->stage = nullptr;
-  if (s->ev) (void)hipEventDestroy(s->ev);
-  s->ev = nullptr;
+  drop_events(s);
 }
 
 void progress(Server* S) {
@@ -645,7 +658,7 @@ void progress(Server* S) {
         float vmax;
         memcpy(&vmax, &s->stage[0], 4);
         lk.unlock();
-        const hipError_t e = admit_model(S, s, (double)vmax);
+        const hipError_t e = admit_model(S, s, (double)vmax, s->ev);
         lk.lock();
         if (e == hipSuccess) {
           s->state = State::Issued;
@@ -660,8 +673,7 @@ void progress(Server* S) {
         s->state = State::Staged;
         give_pinned(S, s->stage, s->stage_cap);
         s->stage = nullptr;
-        (void)hipEventDestroy(s->ev);
-        s->ev = nullptr;
+        drop_events(s);
         ++i;
         continue;
       }
@@ -684,8 +696,7 @@ void progress(Server* S) {
       s->check_pending = false;
       give_pinned(S, s->stage, s->stage_cap);
       s->stage = nullptr;
-      (void)hipEventDestroy(s->ev);
-      s->ev = nullptr;
+      drop_events(s);
       if (rc == FD_OK) continue;
       // unstable (or failed): leave the step; its block is released once the steps
       // already queued with it have run
@@ -722,8 +733,9 @@ void progress(Server* S) {
       s->host_cap = (size_t)s->d.nt * (size_t)s->d.nrec;
       s->host = take_pinned(S, s->host_cap, &cap);
       if (!s->host) break;  // retried on the next pass
-      // admission work still running: the compute stream waits for it, not the host
-      if (s->ev && hipStreamWaitEvent(S->cs, s->ev, 0) != hipSuccess) {
+      // admission work still running: the compute stream waits for the model's part
+      // of it (the stability check may land later), not the host
+      if (s->ev && hipStreamWaitEvent(S->cs, s->mev ? s->mev : s->ev, 0) != hipSuccess) {
         give_pinned(S, s->host, cap);
         s->host = nullptr;
         break;
