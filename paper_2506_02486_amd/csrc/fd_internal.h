@@ -123,7 +123,7 @@ void set_kchunk_override(int kc);
 // (0: automatic, 1: always 64 x 32, 2: always 64 x 16).
 bool forward_small_tiles(const Geo& g);
 void set_tile_override(int mode);
-// Forward updates over g (no receiver rows added in the kernel) take the 16-byte-lane
+// Forward updates (and gradient passes) over g take the 16-byte-lane
 // kernel of fd_stencil4.hip: bandwidth-bound grids (more than kWideGridPoints
 // interior points), or as forced by set_tile_override (4: wherever it fits; 1, 2,
 // 3: never).
@@ -136,8 +136,9 @@ bool wide_forward_fits(const Geo& g, const float* const arrays[4], const float* 
 // tiles_x, tiles_y, kchunk, zchunks of the 16-byte-lane kernel's launch over g
 void wide_forward_shape(const Geo& g, int out[4]);
 // The forward step (launch_step, or with rin/sout launch_step_exchange) by the
-// 16-byte-lane kernel; same bits.  rp (optional, not rp->add): the kernel writes
-// the receiver row of un itself, as launch_step does.
+// 16-byte-lane kernel; same bits.  rp (optional): the kernel writes the receiver
+// row of un itself, or with rp->add adds the row scaled by vdt2 / (1+eta), as
+// launch_step does.
 hipError_t launch_forward_wide(const Geo& g, const Coef& c, const float* up, const float* u,
                                float* un, const float* q, const float* ex, const float* ey,
                                const float* ez, const fd_source* src, const float* const rin[2],
@@ -146,6 +147,11 @@ hipError_t launch_forward_wide(const Geo& g, const Coef& c, const float* up, con
 // Whether launch_step over g with these arrays (u_prev, u, u_next, vdt2) takes the
 // 16-byte-lane kernel.
 bool wide_takes_step(const Geo& g, const float* const arrays[4]);
+// launch_grad by the 16-byte-lane kernel (same bits); gq is read and written in
+// place.  The caller checks wide_forward_fits for {an1, u, gq, gq}.
+hipError_t launch_grad_wide(const Geo& g, const Coef& c, const float* u, const float* an1,
+                            float* gq, const float* ex, const float* ey, const float* ez,
+                            const fd_source* src, hipStream_t s);
 // Whether a z-marching step over g takes its receiver row in the stencil launch
 // (small grids, whose launches are short) rather than in a launch of its own.
 bool receiver_plane_pays(const Geo& g);

@@ -674,7 +674,7 @@ hipError_t launch_step(const Geo& g, const Coef& c, const float* up, const float
                        float* un, const float* q, const float* ex, const float* ey,
                        const float* ez, const fd_source* src, hipStream_t s,
                        const RecPlane* rp) {
-  if (!(rp && rp->map && rp->add)) {
+  {
     const float* const arr[4] = {up, u, un, q};
     if (wide_takes_step(g, arr))
       return launch_forward_wide(g, c, up, u, un, q, ex, ey, ez, src, nullptr, nullptr, s, rp);
@@ -750,6 +750,11 @@ hipError_t launch_adjoint(const Geo& g, const Coef& c, const float* ann, const f
 hipError_t launch_grad(const Geo& g, const Coef& c, const float* u, const float* an1,
                        float* gq, const float* ex, const float* ey, const float* ez,
                        const fd_source* src, hipStream_t s) {
+  if (forward_wide_tiles(g)) {
+    const float* const arr[4] = {an1, u, gq, gq};
+    if (wide_forward_fits(g, arr, nullptr))
+      return launch_grad_wide(g, c, u, an1, gq, ex, ey, ez, src, s);
+  }
   Params p = base_params(g, c, ex, ey, ez);
   p.f = u;
   p.fq = u;

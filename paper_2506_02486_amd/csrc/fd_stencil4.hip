@@ -74,6 +74,7 @@ struct P4 {
   const int32_t* rmap;
   int rk;
   float* rrow;
+  bool radd;  // rrow is a row to add at the receivers, scaled by vdt2 / (1+eta)
 };
 
 __device__ __forceinline__ int remap_block4(int bid, int nb) {
@@ -91,7 +92,7 @@ __device__ __forceinline__ f4 ld4_nt(const char* base, unsigned boff) {
 
 // The work of one block: tile (bx, by) of the x-y plane, z chunk bz, of the grid
 // and operands p describes.
-template <bool SPONGE, bool FUSE, bool XCH>
+template <bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
 __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const int by,
                                                const int bz) {
   __shared__ __attribute__((aligned(16))) float sm[2][LY * LX];
@@ -254,18 +255,30 @@ __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const 
   // plane (loaded here, long before that plane is stored, so that its stores wait
   // for nothing).  Not in the exchange form, whose receiver row is taken where the
   // faces are packed.
-  const bool rec_chunk = FUSE && !XCH && p.rk >= kb && p.rk < ke;
+  const bool rec_chunk = FUSE && !XCH && !GRAD && p.rk >= kb && p.rk < ke;
   int rix[RY][4];
 #pragma unroll
   for (int r = 0; r < RY; ++r)
 #pragma unroll
     for (int e = 0; e < 4; ++e) rix[r][e] = -1;
+  float rval[RY][4];  // radd: the row values to add there
+#pragma unroll
+  for (int r = 0; r < RY; ++r)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rval[r][e] = 0.f;
   if (rec_chunk) {
 #pragma unroll
     for (int r = 0; r < RY; ++r)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         if (x + e < nx && yr + r < ny) rix[r][e] = p.rmap[(long long)(yr + r) * nx + x + e];
+    if (p.radd) {
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (rix[r][e] >= 0) rval[r][e] = p.rrow[rix[r][e]];
+    }
   }
   const Coef& c = p.c;
   auto iter = [&](auto pos, const int k) {
@@ -337,16 +350,32 @@ __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const 
           lap += c.cz[m] * (zq[(C + m) % 10][r][e] + zq[(C + 10 - m) % 10][r][e]);
         float eta = 0.f;
         if (damped) eta = exc[e] + eyr[r] + ezk;
-        float v = 2.f * u0 - ua[e] + ub[e] * lap;
-        if (damped && eta != 0.f) v = (v + eta * ua[e]) * __builtin_amdgcn_rcpf(1.f + eta);
-        if (FUSE && src_plane) {
-          // no contraction: rounds exactly as inject_source
+        float v;
+        if constexpr (GRAD) {
+          // g += D a (L u + f): ua is a^{n+1}, ub the accumulator (as the gradient
+          // mode of the marching kernel, same rounding)
+          float src = 0.f;
+          if (src_plane && x + e == p.si && yr + r == p.sj) src = p.sw;
+          float D = 1.f;
+          if (damped && eta != 0.f) D = __builtin_amdgcn_rcpf(1.f + eta);
+          v = ub[e] + D * ua[e] * (lap + src);
+        } else {
+          v = 2.f * u0 - ua[e] + ub[e] * lap;
+          if (damped && eta != 0.f) v = (v + eta * ua[e]) * __builtin_amdgcn_rcpf(1.f + eta);
+          if (FUSE && src_plane) {
+            // no contraction: rounds exactly as inject_source
 #pragma clang fp contract(off)
-          if (x + e == p.si && yr + r == p.sj) v += ub[e] * p.sw / (1.f + eta);
+            if (x + e == p.si && yr + r == p.sj) v += ub[e] * p.sw / (1.f + eta);
+          }
+          if (rec_chunk && p.radd && k == p.rk && rix[r][e] >= 0) {
+            // rounds as fd_scatter_add_scaled: the row value times vdt2 / (1+eta)
+#pragma clang fp contract(off)
+            v += rval[r][e] * (ub[e] / (1.f + eta));
+          }
         }
         v4[e] = v;
       }
-      if (rec_chunk && k == p.rk) {
+      if (rec_chunk && !p.radd && k == p.rk) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           if (rix[r][e] >= 0) p.rrow[rix[r][e]] = v4[e];
@@ -387,12 +416,12 @@ __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const 
   }
 }
 
-template <bool SPONGE, bool FUSE, bool XCH>
+template <bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
 __global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
   const int logical = remap_block4(blockIdx.x, gridDim.x);
   const int bx = logical % p.tiles_x;
   const int rest = logical / p.tiles_x;
-  stencil4_block<SPONGE, FUSE, XCH>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
+  stencil4_block<SPONGE, FUSE, XCH, GRAD>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
 }
 
 // Many grids in one launch: block b runs tile tiles[remap(b)] = (slot, bx, by, bz) of
@@ -450,7 +479,7 @@ __global__ void __launch_bounds__(LANES * TROWS) multi4_kernel(MultiArgs A) {
   stencil4_block<true, true, false>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
 }
 
-template <bool SPONGE, bool FUSE, bool XCH>
+template <bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
 hipError_t launch4(P4 p, hipStream_t st) {
   // one block per CU: its 8 waves take a CU's share of 16 (more than 128 VGPRs)
   const LaunchShape sh = stencil_shape(p.g, TX, TY, 16);
@@ -459,7 +488,7 @@ hipError_t launch4(P4 p, hipStream_t st) {
   p.kchunk = sh.kchunk;
   const long long nb = (long long)sh.tiles_x * sh.tiles_y * sh.zchunks;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((stencil4_kernel<SPONGE, FUSE, XCH>), dim3((unsigned)nb), dim3(LANES, TROWS),
+  hipLaunchKernelGGL((stencil4_kernel<SPONGE, FUSE, XCH, GRAD>), dim3((unsigned)nb), dim3(LANES, TROWS),
                      0, st, p);
   return hipGetLastError();
 }
@@ -549,6 +578,32 @@ hipError_t launch_wide_multi(const WideStep* steps, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_grad_wide(const Geo& g, const Coef& c, const float* u, const float* an1,
+                            float* gq, const float* ex, const float* ey, const float* ez,
+                            const fd_source* src, hipStream_t s) {
+  P4 p{};
+  p.g = g;
+  p.c = c;
+  p.u = u;
+  p.up = an1;
+  p.q = gq;
+  p.un = gq;
+  p.ex = ex;
+  p.ey = ey;
+  p.ez = ez;
+  p.si = p.sj = p.sk = -1;
+  p.sw = 0.f;
+  p.rk = -1;
+  if (src) {
+    p.si = src->i;
+    p.sj = src->j;
+    p.sk = src->k;
+    p.sw = src->w;
+  }
+  if (ex) return launch4<true, false, false, true>(p, s);
+  return launch4<false, false, false, true>(p, s);
+}
+
 void wide_forward_shape(const Geo& g, int out[4]) {
   const LaunchShape sh = stencil_shape(g, TX, TY, 16);
   out[0] = sh.tiles_x;
@@ -578,6 +633,7 @@ hipError_t launch_forward_wide(const Geo& g, const Coef& c, const float* up, con
     p.rmap = rp->map;
     p.rk = rp->k;
     p.rrow = rp->row;
+    p.radd = rp->add;
   }
   if (src) {
     p.si = src->i;

@@ -34,7 +34,10 @@ import torch
 from . import api
 
 # grids up to this many points run short, latency-bound launches: there the receiver
-# residual is added in the adjoint update's own launch (fd_adjoint_step_scaled_res)
+# residual is added in the adjoint update's own launch (fd_adjoint_step_scaled_res),
+# as it is on grids the 16-byte-lane kernel steps (it loads the residual row before it
+# marches); the marching kernel of one float per lane in between would wait for its
+# map lookup, and a separate launch costs less there
 SMALL_GRID_POINTS = 1 << 20
 
 
@@ -192,7 +195,10 @@ class FWIProblem:
     @property
     def _inject_in_step(self) -> bool:
         g = self.grid
-        return self.rec_plane is not None and g.nx * g.ny * g.nz <= SMALL_GRID_POINTS
+        if self.rec_plane is None:
+            return False
+        return (g.nx * g.ny * g.nz <= SMALL_GRID_POINTS
+                or api.step_kernel(g)["kernel"] == "wide_128x32")
 
     def _backward_scaled(self, res: torch.Tensor, want_grad_w: bool):
         g, nt = self.grid, self.nt
@@ -202,15 +208,16 @@ class FWIProblem:
         gb = g.zeros(self.device)
         seg = self._segment_buffers()
         grad_w = torch.zeros(nt, dtype=torch.float32, device=self.device) if want_grad_w else None
+        in_step = self._inject_in_step
         for j in range(self._segments() - 1, -1, -1):
             s, e, seg = self._recompute(j, seg)
             for n in range(e - 1, s - 1, -1):
                 if grad_w is not None:
                     api.record_receivers(g, B, self.src_off, grad_w[n:n + 1])
                 # the residual of step n-1 enters at the receivers: in the update's own
-                # launch when they share one plane of a small grid (on bandwidth-bound
-                # grids the separate launch costs less than the lookup in the update)
-                inj = (self.rec_plane, res[n - 1]) if n >= 1 and self._inject_in_step else None
+                # launch when they share one plane (see SMALL_GRID_POINTS), else by a
+                # separate launch
+                inj = (self.rec_plane, res[n - 1]) if n >= 1 and in_step else None
                 api.adjoint_step_scaled(g, A, B, A, self.vdt2, self.sponge, u_n=seg[n - s],
                                         g_b=gb, src=(self.src, float(self.w[n])), res=inj)
                 if n >= 1 and inj is None:

@@ -55,9 +55,20 @@ def _fields(g, seeds, periodic):
     return out
 
 
+@pytest.mark.parametrize("tiles", [0, 4])
 @pytest.mark.parametrize("periodic", [False, True])
 @pytest.mark.parametrize("shape", [(70, 37, 29), (64, 16, 33)])
-def test_adjoint_step_parity(shape, periodic):
+def test_adjoint_step_parity(shape, periodic, tiles):
+    """fd_adjoint_step with its gradient pass (damped: D from the sponge) against the
+    oracle's transpose step; tiles 4 runs the gradient pass on the 16-byte-lane kernel."""
+    api.set_tiles(tiles)
+    try:
+        _adjoint_step_parity(shape, periodic)
+    finally:
+        api.set_tiles(0)
+
+
+def _adjoint_step_parity(shape, periodic):
     nx, ny, nz = shape
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
     sim = api.Simulation(v, sponge_width=6)
@@ -242,13 +253,10 @@ def test_fwi_gradient_matches_oracle_and_central_differences():
     assert e_gfd <= 2e-2
 
 
-@pytest.mark.parametrize("tiles", [0, 1, 2, 3])
-def test_residual_plane_in_adjoint_launch_matches_scatter(tiles):
-    """fd_adjoint_step_scaled_res (the residual row added at receivers on one plane in
-    the update's launch) gives the bits of fd_adjoint_step_scaled followed by
-    fd_scatter_add_scaled, receivers inside and outside the sponge: automatic shape (this
-    small grid takes the one-thread-per-point kernel), both marching tile shapes, and the
-    point kernel forced."""
+def _scaled_step_with_residual(tiles, fused):
+    """One fd_adjoint_step_scaled with its gradient on a 70 x 37 x 29 grid (sponge 6)
+    and a residual row at 400 receivers on the plane k = 26: added in the update's
+    launch (fused) or by fd_scatter_add_scaled; returns (b_out, g_b)."""
     nx, ny, nz = 70, 37, 29
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
     sim = api.Simulation(v, sponge_width=6)
@@ -263,20 +271,42 @@ def test_residual_plane_in_adjoint_launch_matches_scatter(tiles):
     row = torch.from_numpy(rng.standard_normal(400).astype(np.float32)).cuda()
     api.set_tiles(tiles)
     try:
-        outs = []
-        for fused in (False, True):
-            out, gb = g.zeros(), g.zeros()
-            if fused:
-                api.adjoint_step_scaled(g, b2, b1, out, sim.vdt2, sim.sponge, u_n=u, g_b=gb,
-                                        src=((5, 6, 7), 2.0), res=(plane, row))
-            else:
-                api.adjoint_step_scaled(g, b2, b1, out, sim.vdt2, sim.sponge, u_n=u, g_b=gb,
-                                        src=((5, 6, 7), 2.0))
-                api.scatter_add_scaled(g, out, off, row, sim.vdt2, sim.sponge)
-            outs.append((out, gb))
-        assert same_bits(outs[0][0], outs[1][0]) and same_bits(outs[0][1], outs[1][1])
+        out, gb = g.zeros(), g.zeros()
+        if fused:
+            api.adjoint_step_scaled(g, b2, b1, out, sim.vdt2, sim.sponge, u_n=u, g_b=gb,
+                                    src=((5, 6, 7), 2.0), res=(plane, row))
+        else:
+            api.adjoint_step_scaled(g, b2, b1, out, sim.vdt2, sim.sponge, u_n=u, g_b=gb,
+                                    src=((5, 6, 7), 2.0))
+            api.scatter_add_scaled(g, out, off, row, sim.vdt2, sim.sponge)
+        torch.cuda.synchronize()
+        return out, gb
     finally:
         api.set_tiles(0)
+
+
+@pytest.mark.parametrize("tiles", [0, 1, 2, 3, 4])
+def test_residual_plane_in_adjoint_launch_matches_scatter(tiles):
+    """fd_adjoint_step_scaled_res (the residual row added at receivers on one plane in
+    the update's launch) gives the bits of fd_adjoint_step_scaled followed by
+    fd_scatter_add_scaled, receivers inside and outside the sponge: automatic shape (this
+    small grid takes the one-thread-per-point kernel), both marching tile shapes, the
+    point kernel forced, and the 16-byte-lane kernel forced (the update with the row
+    values loaded before the march, and the gradient pass)."""
+    a = _scaled_step_with_residual(tiles, False)
+    b = _scaled_step_with_residual(tiles, True)
+    assert same_bits(a[0], b[0]) and same_bits(a[1], b[1])
+
+
+def test_scaled_adjoint_and_gradient_bits_do_not_depend_on_the_kernel():
+    """The scaled adjoint update with its residual row and the gradient pass give the
+    same bits whichever kernel runs them: the one-thread-per-point kernel, the marching
+    kernels of one float per lane (64 x 32 and 64 x 16 tiles) and the 16-byte-lane
+    kernel (128 x 32 tiles)."""
+    ref = _scaled_step_with_residual(3, True)
+    for tiles in (1, 2, 4):
+        got = _scaled_step_with_residual(tiles, True)
+        assert same_bits(got[0], ref[0]) and same_bits(got[1], ref[1]), tiles
 
 
 def test_fwi_checkpoint_interval_does_not_change_the_gradient():
