@@ -108,6 +108,9 @@ def lib():
         L.ora_fwi_gradient.argtypes = [i32, i32, i32, f64, f64, f64, _dp, f64, i32, _dpn,
                                        i32, i32, i32, _dpn, _dpn, _dpn, i32, i32, _ipn,
                                        _dp, _dpn, _dpn, _dpn, _dpn]
+        vp = C.c_void_p
+        L.ora_block_gemm.restype = None
+        L.ora_block_gemm.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32]
         L.ora_threads.restype = i32
         L.ora_threads.argtypes = []
         L.ora_set_threads.restype = None
@@ -317,3 +320,65 @@ def fwi_gradient(v: np.ndarray | None, nt: int, dt: float, obs: np.ndarray, src,
     if J < 0:
         raise MemoryError("oracle gradient: out of memory")
     return {"J": J, "traces": traces, "g_vdt2": g, "grad_m": gm, "grad_w": gw}
+
+
+# ------------------------------------------------- Cannon's matrix multiply (Sec. 4.4)
+
+def _rows(x: np.ndarray, name: str) -> int:
+    """Leading dimension (elements) of a 2-D FP64 array with unit column stride."""
+    if x.dtype != np.float64 or x.ndim != 2:
+        raise ValueError(f"{name}: a 2-D float64 array is needed")
+    if x.size == 0:
+        return max(x.shape[1], 1)
+    if x.shape[1] > 1 and x.strides[1] != 8:
+        raise ValueError(f"{name}: unit column stride is needed")
+    return x.strides[0] // 8 if x.shape[0] > 1 else max(x.shape[1], 1)
+
+
+def block_gemm(a: np.ndarray, b: np.ndarray, c: np.ndarray | None = None,
+               accumulate: bool = False) -> np.ndarray:
+    """The local block product of one Cannon step, by its definition (ora_block_gemm):
+    c = (c if accumulate else 0) + a @ b in FP64, each element summed over the inner
+    index in increasing order.  ``a`` (m, k), ``b`` (k, n), ``c`` (m, n) may be row
+    views of larger arrays; ``c`` is written in place and returned."""
+    m, k = a.shape
+    k2, n = b.shape
+    if k != k2:
+        raise ValueError("block_gemm: inner dimensions differ")
+    if c is None:
+        c = np.zeros((m, n))
+        accumulate = False
+    if c.shape != (m, n):
+        raise ValueError("block_gemm: c has the wrong shape")
+    lib().ora_block_gemm(m, n, k, a.ctypes.data, _rows(a, "a"), b.ctypes.data, _rows(b, "b"),
+                         c.ctypes.data, _rows(c, "c"), 1 if accumulate else 0)
+    return c
+
+
+def cannon_order(rank: int, P: int) -> list:
+    """The B row stripes rank ``rank`` multiplies with, in step order: it starts with
+    its own stripe and receives its neighbour's after every step (a ring)."""
+    return [(rank + s) % P for s in range(P)]
+
+
+def cannon(A: np.ndarray, B: np.ndarray, P: int) -> np.ndarray:
+    """C = A @ B by Cannon's algorithm on P simulated ranks (Sec. 4.4): with Ns = N/P,
+    rank r holds the row stripes A_r, B_r and C_r (Ns x N); at each of its P steps it
+    adds A_r[:, q*Ns:(q+1)*Ns] @ B_q (a product of N * Ns * Ns multiply-adds) to C_r,
+    where B_q is the stripe it holds, then passes that stripe around the ring."""
+    N = A.shape[0]
+    if A.shape != (N, N) or B.shape != (N, N) or P < 1 or N % P:
+        raise ValueError("cannon: square N x N operands with N divisible by P are needed")
+    ns = N // P
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    C = np.zeros((N, N))
+    held = list(range(P))  # the B stripe each rank holds
+    for _ in range(P):
+        for r in range(P):
+            q = held[r]
+            block_gemm(A[r * ns:(r + 1) * ns, q * ns:(q + 1) * ns], B[q * ns:(q + 1) * ns, :],
+                       C[r * ns:(r + 1) * ns, :], accumulate=True)
+        held = [held[(r + 1) % P] for r in range(P)]  # each rank receives from r + 1
+    return C
+

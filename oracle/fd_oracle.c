@@ -18,6 +18,9 @@
  * ((k+4)*(ny+8) + (j+4))*(nx+8) + (i+4).  Interior-only arrays handed in or
  * out are C-ordered (nz, ny, nx).
  *
+ * The library also holds the local block product of Cannon's matrix multiply
+ * (Sec. 4.4), ora_block_gemm, the one dense contraction in the paper.
+ *
  * Build: gcc -O2 -fopenmp -shared -fPIC fd_oracle.c -lm (no -ffast-math).
  */
 #include <math.h>
@@ -437,6 +440,26 @@ double ora_fwi_gradient(int nx, int ny, int nz, double dx, double dy, double dz,
   free(vdt2); free(states); free(zero); free(res); free(g);
   for (int t = 0; t < 3; ++t) free(A[t]);
   return J;
+}
+
+/* ---------------------------------------------------------------------------
+ * Cannon's matrix multiply (Sec. 4.4): each of P ranks holds a stripe of Ns = N/P
+ * rows and performs P products of N * Ns * Ns multiply-adds; the product of one
+ * step is a plain block product.  Here, by its definition, in FP64:
+ *     C[i][j] = (accumulate ? C[i][j] : 0) + sum over p = 0 .. k-1 of A[i][p] B[p][j]
+ * for 0 <= i < m, 0 <= j < n; row-major operands with leading dimensions lda, ldb,
+ * ldc (elements between consecutive rows).  The sum runs over p in increasing
+ * order, starting from the old C[i][j] (or 0).  Rows of C are independent (one
+ * thread per row block; the arithmetic of an element never depends on it). */
+void ora_block_gemm(int64_t m, int64_t n, int64_t k, const double* a, int64_t lda,
+                    const double* b, int64_t ldb, double* c, int64_t ldc, int accumulate) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double s = accumulate ? c[i * ldc + j] : 0.0;
+      for (int64_t p = 0; p < k; ++p) s += a[i * lda + p] * b[p * ldb + j];
+      c[i * ldc + j] = s;
+    }
 }
 
 /* Sets the OpenMP threads of later parallel regions (n >= 1). */

@@ -15,7 +15,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "fd_oracle.c")
-PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_adjoint.py"]
+PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_adjoint.py", "tests/test_oracle_gemm.py"]
 
 # (what the mistake is, exact text in the oracle, replacement)
 MUTATIONS = [
@@ -42,6 +42,15 @@ MUTATIONS = [
      "w[n] = (1.0 - a) * exp(-a);"),
     ("gradient sign", "grad_m_out[o] = -g[q] * vdt2[q] * vdt2[q] / (dt * dt);",
      "grad_m_out[o] = g[q] * vdt2[q] * vdt2[q] / (dt * dt);"),
+    ("gemm: inner index from 1",
+     "for (int64_t p = 0; p < k; ++p) s += a[i * lda + p] * b[p * ldb + j];",
+     "for (int64_t p = 1; p < k; ++p) s += a[i * lda + p] * b[p * ldb + j];"),
+    ("gemm: B transposed", "s += a[i * lda + p] * b[p * ldb + j];",
+     "s += a[i * lda + p] * b[j * ldb + p];"),
+    ("gemm: accumulate ignored", "double s = accumulate ? c[i * ldc + j] : 0.0;",
+     "double s = 0.0;"),
+    ("gemm: row stride of A taken as k", "s += a[i * lda + p] * b[p * ldb + j];",
+     "s += a[i * k + p] * b[p * ldb + j];"),
     ("point step: x and z spacing swapped",
      "const double id2[3] = {1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz)};",
      "const double id2[3] = {1.0 / (dz * dz), 1.0 / (dy * dy), 1.0 / (dx * dx)};"),
