@@ -21,8 +21,10 @@ u^{n-1} and vdt2 read once, u^{n+1} written once; plus 4 B per x-face point read
 
 Further legs in the same line (each skippable): ``serving`` (the continuous-batching
 shot server against the plain per-shot loop), ``small`` (64^3 parity configuration),
-``large`` (1024 x 1024 x 512, with its own roofline and CPU baseline), ``fwi`` (the
-256^3 FWI gradient, with its roofline against the gradient's algorithmic bytes).
+``large`` (1024 x 1024 x 512, with its own roofline and CPU baseline), ``cannon`` (one
+rank's block products of Cannon's matrix multiply, N = 30240, P = 8, against the FP64
+matrix peak), ``fwi`` (the 256^3 FWI gradient, with its roofline against the
+gradient's algorithmic bytes).
 """
 from __future__ import annotations
 
@@ -555,6 +557,80 @@ def fwi_bench(n=256, nt=1000, every=32):
     return out
 
 
+PEAK_FP64_MFMA_TFLOPS = 78.6
+
+
+def cannon_bench(N=30240, P=8, reps=3, cpu=True, cpu_cols=32):
+    """Cannon's matrix multiply (Sec. 4.4), the local work of one rank: N = 30240,
+    P = 8 ranks (Ns = 3780), rank 0's P block products C_0 += A_0[:, q-block] @ B_q
+    (3780 x 30240 x 3780 each, FP64 on the matrix cores) with every B stripe resident
+    (the ring shift between ranks needs other GPUs).  Seeded normal operands made on
+    the device.  ``value`` is TFLOP/s over `reps` timed rank passes after one warm-up;
+    the roofline rates the block-product kernel against the FP64 matrix peak; the CPU
+    baseline times the FP64 oracle on `cpu_cols` columns of C_0 over all P steps."""
+    import numpy as np
+    import torch
+
+    from paper_2506_02486_amd import api
+
+    ns = N // P
+    log(f"cannon: N={N}, P={P}, rank 0's {P} products of {ns} x {N} x {ns}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    A0 = torch.randn((ns, N), generator=g, device="cuda", dtype=torch.float64)
+    B = torch.randn((N, N), generator=g, device="cuda", dtype=torch.float64)
+    C0 = torch.zeros((ns, N), device="cuda", dtype=torch.float64)
+    stream = torch.cuda.current_stream()
+    api.cannon_rank(A0, B, C0, 0, P, stream)  # warm-up
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        api.cannon_rank(A0, B, C0, 0, P, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_launch = e0.elapsed_time(e1) / (reps * P)
+    flops_launch = 2.0 * ns * N * ns
+    tflops = flops_launch / ms_launch / 1e9
+    finite = bool(torch.isfinite(C0).all().item())
+    out = {"workload": f"Cannon's matrix multiply, N={N}, P={P}: one rank's {P} local block "
+                       f"products C_r += A_r[:, q-block] @ B_q ({ns} x {N} x {ns}, FP64), "
+                       f"all B stripes resident, seeded normal operands",
+           "value": round(tflops, 2), "unit": "TFLOP/s", "dtype": "f64",
+           "ms_per_rank_pass": round(ms_launch * P, 3),
+           "roofline": {"bound": "mfma", "kernel": "gemm_f64_kernel (128 x 128 tiles, "
+                                                   "v_mfma_f64_16x16x4f64)",
+                        "achieved": round(tflops, 2), "peak": PEAK_FP64_MFMA_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP64_MFMA_TFLOPS, 4),
+                        "traffic": None, "algorithmic_flops_per_launch": flops_launch,
+                        "avg_launch_ms": round(ms_launch, 4)},
+           "finite": finite}
+    if cpu:
+        import oracle
+        log(f"cannon: CPU oracle on {cpu_cols} columns of C_0")
+        cols = np.linspace(0, N - 1, cpu_cols).astype(np.int64)
+        a_h = A0.cpu().numpy()
+        bcols = np.ascontiguousarray(B[:, torch.from_numpy(cols).cuda()].cpu().numpy())
+        t0 = time.perf_counter()
+        got = np.zeros((ns, cpu_cols))
+        for q in api.cannon_order(0, P):
+            oracle.block_gemm(a_h[:, q * ns:(q + 1) * ns], bcols[q * ns:(q + 1) * ns], got,
+                              accumulate=True)
+        el = time.perf_counter() - t0
+        ref = C0[:, torch.from_numpy(cols).cuda()].cpu().numpy() / (reps + 1)
+        out["cpu_baseline"] = {
+            "value": round(2.0 * ns * N * cpu_cols / el / 1e12, 6), "unit": "TFLOP/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"FP64 oracle (plain loops), {cpu_cols} columns of C_0 over the {P} "
+                      f"steps ({2.0 * ns * N * cpu_cols / 1e9:.2f} GFLOP) in {el:.2f} s"}
+        # the GPU ran the rank pass reps + 1 times into C_0: compare the mean
+        out["sampled_columns_rel_err"] = float(np.linalg.norm(ref - got) / np.linalg.norm(got))
+    del A0, B, C0
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -575,6 +651,8 @@ def main():
                     help="optional .npy path to cache the 1024x1024x512 velocity model")
     ap.add_argument("--no-fwi", action="store_true", help="skip the 256^3 FWI gradient legs")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^3 small-grid leg")
+    ap.add_argument("--no-cannon", action="store_true",
+                    help="skip the Cannon block-product leg (N=30240, P=8)")
     ap.add_argument("--shots", type=int, default=256, help="shots in the serving stream")
     ap.add_argument("--vcache", default=None,
                     help="optional .npy path to cache the generated velocity model")
@@ -749,6 +827,8 @@ def main():
     if not args.no_large:
         out["large"] = large_bench(steps=args.large_steps, cpu=not args.no_cpu_baseline,
                                    vcache=args.vcache_large)
+    if not args.no_cannon:
+        out["cannon"] = cannon_bench(cpu=not args.no_cpu_baseline)
     if not args.no_fwi:
         out["fwi"] = fwi_bench()
         # the same gradient keeping all 1000 states in HBM (89 GB): no recompute

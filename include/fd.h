@@ -588,6 +588,25 @@ int fd_server_shutdown(void* srv);
 /* Shut down (as above) and free the server; its shot ids become invalid. */
 int fd_server_destroy(void* srv);
 
+/* ------------------------------------------------------------------------
+ * Cannon's matrix multiply: the local block product (Sec. 4.4).  Each of P ranks
+ * holds row stripes of Ns = N/P rows and at each of its P steps adds the product
+ * of an Ns x Ns block of its A stripe and the B stripe it holds (N * Ns * Ns
+ * multiply-adds) to its C stripe.  This is that step on one device:
+ *     C = (accumulate ? C : 0) + A B,
+ * A m x k, B k x n, C m x n, FP64, row-major device arrays with leading dimensions
+ * lda >= k, ldb >= n, ldc >= n (elements between consecutive rows), on the FP64
+ * matrix cores.  The ring shift of the B stripes between ranks is not part of it.
+ * Each element is a sum of the same products as the definition, in another order
+ * (within the FP64 error bound of the definition; exact where every partial sum is
+ * exactly representable, e.g. small integers).  m == 0 or n == 0: nothing happens;
+ * k == 0: C becomes C (accumulate) or 0.  FD_EINVAL for a negative extent, a NULL
+ * array that is needed, a leading dimension too small, or C overlapping A or B.
+ * Asynchronous on `stream`; the arrays stay the caller's. */
+int fd_block_gemm_f64(int64_t m, int64_t n, int64_t k, const double* a, int64_t lda,
+                      const double* b, int64_t ldb, double* c, int64_t ldc, int32_t accumulate,
+                      void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,8 @@ SIGNATURES = {
     "fd_cfl_dt": (C.c_int, [_G, _P, _f64, _P, C.POINTER(_f64), C.POINTER(_f64), _P]),
     "fd_cfl_dt_static": (C.c_int, [_G, _P, _f64, C.POINTER(_f64), C.POINTER(_f64), _P]),
     "fd_prepare_vdt2": (C.c_int, [_G, _P, _P, _f64, _P]),
+    "fd_block_gemm_f64": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P, C.c_int64, _P,
+                                    C.c_int64, _P, C.c_int64, _i32, _P]),
     "fd_prepare_vdt2_m": (C.c_int, [_G, _P, _P, _f64, _P]),
     "fd_sponge_eta_max": (_f64, [_f64, _f64, _f64, _i32, _f64]),
     "fd_sponge_profile": (C.c_int, [_P, _i32, _i32, _f64]),

@@ -681,3 +681,50 @@ class Simulation:
     def state(self):
         """Interior views of (u^{n-1}, u^n)."""
         return self.grid.interior(self.u_prev), self.grid.interior(self.u)
+
+
+# -------------------------------------------------- Cannon's matrix multiply (Sec. 4.4)
+
+def _ld(t: torch.Tensor, name: str) -> int:
+    """Leading dimension of a 2-D float64 device tensor with unit column stride."""
+    if t.dtype != torch.float64 or t.dim() != 2 or not t.is_cuda:
+        raise TypeError(f"{name}: a 2-D float64 device tensor is needed")
+    if t.numel() and t.shape[1] > 1 and t.stride(1) != 1:
+        raise TypeError(f"{name}: unit column stride is needed")
+    return t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+
+
+def block_gemm(a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, accumulate: bool = True,
+               stream=None) -> torch.Tensor:
+    """c = (c if accumulate else 0) + a @ b in FP64 on the matrix cores
+    (fd_block_gemm_f64): the local product of one Cannon step.  a (m, k), b (k, n),
+    c (m, n) may be row views of larger tensors; c is written in place."""
+    m, k = a.shape
+    k2, n = b.shape
+    if k != k2 or tuple(c.shape) != (m, n):
+        raise ValueError("block_gemm: shapes do not match")
+    check(lib().fd_block_gemm_f64(m, n, k, a.data_ptr(), _ld(a, "a"), b.data_ptr(), _ld(b, "b"),
+                                  c.data_ptr(), _ld(c, "c"), 1 if accumulate else 0,
+                                  _stream(stream)), "fd_block_gemm_f64")
+    return c
+
+
+def cannon_order(rank: int, P: int) -> list:
+    """The B row stripes rank ``rank`` multiplies with, in step order (its own first,
+    then the one its ring neighbour passes on after each step)."""
+    return [(rank + s) % P for s in range(P)]
+
+
+def cannon_rank(A_r: torch.Tensor, B: torch.Tensor, C_r: torch.Tensor, rank: int, P: int,
+                stream=None) -> torch.Tensor:
+    """The P local steps of one rank of Cannon's algorithm (Sec. 4.4) with every B
+    stripe resident (the ring shift that would bring them in is not done here):
+    C_r += A_r[:, q*Ns:(q+1)*Ns] @ B[q*Ns:(q+1)*Ns, :] for q in cannon_order(rank, P),
+    Ns = N / P.  A_r and C_r are the rank's Ns x N stripes, B is N x N."""
+    N = B.shape[0]
+    if B.shape != (N, N) or N % P or A_r.shape != (N // P, N) or C_r.shape != (N // P, N):
+        raise ValueError("cannon_rank: stripes of N/P x N and an N x N B are needed")
+    ns = N // P
+    for q in cannon_order(rank, P):
+        block_gemm(A_r[:, q * ns:(q + 1) * ns], B[q * ns:(q + 1) * ns, :], C_r, True, stream)
+    return C_r

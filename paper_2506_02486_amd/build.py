@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfd.so")
 
 SOURCES = ["fd_abi.cpp", "fd_launch.cpp", "fd_stencil.hip", "fd_stencil4.hip", "fd_point.hip",
-           "fd_aux.hip", "fd_server.cpp"]
+           "fd_aux.hip", "fd_server.cpp", "fd_gemm.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

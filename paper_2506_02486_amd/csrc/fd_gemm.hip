@@ -1,0 +1,223 @@
+// fd_gemm.hip -- the local block product of Cannon's matrix multiply on gfx950.
+//
+// In Cannon's algorithm each of P ranks holds row stripes of Ns = N/P rows and, at
+// each of its P steps, multiplies an Ns x Ns block of its A stripe with the B
+// stripe it holds, adding the N * Ns * Ns multiply-adds into its C stripe
+// (Sec. 4.4).  That step is C = C + A B, a dense contraction, so it runs on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64): the paper states no element type,
+// and FP64 is the precision of the oracle that defines the product.
+//
+// Block: 256 threads (4 waves), a 128 x 128 tile of C; each wave owns a 64 x 64
+// quarter as 4 x 4 MFMA tiles of 16 x 16 (16 independent accumulators of 4 doubles
+// per lane).  The K loop takes 16 columns of A and 16 rows of B per stage, staged in
+// double-buffered LDS; the next stage is loaded into registers while the MFMAs of the
+// current one run.
+// Operands of any shape and leading dimension: loads past an edge read 0 and stores
+// past an edge are skipped.  Blocks sharing a B panel (a column of tiles) run on
+// one XCD in succession, so that the panel is read from HBM about once.
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "fd.h"
+#include "fd_internal.h"
+
+namespace fd {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 256;          // threads per block
+constexpr int BM = 128;          // tile rows (M)
+constexpr int BN = 128;          // tile columns (N)
+constexpr int BK = 16;           // K per stage
+constexpr int WT = 64;           // wave tile edge
+// LDS pitches (doubles), chosen so that the 64 lanes of a fragment read (16 rows or
+// columns x 4 k) fall on distinct banks in each half-wave: A is kept row-major [m][k]
+// with pitch 18 (36 fr + 2 fk distinct mod 64 dwords), B as [k][n] with pitch 144
+// (consecutive k 32 banks apart).  (Pitches 130 / 130 with A transposed, and 144 /
+// 144, measured 56.6 and 47.9 TFLOP/s at 3780 x 30240 x 3780.)
+constexpr int SA = BK + 2;
+constexpr int SB = BN + 16;
+constexpr int A_PER = BM * BK / GT;  // A elements a thread loads per stage (8)
+constexpr int B_PER = BK * BN / GT;  // B elements a thread loads per stage (8)
+
+struct GemmArgs {
+  int64_t m, n, k;
+  const double* a;
+  int64_t lda;
+  const double* b;
+  int64_t ldb;
+  double* c;
+  int64_t ldc;
+  int tiles_m;
+  int accumulate;
+};
+
+// Blocks b, b+8, b+16, ... run on one XCD; give each XCD a contiguous run of
+// logical tiles (row tiles fastest: the tiles of one B panel).
+__device__ __forceinline__ int remap_gemm(int bid, int nb) {
+  const int per = nb >> 3;
+  if (bid < (per << 3)) return (bid & 7) * per + (bid >> 3);
+  return bid;
+}
+
+__global__ void __launch_bounds__(GT, 2) gemm_f64_kernel(GemmArgs g) {
+  __shared__ double sa[2][BM * SA];
+  __shared__ double sb[2][BK * SB];
+
+  const int logical = remap_gemm(blockIdx.x, gridDim.x);
+  const int64_t m0 = (int64_t)(logical % g.tiles_m) * BM;
+  const int64_t n0 = (int64_t)(logical / g.tiles_m) * BN;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  const int wm = (w >> 1) * WT;
+  const int wn = (w & 1) * WT;
+
+  // stage loads: A as 16 consecutive k of rows t/16 + 16 i; B as 128 consecutive
+  // columns of rows t/128 + 2 i (each instruction: 4 rows of 128 bytes of A, 512
+  // contiguous bytes of B)
+  const int ak = t & 15;
+  const int ar = t >> 4;
+  const int bc = t & 127;
+  const int br = t >> 7;
+  // Every load is unconditional: one past an edge reads the clamped element (in
+  // bounds) and is replaced by 0, so no branch splits the loads of a stage.
+  double ra[A_PER], rb[B_PER];
+  auto load_stage = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int64_t row = m0 + ar + 16 * i;
+      const int64_t col = k0 + ak;
+      const double x = g.a[std::min(row, g.m - 1) * g.lda + std::min(col, g.k - 1)];
+      ra[i] = (row < g.m && col < g.k) ? x : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) {
+      const int64_t row = k0 + br + 2 * i;
+      const int64_t col = n0 + bc;
+      const double x = g.b[std::min(row, g.k - 1) * g.ldb + std::min(col, g.n - 1)];
+      rb[i] = (row < g.k && col < g.n) ? x : 0.0;
+    }
+  };
+  auto store_stage = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) sa[buf][(ar + 16 * i) * SA + ak] = ra[i];
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) sb[buf][(br + 2 * i) * SB + bc] = rb[i];
+  };
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t stages = (g.k + BK - 1) / BK;
+  if (stages > 0) {
+    load_stage(0);
+    store_stage(0);
+  }
+  __syncthreads();
+  // fragment lanes: A rows / B columns lane % 16 of a 16-wide tile, k = lane / 16
+  const int fr = lane & 15;
+  const int fk = lane >> 4;
+  for (int64_t s = 0; s < stages; ++s) {
+    const int buf = (int)(s & 1);
+    // the next stage's loads, unconditional (the last iteration reloads its own
+    // stage into the buffer nobody reads again): a load under a branch would make
+    // the compiler wait for it where the branch joins, before the MFMAs
+    load_stage(std::min(s + 1, stages - 1) * BK);
+    const double* A = sa[buf];
+    const double* B = sb[buf];
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = A[(wm + 16 * i + fr) * SA + kk + fk];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = B[(kk + fk) * SB + wn + 16 * j + fr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    store_stage(buf ^ 1);
+    __syncthreads();
+  }
+
+  // accumulator element v of lane l holds row l / 16 + 4 v, column l % 16 of its
+  // 16 x 16 tile (the lane layout of v_mfma_f64_16x16x4f64, checked with one-hot
+  // operands on the device)
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = n0 + wn + 16 * j + fr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm + 16 * i + fk + 4 * v;
+        if (row < g.m && col < g.n) {
+          double* p = g.c + row * g.ldc + col;
+          *p = g.accumulate ? *p + acc[i][j][v] : acc[i][j][v];
+        }
+      }
+    }
+}
+
+// Last byte (exclusive) a row-major rows x cols operand with leading dimension ld
+// occupies, from its first element.
+int64_t extent_bytes(int64_t rows, int64_t cols, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return 8 * ((rows - 1) * ld + cols);
+}
+
+bool ranges_overlap(const void* p, int64_t pn, const void* q, int64_t qn) {
+  if (pn <= 0 || qn <= 0) return false;
+  const char* a = static_cast<const char*>(p);
+  const char* b = static_cast<const char*>(q);
+  return a < b + qn && b < a + pn;
+}
+
+}  // namespace
+}  // namespace fd
+
+using namespace fd;
+
+extern "C" int fd_block_gemm_f64(int64_t m, int64_t n, int64_t k, const double* a, int64_t lda,
+                                 const double* b, int64_t ldb, double* c, int64_t ldc,
+                                 int32_t accumulate, void* stream) {
+  if (m < 0 || n < 0 || k < 0) return fail(FD_EINVAL, "fd_block_gemm_f64: negative extent");
+  if (m == 0 || n == 0) return FD_OK;
+  if (!c) return fail(FD_EINVAL, "fd_block_gemm_f64: c is NULL");
+  if (ldc < n) return fail(FD_EINVAL, "fd_block_gemm_f64: ldc < n");
+  if (k > 0) {
+    if (!a || !b) return fail(FD_EINVAL, "fd_block_gemm_f64: a or b is NULL");
+    if (lda < k || ldb < n) return fail(FD_EINVAL, "fd_block_gemm_f64: lda < k or ldb < n");
+    const int64_t cb = extent_bytes(m, n, ldc);
+    if (ranges_overlap(c, cb, a, extent_bytes(m, k, lda)) ||
+        ranges_overlap(c, cb, b, extent_bytes(k, n, ldb)))
+      return fail(FD_EINVAL, "fd_block_gemm_f64: c overlaps a or b");
+  }
+  const int64_t tm = (m + BM - 1) / BM;
+  const int64_t tn = (n + BN - 1) / BN;
+  if (tm * tn > 0x7fffffffLL || tm > 0x7fffffffLL)
+    return fail(FD_EINVAL, "fd_block_gemm_f64: too many tiles");
+  GemmArgs g;
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.a = a;
+  g.lda = lda;
+  g.b = b;
+  g.ldb = ldb;
+  g.c = c;
+  g.ldc = ldc;
+  g.tiles_m = (int)tm;
+  g.accumulate = accumulate ? 1 : 0;
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)(tm * tn)), dim3(GT), 0,
+                     reinterpret_cast<hipStream_t>(stream), g);
+  return check_hip(hipGetLastError(), "fd_block_gemm_f64 launch");
+}

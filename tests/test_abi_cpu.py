@@ -343,3 +343,26 @@ def test_forward_graph_argument_checks(L):
     assert b"distinct" in L.fd_last_error()
     assert L.fd_graph_launch(None, None) == _lib.FD_EINVAL
     assert L.fd_graph_destroy(None) == _lib.FD_OK
+
+
+def test_block_gemm_argument_checks(L):
+    """fd_block_gemm_f64 (Cannon's local product) refuses bad extents, NULL arrays,
+    short leading dimensions and C overlapping A or B before any launch; empty
+    products do nothing."""
+    EINVAL = _lib.FD_EINVAL
+    m, n, k = 40, 30, 20
+    a, b, c = FAKE, FAKE + 8 * m * k, FAKE + 8 * (m * k + k * n)
+    G = L.fd_block_gemm_f64
+    assert G(-1, n, k, a, k, b, n, c, n, 1, None) == EINVAL
+    assert G(m, n, -2, a, k, b, n, c, n, 1, None) == EINVAL
+    assert G(m, n, k, None, k, b, n, c, n, 1, None) == EINVAL
+    assert G(m, n, k, a, k, None, n, c, n, 1, None) == EINVAL
+    assert G(m, n, k, a, k, b, n, None, n, 1, None) == EINVAL
+    assert G(m, n, k, a, k - 1, b, n, c, n, 1, None) == EINVAL   # lda < k
+    assert G(m, n, k, a, k, b, n - 1, c, n, 1, None) == EINVAL   # ldb < n
+    assert G(m, n, k, a, k, b, n, c, n - 1, 1, None) == EINVAL   # ldc < n
+    assert G(m, n, k, a, k, b, n, a + 8, n, 1, None) == EINVAL   # c overlaps a
+    assert G(m, n, k, a, k, b, n, b + 8 * n, n, 1, None) == EINVAL  # c overlaps b
+    assert G(0, n, k, a, k, b, n, c, n, 1, None) == 0            # nothing to do
+    assert G(m, 0, k, a, k, b, n, c, n, 1, None) == 0
+    assert G(0, 0, 0, None, 0, None, 0, None, 0, 0, None) == 0

@@ -1,0 +1,129 @@
+"""GPU parity of Cannon's local block product (fd_block_gemm_f64, Sec. 4.4) with the
+FP64 oracle's definition (oracle.block_gemm, oracle.cannon).
+
+With small integer operands every partial sum is exact in FP64, so the matrix-core
+product must equal the oracle bit for bit in any summation order: these cases span
+several 128 x 128 tiles with ragged edges in m, n and k, leading dimensions wider
+than the rows, accumulate on and off, and a single 16 x 16 x 4 tile (the MFMA lane
+layout).  Random normal operands are compared with the oracle within the FP64 error
+bound of a k-term dot product, 4 k u (|A| |B| + |C0|) elementwise.  The Cannon
+schedule of every rank reproduces the oracle's P-rank product, and at the full size of
+the paper's experiment (N = 30240, P = 8: rank 0's eight steps of 3780 x 30240 x 3780)
+sampled columns equal the oracle's exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as ora
+
+pytestmark = pytest.mark.gpu
+
+api = pytest.importorskip("paper_2506_02486_amd.api")
+_lib = pytest.importorskip("paper_2506_02486_amd._lib")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _padded(x: np.ndarray, extra: int, fill: float = 0.0) -> torch.Tensor:
+    """x as the leading columns of a wider device array (leading dimension > width)."""
+    t = torch.full((x.shape[0], x.shape[1] + extra), fill, dtype=torch.float64, device="cuda")
+    t[:, :x.shape[1]] = torch.from_numpy(x)
+    return t
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (16, 16, 4), (128, 128, 16), (130, 257, 33),
+                                   (300, 129, 70), (17, 5, 300), (255, 384, 1)])
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_integer_operands_bit_exact(m, n, k, accumulate):
+    rng = np.random.default_rng(m + 7 * n + 31 * k)
+    A = rng.integers(-40, 41, (m, k)).astype(np.float64)
+    B = rng.integers(-40, 41, (k, n)).astype(np.float64)
+    C0 = rng.integers(-500, 501, (m, n)).astype(np.float64)
+    a, b, c = _padded(A, 3), _padded(B, 5), _padded(C0, 2, fill=9.0)
+    api.block_gemm(a[:, :k], b[:, :n], c[:, :n], accumulate=accumulate)
+    torch.cuda.synchronize()
+    want = ora.block_gemm(A, B, C0.copy(), accumulate=accumulate)
+    got = c.cpu().numpy()
+    print(f"gemm {m}x{n}x{k} acc={accumulate}: max |diff| {np.abs(got[:, :n] - want).max():.1e}")
+    assert np.array_equal(got[:, :n], want)
+    assert np.all(got[:, n:] == 9.0)  # nothing outside C is written
+
+
+@pytest.mark.parametrize("m,n,k", [(200, 300, 257), (129, 131, 1000)])
+def test_random_operands_within_fp64_bound(m, n, k):
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((m, k))
+    B = rng.standard_normal((k, n))
+    C0 = rng.standard_normal((m, n))
+    c = torch.from_numpy(C0).cuda()
+    api.block_gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), c, accumulate=True)
+    got = c.cpu().numpy()
+    want = ora.block_gemm(A, B, C0.copy(), accumulate=True)
+    eps = np.finfo(np.float64).eps
+    bound = 4 * k * eps * (np.abs(A) @ np.abs(B) + np.abs(C0))
+    err = np.abs(got - want)
+    print(f"gemm {m}x{n}x{k} random: max err / bound {float((err / bound).max()):.3f}, "
+          f"rel L2 {np.linalg.norm(got - want) / np.linalg.norm(want):.2e}")
+    assert np.all(err <= bound)
+
+
+def test_empty_inner_dimension_and_empty_outputs():
+    c = torch.full((7, 9), 3.0, dtype=torch.float64, device="cuda")
+    a = torch.zeros((7, 0), dtype=torch.float64, device="cuda")
+    b = torch.zeros((0, 9), dtype=torch.float64, device="cuda")
+    api.block_gemm(a, b, c, accumulate=True)
+    torch.cuda.synchronize()
+    assert torch.all(c == 3.0)
+    api.block_gemm(a, b, c, accumulate=False)
+    torch.cuda.synchronize()
+    assert torch.all(c == 0.0)
+    e = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
+    api.block_gemm(e, torch.zeros((4, 5), dtype=torch.float64, device="cuda"),
+                   torch.zeros((0, 5), dtype=torch.float64, device="cuda"))
+    with pytest.raises(_lib.FDError) as err:
+        api.block_gemm(c[:, :4], c[:4, :], c, accumulate=True)  # c overlaps a and b
+    assert err.value.code == _lib.FD_EINVAL
+
+
+@pytest.mark.parametrize("N,P", [(96, 4), (300, 3), (260, 5)])
+def test_cannon_ranks_reproduce_the_product(N, P):
+    rng = np.random.default_rng(N + P)
+    A = rng.integers(-30, 31, (N, N)).astype(np.float64)
+    B = rng.integers(-30, 31, (N, N)).astype(np.float64)
+    want = ora.cannon(A, B, P)
+    ns = N // P
+    Bd = torch.from_numpy(B).cuda()
+    for r in range(P):
+        Cr = torch.zeros((ns, N), dtype=torch.float64, device="cuda")
+        api.cannon_rank(torch.from_numpy(A[r * ns:(r + 1) * ns]).cuda(), Bd, Cr, r, P)
+        assert np.array_equal(Cr.cpu().numpy(), want[r * ns:(r + 1) * ns])
+
+
+def test_full_size_rank_sampled_columns_exact():
+    """N = 30240, P = 8: rank 0's eight local products (3780 x 30240 x 3780 each) on
+    integer operands in [-3, 3]; 12 columns of C_0 (first, last, tile edges, ragged
+    tail) against the oracle, exactly."""
+    N, P = 30240, 8
+    ns = N // P
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    A0 = torch.randint(-3, 4, (ns, N), generator=g, device="cuda").to(torch.float64)
+    B = torch.randint(-3, 4, (N, N), generator=g, device="cuda").to(torch.float64)
+    C0 = torch.zeros((ns, N), dtype=torch.float64, device="cuda")
+    api.cannon_rank(A0, B, C0, 0, P)
+    torch.cuda.synchronize()
+    cols = [0, 1, 127, 128, 4095, 15000, 30111, 30112, 30200, 30238, 30239, 20000]
+    a_h = A0.cpu().numpy()
+    for j in cols:
+        want = ora.block_gemm(a_h, np.ascontiguousarray(B[:, j:j + 1].cpu().numpy()))
+        got = np.ascontiguousarray(C0[:, j:j + 1].cpu().numpy())
+        assert np.array_equal(got, want), j
+    del A0, B, C0
+    torch.cuda.empty_cache()
