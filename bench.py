@@ -654,6 +654,9 @@ def main():
     ap.add_argument("--no-cannon", action="store_true",
                     help="skip the Cannon block-product leg (N=30240, P=8)")
     ap.add_argument("--shots", type=int, default=256, help="shots in the serving stream")
+    ap.add_argument("--only", choices=["cannon", "fwi", "large", "serving"], default=None,
+                    help="run only this leg (no 512^3 step) and print its JSON object; for "
+                         "profiling a leg by itself")
     ap.add_argument("--vcache", default=None,
                     help="optional .npy path to cache the generated velocity model")
     args = ap.parse_args()
@@ -671,6 +674,18 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm device"
     torch.cuda.set_device(0)
+    if args.only:
+        cpu = not args.no_cpu_baseline
+        if args.only == "cannon":
+            leg = cannon_bench(cpu=cpu)
+        elif args.only == "fwi":
+            leg = fwi_bench()
+        elif args.only == "large":
+            leg = large_bench(steps=args.large_steps, cpu=cpu, vcache=args.vcache_large)
+        else:
+            leg = serving_bench(nshots=args.shots)
+        print(json.dumps(leg), flush=True)
+        return
     n = args.n
     log(f"bench: generating {n}^3 smooth velocity model")
     if args.vcache and os.path.exists(args.vcache):

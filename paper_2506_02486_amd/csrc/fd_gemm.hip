@@ -27,11 +27,12 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int GT = 256;          // threads per block
 constexpr int BM = 128;          // tile rows (M)
 constexpr int BN = 128;          // tile columns (N)
 constexpr int BK = 16;           // K per stage
 constexpr int WT = 64;           // wave tile edge
+constexpr int WAVES_N = BN / WT;
+constexpr int GT = 64 * (BM / WT) * WAVES_N;  // threads per block
 // LDS pitches (doubles), chosen so that the 64 lanes of a fragment read (16 rows or
 // columns x 4 k) fall on distinct banks in each half-wave: A is kept row-major [m][k]
 // with pitch 18 (36 fr + 2 fk distinct mod 64 dwords), B as [k][n] with pitch 144
@@ -39,6 +40,7 @@ constexpr int WT = 64;           // wave tile edge
 // 144, measured 56.6 and 47.9 TFLOP/s at 3780 x 30240 x 3780.)
 constexpr int SA = BK + 2;
 constexpr int SB = BN + 16;
+constexpr int MIN_BLOCKS = 2;    // blocks per CU (LDS: 2 x 73.7 KB of 160 KB)
 constexpr int A_PER = BM * BK / GT;  // A elements a thread loads per stage (8)
 constexpr int B_PER = BK * BN / GT;  // B elements a thread loads per stage (8)
 
@@ -62,7 +64,7 @@ __device__ __forceinline__ int remap_gemm(int bid, int nb) {
   return bid;
 }
 
-__global__ void __launch_bounds__(GT, 2) gemm_f64_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(GT, MIN_BLOCKS) gemm_f64_kernel(GemmArgs g) {
   __shared__ double sa[2][BM * SA];
   __shared__ double sb[2][BK * SB];
 
@@ -72,30 +74,30 @@ __global__ void __launch_bounds__(GT, 2) gemm_f64_kernel(GemmArgs g) {
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
-  const int wm = (w >> 1) * WT;
-  const int wn = (w & 1) * WT;
+  const int wm = (w / WAVES_N) * WT;
+  const int wn = (w % WAVES_N) * WT;
 
-  // stage loads: A as 16 consecutive k of rows t/16 + 16 i; B as 128 consecutive
-  // columns of rows t/128 + 2 i (each instruction: 4 rows of 128 bytes of A, 512
-  // contiguous bytes of B)
-  const int ak = t & 15;
-  const int ar = t >> 4;
-  const int bc = t & 127;
-  const int br = t >> 7;
+  // stage loads: A as BK consecutive k of rows t / BK + (GT / BK) i; B as BN
+  // consecutive columns of rows t / BN + (GT / BN) i (each instruction: 4 rows of 128
+  // bytes of A, 512 contiguous bytes of B)
+  const int ak = t % BK;
+  const int ar = t / BK;
+  const int bc = t % BN;
+  const int br = t / BN;
   // Every load is unconditional: one past an edge reads the clamped element (in
   // bounds) and is replaced by 0, so no branch splits the loads of a stage.
   double ra[A_PER], rb[B_PER];
   auto load_stage = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < A_PER; ++i) {
-      const int64_t row = m0 + ar + 16 * i;
+      const int64_t row = m0 + ar + (GT / BK) * i;
       const int64_t col = k0 + ak;
       const double x = g.a[std::min(row, g.m - 1) * g.lda + std::min(col, g.k - 1)];
       ra[i] = (row < g.m && col < g.k) ? x : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < B_PER; ++i) {
-      const int64_t row = k0 + br + 2 * i;
+      const int64_t row = k0 + br + (GT / BN) * i;
       const int64_t col = n0 + bc;
       const double x = g.b[std::min(row, g.k - 1) * g.ldb + std::min(col, g.n - 1)];
       rb[i] = (row < g.k && col < g.n) ? x : 0.0;
@@ -103,9 +105,9 @@ __global__ void __launch_bounds__(GT, 2) gemm_f64_kernel(GemmArgs g) {
   };
   auto store_stage = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < A_PER; ++i) sa[buf][(ar + 16 * i) * SA + ak] = ra[i];
+    for (int i = 0; i < A_PER; ++i) sa[buf][(ar + (GT / BK) * i) * SA + ak] = ra[i];
 #pragma unroll
-    for (int i = 0; i < B_PER; ++i) sb[buf][(br + 2 * i) * SB + bc] = rb[i];
+    for (int i = 0; i < B_PER; ++i) sb[buf][(br + (GT / BN) * i) * SB + bc] = rb[i];
   };
 
   d4 acc[4][4];
