@@ -6,10 +6,11 @@ scaled form (fd_adjoint_step_scaled on b = vdt2 D lambda, against vdt2 D times t
 oracle's step); the transpose
 identity is checked in FP32 with FP64 reductions (<= 1e-5 relative); the checkpointed
 FWI gradient is compared with the oracle's full-storage gradient driven by the same
-residual (relative L2 <= 1e-3), with the oracle's own end-to-end gradient and FP64
-central differences of the misfit (<= 2e-2: there the FP32 forward error is amplified
-by the small residual), and at the full 256^3 / 1000-step size by the
-source-to-traces dot-product test.
+residual (relative L2 <= 2e-5; measured 5e-6), with the oracle's own end-to-end
+gradient (<= 1.5e-2; measured 9.2e-3) and FP64 central differences of the misfit
+(<= 1.5e-2; measured 7.1e-3: there the FP32 forward error, ~1e-5 of the traces, is
+amplified by the residual, a small difference of nearby models), and at the full
+256^3 / 1000-step size by the source-to-traces dot-product test.
 """
 import numpy as np
 import pytest
@@ -215,8 +216,8 @@ def test_fwi_gradient_matches_oracle_and_central_differences():
     e_J = abs(J - ref["J"]) / ref["J"]
     e_g = rel_l2(gm, ref["grad_m"])
     print(f"FWI 64^3: J rel err {e_J:.2e}, gradient vs oracle rel L2 {e_g:.2e}")
-    assert e_J <= 1e-2
-    assert e_g <= 2e-2
+    assert e_J <= 6e-3
+    assert e_g <= 1.5e-2
     # ... and the adjoint sweep itself tightly: the oracle is driven by exactly the
     # residual the GPU saw (obs shifted by the GPU-minus-oracle trace difference).
     tr_gpu = prob.forward(m, checkpoints=False).cpu().numpy().astype(np.float64)
@@ -230,9 +231,9 @@ def test_fwi_gradient_matches_oracle_and_central_differences():
     e_ab = rel_l2(gm_a, gm)
     print(f"FWI 64^3: same residual: scaled {e_same:.2e}, lambda {e_same_a:.2e}, "
           f"scaled vs lambda {e_ab:.2e}")
-    assert e_same <= 1e-3
-    assert e_same_a <= 1e-3
-    assert e_ab <= 5e-4
+    assert e_same <= 2e-5
+    assert e_same_a <= 2e-5
+    assert e_ab <= 5e-6
     vox = fd_voxels(ref["grad_m"], count=16, seed=5)
 
     def Jo(mm):
@@ -250,7 +251,7 @@ def test_fwi_gradient_matches_oracle_and_central_differences():
     e_gfd = rel_l2(gm.flat[vox], fd)
     print(f"FWI 64^3: oracle vs FD {e_ofd:.2e}, GPU vs FD {e_gfd:.2e}")
     assert e_ofd <= 1e-6
-    assert e_gfd <= 2e-2
+    assert e_gfd <= 1.5e-2
 
 
 def _scaled_step_with_residual(tiles, fused):
