@@ -455,6 +455,7 @@ __global__ void __launch_bounds__(LANES * TROWS) batched4_kernel(const BatchShot
   p.rmap = b.rmap;
   p.rk = b.rmap ? b.rk : -1;
   p.rrow = b.traces + (size_t)n * (size_t)b.nrec;
+  p.radd = false;  // the trace row is written, not added to
   stencil4_block<true, true, false>(p, t.y, t.z, t.w);
 }
 
