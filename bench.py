@@ -599,7 +599,7 @@ def cannon_bench(N=30240, P=8, reps=3, cpu=True, cpu_cols=32):
                        f"all B stripes resident, seeded normal operands",
            "value": round(tflops, 2), "unit": "TFLOP/s", "dtype": "f64",
            "ms_per_rank_pass": round(ms_launch * P, 3),
-           "roofline": {"bound": "mfma", "kernel": "gemm_f64_kernel (128 x 128 tiles, "
+           "roofline": {"bound": "mfma", "kernel": "gemm_f64_kernel (256 x 128 tiles, 16 waves, "
                                                    "v_mfma_f64_16x16x4f64)",
                         "achieved": round(tflops, 2), "peak": PEAK_FP64_MFMA_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(tflops / PEAK_FP64_MFMA_TFLOPS, 4),

@@ -7,9 +7,10 @@
 // FP64 matrix cores (v_mfma_f64_16x16x4f64): the paper states no element type,
 // and FP64 is the precision of the oracle that defines the product.
 //
-// Block: 256 threads (4 waves), a 128 x 128 tile of C; each wave owns a 64 x 64
-// quarter as 4 x 4 MFMA tiles of 16 x 16 (16 independent accumulators of 4 doubles
-// per lane).  The K loop takes 16 columns of A and 16 rows of B per stage, staged in
+// Block: 1024 threads (16 waves), a 256 x 128 tile of C; each wave owns a 32 x 64
+// piece as 2 x 4 MFMA tiles of 16 x 16 (8 independent accumulators of 4 doubles per
+// lane), so that four waves share each SIMD and one's LDS and barrier phases hide
+// behind the others' MFMAs.  The K loop takes 16 columns of A and 16 rows of B per stage, staged in
 // double-buffered LDS; the next stage is loaded into registers while the MFMAs of the
 // current one run.
 // Operands of any shape and leading dimension: loads past an edge read 0 and stores
@@ -27,22 +28,27 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128;          // tile rows (M)
+constexpr int BM = 256;          // tile rows (M)
 constexpr int BN = 128;          // tile columns (N)
 constexpr int BK = 16;           // K per stage
-constexpr int WT = 64;           // wave tile edge
-constexpr int WAVES_N = BN / WT;
-constexpr int GT = 64 * (BM / WT) * WAVES_N;  // threads per block
+constexpr int WTM = 32;          // wave tile rows
+constexpr int WTN = 64;          // wave tile columns
+constexpr int WAVES_N = BN / WTN;
+constexpr int GT = 64 * (BM / WTM) * WAVES_N;  // threads per block
+constexpr int FM = WTM / 16;     // MFMA tiles per wave, rows
+constexpr int FN = WTN / 16;     // MFMA tiles per wave, columns
 // LDS pitches (doubles), chosen so that the 64 lanes of a fragment read (16 rows or
 // columns x 4 k) fall on distinct banks in each half-wave: A is kept row-major [m][k]
 // with pitch 18 (36 fr + 2 fk distinct mod 64 dwords), B as [k][n] with pitch 144
-// (consecutive k 32 banks apart).  (Pitches 130 / 130 with A transposed, and 144 /
-// 144, measured 56.6 and 47.9 TFLOP/s at 3780 x 30240 x 3780.)
+// (consecutive k 32 banks apart).
 constexpr int SA = BK + 2;
 constexpr int SB = BN + 16;
-constexpr int MIN_BLOCKS = 2;    // blocks per CU (LDS: 2 x 73.7 KB of 160 KB)
-constexpr int A_PER = BM * BK / GT;  // A elements a thread loads per stage (8)
-constexpr int B_PER = BK * BN / GT;  // B elements a thread loads per stage (8)
+// waves per SIMD the register budget must allow (the second __launch_bounds__
+// argument): one block of 16 waves per CU (LDS 110.6 KB of 160 KB), at most 128
+// VGPRs per lane
+constexpr int WAVES_PER_SIMD = 4;
+constexpr int A_PER = BM * BK / GT;  // A elements a thread loads per stage
+constexpr int B_PER = BK * BN / GT;  // B elements a thread loads per stage
 
 struct GemmArgs {
   int64_t m, n, k;
@@ -64,7 +70,7 @@ __device__ __forceinline__ int remap_gemm(int bid, int nb) {
   return bid;
 }
 
-__global__ void __launch_bounds__(GT, MIN_BLOCKS) gemm_f64_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(GT, WAVES_PER_SIMD) gemm_f64_kernel(GemmArgs g) {
   __shared__ double sa[2][BM * SA];
   __shared__ double sb[2][BK * SB];
 
@@ -74,8 +80,8 @@ __global__ void __launch_bounds__(GT, MIN_BLOCKS) gemm_f64_kernel(GemmArgs g) {
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
-  const int wm = (w / WAVES_N) * WT;
-  const int wn = (w % WAVES_N) * WT;
+  const int wm = (w / WAVES_N) * WTM;
+  const int wn = (w % WAVES_N) * WTN;
 
   // stage loads: A as BK consecutive k of rows t / BK + (GT / BK) i; B as BN
   // consecutive columns of rows t / BN + (GT / BN) i (each instruction: 4 rows of 128
@@ -110,11 +116,11 @@ __global__ void __launch_bounds__(GT, MIN_BLOCKS) gemm_f64_kernel(GemmArgs g) {
     for (int i = 0; i < B_PER; ++i) sb[buf][(br + (GT / BN) * i) * SB + bc] = rb[i];
   };
 
-  d4 acc[4][4];
+  d4 acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int64_t stages = (g.k + BK - 1) / BK;
   if (stages > 0) {
@@ -135,15 +141,15 @@ __global__ void __launch_bounds__(GT, MIN_BLOCKS) gemm_f64_kernel(GemmArgs g) {
     const double* B = sb[buf];
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double af[4], bf[4];
+      double af[FM], bf[FN];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) af[i] = A[(wm + 16 * i + fr) * SA + kk + fk];
+      for (int i = 0; i < FM; ++i) af[i] = A[(wm + 16 * i + fr) * SA + kk + fk];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bf[j] = B[(kk + fk) * SB + wn + 16 * j + fr];
+      for (int j = 0; j < FN; ++j) bf[j] = B[(kk + fk) * SB + wn + 16 * j + fr];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
     store_stage(buf ^ 1);
@@ -154,9 +160,9 @@ __global__ void __launch_bounds__(GT, MIN_BLOCKS) gemm_f64_kernel(GemmArgs g) {
   // 16 x 16 tile (the lane layout of v_mfma_f64_16x16x4f64, checked with one-hot
   // operands on the device)
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < FN; ++j) {
       const int64_t col = n0 + wn + 16 * j + fr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
