@@ -43,7 +43,8 @@ PEAK_HBM_GBPS = 8000.0
 METRIC = "Gpts/s + % HBM roofline; shots/s and p50/p99 latency vs plain per-shot loop"
 CSRC = os.path.join(ROOT, "paper_2506_02486_amd", "csrc")
 # source file of each forward kernel (the counter summary is valid for one version)
-KERNEL_SRC = {"wide_128x32": "fd_stencil4.hip", "march_64x32": "fd_stencil.hip",
+KERNEL_SRC = {"wide_128x32": "fd_stencil4.hip", "wide_64x64": "fd_stencil4.hip",
+              "march_64x32": "fd_stencil.hip",
               "march_64x16": "fd_stencil.hip", "point": "fd_point.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fd_step_512_traffic.txt")
 

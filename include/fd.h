@@ -135,15 +135,18 @@ int fd_set_kchunk(int32_t kchunk);
  * 2^22 points, which stay in cache and whose step is latency-bound, and so does
  * fd_step_exchange / fd_forward_run with all twelve face buffers on grids of at
  * most 2^21 points, the faces then read and written in that one launch; grids of
- * at least 7.5 million points take the kernel of 16-byte lanes and 128 x 32 tiles
- * (the exchange form where nx is a multiple of 128; not where the receiver row is
- * taken in the stencil launch; arrays and face buffers 16-byte aligned); the others
- * the z-marching kernel of one float per lane, 64 x 16 tiles for grids of at most
- * 2^20 points, 64 x 32 above.  1 = always 64 x 32, 2 = always 64 x 16 (both: never
- * one thread per point nor 16-byte lanes), 3 = one thread per point wherever it
- * applies (64 x 16 elsewhere), 4 = 16-byte lanes wherever they apply (64 x 32
- * elsewhere).  Process-wide; results do not depend on it (fd_step_kernel reports the
- * choice).  FD_EINVAL for another mode. */
+ * at least 7.5 million points take the kernel of 16-byte lanes (the exchange form
+ * where nx is a multiple of 128, with 128 x 32 tiles; the update without faces and
+ * the gradient pass with 128 x 32 tiles, or 64 x 64 where the launch model prefers
+ * them by a tenth, i.e. where a 128-wide tile column would be mostly empty; arrays
+ * and face buffers 16-byte aligned); the others the z-marching kernel of one float
+ * per lane, 64 x 16 tiles for grids of at most 2^20 points, 64 x 32 above.  1 =
+ * always 64 x 32, 2 = always 64 x 16 (both: never one thread per point nor 16-byte
+ * lanes), 3 = one thread per point wherever it applies (64 x 16 elsewhere), 4 =
+ * 16-byte lanes wherever they apply, 128 x 32 tiles (64 x 32 elsewhere), 5 = the
+ * same with 64 x 64 tiles where the 16-byte-lane kernel takes no faces.
+ * Process-wide; results do not depend on it (fd_step_kernel reports the choice).
+ * FD_EINVAL for another mode. */
 int fd_set_tiles(int32_t mode);
 
 /* Launch shape of the z-marching forward stencil kernel of one float per lane
@@ -166,7 +169,8 @@ enum {
   FD_KERNEL_POINT = 0,        /* one thread per point (small grids, in cache)   */
   FD_KERNEL_MARCH_64x32 = 1,  /* z-marching, one float per lane, 64 x 32 tiles  */
   FD_KERNEL_MARCH_64x16 = 2,  /* the same with 64 x 16 tiles                    */
-  FD_KERNEL_WIDE = 3          /* z-marching, 16-byte lanes, 128 x 32 tiles      */
+  FD_KERNEL_WIDE = 3,         /* z-marching, 16-byte lanes, 128 x 32 tiles      */
+  FD_KERNEL_WIDE_64x64 = 4    /* the same with 64 x 64 tiles (ragged x extents) */
 };
 int fd_step_kernel(const fd_grid* g, int32_t with_faces, int32_t out[6]);
 

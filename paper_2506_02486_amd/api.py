@@ -385,7 +385,8 @@ def step_launch(grid: Grid) -> dict:
     return {"tiles_x": tx, "tiles_y": ty, "kchunk": kc, "zchunks": zc, "blocks": tx * ty * zc}
 
 
-KERNEL_NAMES = {0: "point", 1: "march_64x32", 2: "march_64x16", 3: "wide_128x32"}
+KERNEL_NAMES = {0: "point", 1: "march_64x32", 2: "march_64x16", 3: "wide_128x32",
+                4: "wide_64x64"}
 
 
 def step_kernel(grid: Grid, faces: bool = False) -> dict:

@@ -185,10 +185,10 @@ int fd_set_kchunk(int32_t kchunk) {
 }
 
 int fd_set_tiles(int32_t mode) {
-  if (mode < 0 || mode > 4)
+  if (mode < 0 || mode > 5)
     return fail(FD_EINVAL,
-                "tile mode %d: 0 (automatic), 1 (64 x 32), 2 (64 x 16), 3 (one thread per point) "
-                "or 4 (128 x 32, 16-byte lanes)",
+                "tile mode %d: 0 (automatic), 1 (64 x 32), 2 (64 x 16), 3 (one thread per point), "
+                "4 (128 x 32, 16-byte lanes) or 5 (64 x 64, 16-byte lanes)",
                 mode);
   set_tile_override(mode);
   return FD_OK;
@@ -224,10 +224,20 @@ int fd_step_kernel(const fd_grid* g, int32_t with_faces, int32_t out[6]) {
   if (point) {
     kind = FD_KERNEL_POINT;
   } else if (forward_wide_tiles(geo) && wide_fits) {
-    kind = FD_KERNEL_WIDE;
-    wide_forward_shape(geo, o);
-    tx = 128;
-    ty = 32;
+    // the exchange form keeps 128 x 32 tiles (its x faces are whole tile columns)
+    const bool narrow = !x_inside && wide_narrow_tiles(geo);
+    kind = narrow ? FD_KERNEL_WIDE_64x64 : FD_KERNEL_WIDE;
+    if (narrow) {
+      wide_forward_shape(geo, o);
+    } else {
+      const LaunchShape sh = stencil_shape(geo, 128, 32, 16);
+      o[0] = sh.tiles_x;
+      o[1] = sh.tiles_y;
+      o[2] = sh.kchunk;
+      o[3] = sh.zchunks;
+    }
+    tx = narrow ? 64 : 128;
+    ty = narrow ? 64 : 32;
   } else {
     const bool small = forward_small_tiles(geo);
     kind = small ? FD_KERNEL_MARCH_64x16 : FD_KERNEL_MARCH_64x32;

@@ -118,6 +118,15 @@ struct LaunchShape {
 LaunchShape stencil_shape(const Geo& g, int tx, int ty, int waves_per_block);
 // Process-wide z chunk for every stencil launch (0: automatic).
 void set_kchunk_override(int kc);
+// Modelled time (arbitrary units) of the launch stencil_shape picks for tx x ty
+// tiles over g.
+double stencil_cost(const Geo& g, int tx, int ty, int waves_per_block);
+// The process-wide tile mode of set_tile_override.
+int tile_override();
+// Whether the 16-byte-lane forward update and gradient pass over g (not the
+// exchange form) take 64 x 64 tiles instead of 128 x 32 (tile mode 5: always; 4:
+// never; else where the launch model prefers them by a tenth).
+bool wide_narrow_tiles(const Geo& g);
 // Forward launches over g use 64 x 16 tiles instead of 64 x 32: small grids (at
 // most kSmallGridPoints interior points), or as forced by set_tile_override
 // (0: automatic, 1: always 64 x 32, 2: always 64 x 16).
@@ -125,8 +134,8 @@ bool forward_small_tiles(const Geo& g);
 void set_tile_override(int mode);
 // Forward updates (and gradient passes) over g take the 16-byte-lane
 // kernel of fd_stencil4.hip: bandwidth-bound grids (more than kWideGridPoints
-// interior points), or as forced by set_tile_override (4: wherever it fits; 1, 2,
-// 3: never).
+// interior points), or as forced by set_tile_override (4, 5: wherever it fits; 1,
+// 2, 3: never).
 bool forward_wide_tiles(const Geo& g);
 // Whether the 16-byte-lane kernel can take a step over g: rows, strides and origin
 // multiples of 4 floats, the four volume arrays (u_prev, u, u_next, vdt2) 16-byte

@@ -93,9 +93,17 @@ LaunchShape stencil_shape(const Geo& g, int tx, int ty, int waves_per_block) {
 
 void set_kchunk_override(int kc) { g_kchunk_override.store(kc, std::memory_order_relaxed); }
 
+double stencil_cost(const Geo& g, int tx, int ty, int waves_per_block) {
+  const LaunchShape s = stencil_shape(g, tx, ty, waves_per_block);
+  const long long R = std::max(1, 4096 / std::max(1, waves_per_block));
+  return launch_cost((long long)s.tiles_x * s.tiles_y * s.zchunks, s.kchunk, R);
+}
+
+int tile_override() { return g_tile_override.load(std::memory_order_relaxed); }
+
 bool forward_small_tiles(const Geo& g) {
   const int mode = g_tile_override.load(std::memory_order_relaxed);
-  if (mode == 1 || mode == 4) return false;
+  if (mode == 1 || mode == 4 || mode == 5) return false;
   if (mode == 2 || mode == 3) return true;
   return (long long)g.nx * g.ny * g.nz <= kSmallGridPoints;
 }
@@ -110,7 +118,7 @@ constexpr long long kWideGridPoints = 7500000;
 
 bool forward_wide_tiles(const Geo& g) {
   const int mode = g_tile_override.load(std::memory_order_relaxed);
-  if (mode == 4) return true;
+  if (mode == 4 || mode == 5) return true;
   if (mode != 0) return false;
   return (long long)g.nx * g.ny * g.nz >= kWideGridPoints;
 }
@@ -125,7 +133,7 @@ constexpr long long kPointGridPoints = 1LL << 22;
 bool point_kernel_pays(const Geo& g) {
   const int mode = g_tile_override.load(std::memory_order_relaxed);
   if (mode == 3) return true;
-  if (mode == 1 || mode == 2 || mode == 4) return false;
+  if (mode == 1 || mode == 2 || mode == 4 || mode == 5) return false;
   return (long long)g.nx * g.ny * g.nz <= kPointGridPoints;
 }
 
@@ -138,7 +146,7 @@ constexpr long long kPointExchangePoints = 1LL << 21;
 bool point_exchange_pays(const Geo& g) {
   const int mode = g_tile_override.load(std::memory_order_relaxed);
   if (mode == 3) return true;
-  if (mode == 1 || mode == 2 || mode == 4) return false;
+  if (mode == 1 || mode == 2 || mode == 4 || mode == 5) return false;
   return (long long)g.nx * g.ny * g.nz <= kPointExchangePoints;
 }
 

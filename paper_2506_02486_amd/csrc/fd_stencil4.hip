@@ -17,15 +17,18 @@
 // before it is needed (eta_z travels with the pointwise operands).
 //
 // Block: 32 x 16 threads (8 waves; a wave holds two thread rows), tile
-// 128 x 32 points, marching along z through a chunk of planes:
-//   * z neighbours: a 9-deep queue of float4 per row in registers, a ring
-//     renamed by unrolling the z loop nine times;
+// 128 x 32 points, marching along z through a chunk of planes (or 16 x 32 threads,
+// tile 64 x 64 points, where the x extent leaves a 128-wide tile column mostly
+// empty: 320 points take 3 columns of 128 or 5 of 64; the launch takes the shape
+// whose modelled cost is lower by 10%):
+//   * z neighbours: a 9-deep queue of float4 per row in registers, a ring of 10
+//     slots renamed by unrolling the z loop ten times;
 //   * the plane (tile + 4-wide x/y halos) is staged in double-buffered LDS;
 //     x neighbours are the lane's own float4 and the two float4 beside it,
 //     y neighbours come from the thread's other row or from LDS;
 //   * each thread of the first 8 thread rows loads one float4 of the y halo
-//     (8 rows x 32 float4), 64 threads of the others one float4 of the x halo
-//     (32 rows x 2 sides); these are loaded in the same iteration as the plane
+//     (8 rows x 32 float4; 8 x 16 with 64 x 64 tiles), 64 (128) threads of the
+//     others one float4 of the x halo (32 (64) rows x 2 sides); these are loaded in the same iteration as the plane
 //     they belong to is loaded by the neighbouring tile as its interior (five
 //     planes ahead, kept in a ring), so those re-reads hit in L2;
 //   * u^{n-1} and vdt2 are prefetched one plane ahead and streamed, like the
@@ -46,13 +49,22 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int LANES = 32;           // lanes per thread row
-constexpr int TROWS = 16;           // thread rows per block
-constexpr int RY = 2;               // y rows per thread
-constexpr int TX = 4 * LANES;       // 128 x points per tile
-constexpr int TY = TROWS * RY;      // 32 y rows per tile
-constexpr int LX = TX + 8;          // LDS row pitch (floats)
-constexpr int LY = TY + 8;          // LDS rows
+// Tile shapes: 32 lanes x 16 thread rows (128 x 32 points), or 16 lanes x 32 thread
+// rows (64 x 64 points), for grids whose x extent leaves a 128-wide tile column
+// mostly empty.  Both are 512 threads; a wave is 2 or 4 thread rows.
+struct Wide128 {
+  static constexpr int LANES = 32;  // lanes per thread row
+  static constexpr int TROWS = 16;  // thread rows per block
+};
+struct Wide64 {
+  static constexpr int LANES = 16;
+  static constexpr int TROWS = 32;
+};
+constexpr int RY = 2;                   // y rows per thread
+constexpr int LANES = Wide128::LANES;   // the shape of the exchange, tile-table and
+constexpr int TROWS = Wide128::TROWS;   // multi-grid launches
+constexpr int TX = 4 * LANES;           // 128 x points per tile
+constexpr int TY = TROWS * RY;          // 32 y rows per tile
 
 struct P4 {
   Geo g;
@@ -92,9 +104,15 @@ __device__ __forceinline__ f4 ld4_nt(const char* base, unsigned boff) {
 
 // The work of one block: tile (bx, by) of the x-y plane, z chunk bz, of the grid
 // and operands p describes.
-template <bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
+template <class SH, bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
 __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const int by,
                                                const int bz) {
+  constexpr int LANES = SH::LANES;
+  constexpr int TX = 4 * LANES;           // x points per tile
+  constexpr int TY = SH::TROWS * RY;      // y rows per tile
+  constexpr int LX = TX + 8;              // LDS row pitch (floats)
+  constexpr int LY = TY + 8;              // LDS rows
+  constexpr int XH = 2 * TY / LANES;      // thread rows that load the x halo
   __shared__ __attribute__((aligned(16))) float sm[2][LY * LX];
 
   const int lx = threadIdx.x;
@@ -145,7 +163,7 @@ __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const 
     h_on = true;
     h_y = tr < 4 ? y0 - 4 + tr : y0 + TY + (tr - 4);
     h_lds = (tr < 4 ? tr : TY + tr) * LX + 4 + 4 * lx;
-  } else if (tr < 10) {
+  } else if (tr < 8 + XH) {
     const int idx = (tr - 8) * LANES + lx;
     h_on = true;
     h_side = idx & 1;
@@ -416,12 +434,12 @@ __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const 
   }
 }
 
-template <bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
-__global__ void __launch_bounds__(LANES * TROWS) stencil4_kernel(P4 p) {
+template <class SH, bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
+__global__ void __launch_bounds__(SH::LANES * SH::TROWS) stencil4_kernel(P4 p) {
   const int logical = remap_block4(blockIdx.x, gridDim.x);
   const int bx = logical % p.tiles_x;
   const int rest = logical / p.tiles_x;
-  stencil4_block<SPONGE, FUSE, XCH, GRAD>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
+  stencil4_block<SH, SPONGE, FUSE, XCH, GRAD>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
 }
 
 // Many grids in one launch: block b runs tile tiles[remap(b)] = (slot, bx, by, bz) of
@@ -456,7 +474,7 @@ __global__ void __launch_bounds__(LANES * TROWS) batched4_kernel(const BatchShot
   p.rk = b.rmap ? b.rk : -1;
   p.rrow = b.traces + (size_t)n * (size_t)b.nrec;
   p.radd = false;  // the trace row is written, not added to
-  stencil4_block<true, true, false>(p, t.y, t.z, t.w);
+  stencil4_block<Wide128, true, true, false>(p, t.y, t.z, t.w);
 }
 
 // Up to kWideMulti grids in one launch, their parameters in the kernel arguments:
@@ -477,20 +495,20 @@ __global__ void __launch_bounds__(LANES * TROWS) multi4_kernel(MultiArgs A) {
   const int t = b - A.start[i];
   const int bx = t % p.tiles_x;
   const int rest = t / p.tiles_x;
-  stencil4_block<true, true, false>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
+  stencil4_block<Wide128, true, true, false>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
 }
 
-template <bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
+template <class SH, bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
 hipError_t launch4(P4 p, hipStream_t st) {
   // one block per CU: its 8 waves take a CU's share of 16 (more than 128 VGPRs)
-  const LaunchShape sh = stencil_shape(p.g, TX, TY, 16);
+  const LaunchShape sh = stencil_shape(p.g, 4 * SH::LANES, SH::TROWS * RY, 16);
   p.tiles_x = sh.tiles_x;
   p.tiles_y = sh.tiles_y;
   p.kchunk = sh.kchunk;
   const long long nb = (long long)sh.tiles_x * sh.tiles_y * sh.zchunks;
   if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((stencil4_kernel<SPONGE, FUSE, XCH, GRAD>), dim3((unsigned)nb), dim3(LANES, TROWS),
-                     0, st, p);
+  hipLaunchKernelGGL((stencil4_kernel<SH, SPONGE, FUSE, XCH, GRAD>), dim3((unsigned)nb),
+                     dim3(SH::LANES, SH::TROWS), 0, st, p);
   return hipGetLastError();
 }
 
@@ -601,12 +619,26 @@ hipError_t launch_grad_wide(const Geo& g, const Coef& c, const float* u, const f
     p.sk = src->k;
     p.sw = src->w;
   }
-  if (ex) return launch4<true, false, false, true>(p, s);
-  return launch4<false, false, false, true>(p, s);
+  if (wide_narrow_tiles(g)) {
+    if (ex) return launch4<Wide64, true, false, false, true>(p, s);
+    return launch4<Wide64, false, false, false, true>(p, s);
+  }
+  if (ex) return launch4<Wide128, true, false, false, true>(p, s);
+  return launch4<Wide128, false, false, false, true>(p, s);
+}
+
+bool wide_narrow_tiles(const Geo& g) {
+  const int mode = tile_override();
+  if (mode == 5) return true;
+  if (mode == 4) return false;
+  // 64 x 64 where they cut the modelled launch time by a tenth: where a 128-wide
+  // tile column would be mostly empty (nx = 257: 3 columns of 128, 5 of 64)
+  return stencil_cost(g, 64, 64, 16) < 0.9 * stencil_cost(g, TX, TY, 16);
 }
 
 void wide_forward_shape(const Geo& g, int out[4]) {
-  const LaunchShape sh = stencil_shape(g, TX, TY, 16);
+  const bool narrow = wide_narrow_tiles(g);
+  const LaunchShape sh = stencil_shape(g, narrow ? 64 : TX, narrow ? 64 : TY, 16);
   out[0] = sh.tiles_x;
   out[1] = sh.tiles_y;
   out[2] = sh.kchunk;
@@ -651,15 +683,24 @@ hipError_t launch_forward_wide(const Geo& g, const Coef& c, const float* up, con
   }
   const bool sponge = ex != nullptr;
   if (xch) {
-    if (sponge) return launch4<true, true, true>(p, s);
-    return launch4<false, true, true>(p, s);
+    if (sponge) return launch4<Wide128, true, true, true>(p, s);
+    return launch4<Wide128, false, true, true>(p, s);
   }
-  if (src || p.rmap) {
-    if (sponge) return launch4<true, true, false>(p, s);
-    return launch4<false, true, false>(p, s);
+  const bool fuse = src || p.rmap;
+  if (wide_narrow_tiles(g)) {
+    if (fuse) {
+      if (sponge) return launch4<Wide64, true, true, false>(p, s);
+      return launch4<Wide64, false, true, false>(p, s);
+    }
+    if (sponge) return launch4<Wide64, true, false, false>(p, s);
+    return launch4<Wide64, false, false, false>(p, s);
   }
-  if (sponge) return launch4<true, false, false>(p, s);
-  return launch4<false, false, false>(p, s);
+  if (fuse) {
+    if (sponge) return launch4<Wide128, true, true, false>(p, s);
+    return launch4<Wide128, false, true, false>(p, s);
+  }
+  if (sponge) return launch4<Wide128, true, false, false>(p, s);
+  return launch4<Wide128, false, false, false>(p, s);
 }
 
 }  // namespace fd

@@ -198,7 +198,7 @@ class FWIProblem:
         if self.rec_plane is None:
             return False
         return (g.nx * g.ny * g.nz <= SMALL_GRID_POINTS
-                or api.step_kernel(g)["kernel"] == "wide_128x32")
+                or api.step_kernel(g)["kernel"] in ("wide_128x32", "wide_64x64"))
 
     def _backward_scaled(self, res: torch.Tensor, want_grad_w: bool):
         g, nt = self.grid, self.nt

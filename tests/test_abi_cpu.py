@@ -240,7 +240,7 @@ def test_step_launch_shape(L):
         assert launch(L, 512, 512, 512, tile_rows=16) == (256, 512)
     finally:
         assert L.fd_set_tiles(0) == 0
-    assert L.fd_set_tiles(5) == _lib.FD_EINVAL and L.fd_set_tiles(-1) == _lib.FD_EINVAL
+    assert L.fd_set_tiles(6) == _lib.FD_EINVAL and L.fd_set_tiles(-1) == _lib.FD_EINVAL
     assert L.fd_set_tiles(3) == 0  # one thread per point; the marching shape is 64 x 16
     try:
         assert launch(L, 512, 512, 512, tile_rows=16) == (256, 512)
@@ -249,19 +249,30 @@ def test_step_launch_shape(L):
     # which forward kernel a step takes (host only)
     out = (C.c_int32 * 6)()
     g = _lib.fd_grid()
+    # (16-byte lanes with 64 x 64 tiles where a 128-wide tile column would be mostly
+    # empty: 320 = 2.5 x 128, 257 = 2.008 x 128; not with the x faces inside)
     for shape, faces, want in (((64, 64, 64), 0, 0), ((64, 64, 64), 1, 0), ((512, 512, 512), 1, 3),
                                ((512, 512, 512), 0, 3), ((320, 320, 320), 1, 1),
-                               ((320, 320, 320), 0, 3), ((192, 192, 192), 0, 1),
+                               ((320, 320, 320), 0, 4), ((192, 192, 192), 0, 1),
+                               ((257, 256, 256), 0, 4), ((384, 384, 384), 0, 3),
                                ((1024, 1024, 512), 1, 3)):
         assert L.fd_grid_init(C.byref(g), *shape, 10.0, 10.0, 10.0) == 0
         assert L.fd_step_kernel(C.byref(g), faces, out) == 0
         assert out[0] == want, (shape, faces, list(out))
         if want == 3:
-            assert (out[1], out[2]) == (128, 32) and out[5] == 256 or shape == (320, 320, 320)
+            assert (out[1], out[2]) == (128, 32) and 240 <= out[5] <= 256
+        if want == 4:
+            assert (out[1], out[2]) == (64, 64) and 240 <= out[5] <= 256
     assert L.fd_set_tiles(4) == 0
     try:
         assert L.fd_grid_init(C.byref(g), 64, 64, 64, 10.0, 10.0, 10.0) == 0
         assert L.fd_step_kernel(C.byref(g), 0, out) == 0 and out[0] == 3
+        assert L.fd_grid_init(C.byref(g), 320, 320, 320, 10.0, 10.0, 10.0) == 0
+        assert L.fd_step_kernel(C.byref(g), 0, out) == 0 and out[0] == 3
+        assert L.fd_set_tiles(5) == 0
+        assert L.fd_grid_init(C.byref(g), 512, 512, 512, 10.0, 10.0, 10.0) == 0
+        assert L.fd_step_kernel(C.byref(g), 0, out) == 0 and out[0] == 4
+        assert L.fd_step_kernel(C.byref(g), 1, out) == 0 and out[0] == 3  # faces: 128 x 32
     finally:
         assert L.fd_set_tiles(0) == 0
     assert L.fd_step_kernel(C.byref(g), 0, None) == _lib.FD_EINVAL

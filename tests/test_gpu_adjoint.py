@@ -56,7 +56,7 @@ def _fields(g, seeds, periodic):
     return out
 
 
-@pytest.mark.parametrize("tiles", [0, 4])
+@pytest.mark.parametrize("tiles", [0, 4, 5])
 @pytest.mark.parametrize("periodic", [False, True])
 @pytest.mark.parametrize("shape", [(70, 37, 29), (64, 16, 33)])
 def test_adjoint_step_parity(shape, periodic, tiles):
@@ -286,7 +286,7 @@ def _scaled_step_with_residual(tiles, fused):
         api.set_tiles(0)
 
 
-@pytest.mark.parametrize("tiles", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("tiles", [0, 1, 2, 3, 4, 5])
 def test_residual_plane_in_adjoint_launch_matches_scatter(tiles):
     """fd_adjoint_step_scaled_res (the residual row added at receivers on one plane in
     the update's launch) gives the bits of fd_adjoint_step_scaled followed by
@@ -303,9 +303,9 @@ def test_scaled_adjoint_and_gradient_bits_do_not_depend_on_the_kernel():
     """The scaled adjoint update with its residual row and the gradient pass give the
     same bits whichever kernel runs them: the one-thread-per-point kernel, the marching
     kernels of one float per lane (64 x 32 and 64 x 16 tiles) and the 16-byte-lane
-    kernel (128 x 32 tiles)."""
+    kernel (128 x 32 and 64 x 64 tiles)."""
     ref = _scaled_step_with_residual(3, True)
-    for tiles in (1, 2, 4):
+    for tiles in (1, 2, 4, 5):
         got = _scaled_step_with_residual(tiles, True)
         assert same_bits(got[0], ref[0]) and same_bits(got[1], ref[1]), tiles
 

@@ -145,6 +145,7 @@ def test_ragged_sponge_loopback_parity(shape):
 
 @pytest.mark.parametrize("shape,kernel", [((256, 136, 72), "march_64x32"),
                                           ((260, 200, 150), "wide_128x32"),
+                                          ((300, 300, 300), "wide_64x64"),
                                           ((512, 512, 512), "wide_128x32")])
 def test_marching_exchange_kernel_100_steps_vs_oracle(shape, kernel):
     """The benchmark's step path over 100 steps: fd_step_exchange with both face sets
@@ -153,8 +154,9 @@ def test_marching_exchange_kernel_100_steps_vs_oracle(shape, kernel):
     takes: 256 x 136 x 72 the kernel of one float per lane with the x faces inside (a
     ragged last tile row, 136 = 4 x 32 + 8, and several z chunks); 260 x 200 x 150 the
     kernel of 16-byte lanes without faces inside (ragged x and y tiles, rows whose last
-    float4 holds one interior point); 512^3, the benchmark's own grid, the 16-byte-lane
-    kernel with the x faces inside."""
+    float4 holds one interior point); 300^3 the same kernel with 64 x 64 tiles (a
+    128-wide tile column would be mostly empty); 512^3, the benchmark's own grid, the
+    16-byte-lane kernel with the x faces inside."""
     nx, ny, nz = shape
     assert api.step_kernel(api.Grid(nx, ny, nz), faces=True)["kernel"] == kernel
     nt, width = 100, 16
@@ -246,7 +248,7 @@ def test_results_independent_of_launch_shape(shape):
     api.set_tiles(0)
     ref = everything()
     try:
-        for tiles in (1, 2, 3, 4):
+        for tiles in (1, 2, 3, 4, 5):
             api.set_tiles(tiles)
             for kc in (0, 1, 2, 5, 9, 10, 17, nz):
                 api.set_kchunk(kc)
@@ -328,7 +330,8 @@ def test_resume_is_bitwise():
                                          ((256, 100, 48), 0), ((128, 64, 40), 1),
                                          ((70, 33, 29), 3), ((70, 33, 29), 4),
                                          ((256, 100, 48), 4), ((135, 37, 12), 4),
-                                         ((260, 200, 150), 0)])
+                                         ((70, 33, 29), 5), ((135, 37, 12), 5),
+                                         ((260, 200, 150), 0), ((300, 260, 100), 0)])
 @pytest.mark.parametrize("faces", [0, 1, 2])
 def test_receiver_plane_in_stencil_matches_separate_record(shape, tiles, faces):
     """fd_forward_run with a receiver plane map (the stencil launch writes the trace
@@ -337,10 +340,11 @@ def test_receiver_plane_in_stencil_matches_separate_record(shape, tiles, faces):
     mode 4 and on the 7.8M-point grid the Dirichlet steps take the 16-byte-lane
     kernel, which loads its receiver map entries before it marches."""
     nx, ny, nz = shape
-    if faces == 0 and (tiles == 4 or nx * ny * nz > 7_500_000):
+    if faces == 0 and (tiles in (4, 5) or nx * ny * nz > 7_500_000):
         api.set_tiles(tiles)
         try:
-            assert api.step_kernel(api.Grid(nx, ny, nz), faces=False)["kernel"] == "wide_128x32"
+            assert api.step_kernel(api.Grid(nx, ny, nz), faces=False)["kernel"] == (
+                "wide_64x64" if tiles == 5 or (nx, ny, nz) == (300, 260, 100) else "wide_128x32")
         finally:
             api.set_tiles(0)
     v = smooth_velocity(nx, ny, nz, seed=2, sigma=3.0)
