@@ -683,8 +683,10 @@ def main():
             leg = fwi_bench()
         elif args.only == "large":
             leg = large_bench(steps=args.large_steps, cpu=cpu, vcache=args.vcache_large)
-        else:
-            leg = serving_bench(nshots=args.shots)
+        else:  # the three serving legs of the full run
+            leg = {"serving": serving_bench(nshots=args.shots, buddy=True),
+                   "serving_latency": serving_bench(nshots=max(16, args.shots // 2), load=0.5),
+                   "serving_small": serving_bench(nshots=args.shots, lo=48, hi=128)}
         print(json.dumps(leg), flush=True)
         return
     n = args.n

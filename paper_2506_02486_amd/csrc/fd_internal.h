@@ -127,6 +127,10 @@ int tile_override();
 // exchange form) take 64 x 64 tiles instead of 128 x 32 (tile mode 5: always; 4:
 // never; else where the launch model prefers them by a tenth).
 bool wide_narrow_tiles(const Geo& g);
+// Whether g's tiles in a launch shared with other grids (launch_wide_multi) are
+// 64 x 64 (modes 5 and 4 as above; else where they cover the plane with a tenth
+// fewer points than 128 x 32).
+bool wide_narrow_in_multi(const Geo& g);
 // Forward launches over g use 64 x 16 tiles instead of 64 x 32: small grids (at
 // most kSmallGridPoints interior points), or as forced by set_tile_override
 // (0: automatic, 1: always 64 x 32, 2: always 64 x 16).

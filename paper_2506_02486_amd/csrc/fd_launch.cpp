@@ -85,7 +85,7 @@ LaunchShape stencil_shape(const Geo& g, int tx, int ty, int waves_per_block) {
       last = {g.nx, g.ny, g.nz, tx, ty, waves_per_block, kc};
     }
   }
-  if (kc > g.nz) kc = g.nz;
+  if (kc > g.nz) kc = std::max(1, g.nz);
   s.kchunk = kc;
   s.zchunks = (g.nz + kc - 1) / kc;
   return s;

@@ -23,8 +23,10 @@
 // alone, grids that are small together share it.
 // A batched step advances every active shot by one launch: a lone shot by the
 // kernel its grid takes alone; several, if one of them is a grid of at least 7.5M
-// points, all by the 16-byte-lane kernel (128 x 32 tiles; up to kWideMulti grids with
-// their parameters in the kernel arguments, more through a tile table), else by the
+// points, all by the 16-byte-lane kernel (up to kWideMulti grids with their
+// parameters in the kernel arguments, each in 128 x 32 tiles or, where those would
+// leave a tenth more of its plane empty, 64 x 64; more through a tile table of
+// 128 x 32 tiles), else by the
 // one-float-per-lane kernel over a tile table (64 x 32 tiles).  Both write the trace
 // rows of shots whose receivers share one plane; one batched receiver launch takes
 // the others.
@@ -83,7 +85,10 @@ constexpr long long kFillPoints = 256LL * 128 * 32 * 8;
 // 32.8; 256^3 twice: 90.6 against 2 x 47.8), of a large and a small grid it does not
 // (384^3 and 256^3: 222 us against 162 + 48).  Throughput at twice the plain loop's
 // rate on the 128..384^3 mix, with this cap on all steps: 8.4M points 1.006x, 16.8M
-// 1.009x, 25.2M 1.020x, 33.6M 1.016x, 67.1M 0.916x.
+// 1.009x, 25.2M 1.020x, 33.6M 1.016x, 67.1M 0.916x.  Joining wherever the launch model
+// (choose_kchunk's) prices one launch of the running shots and the new one below the
+// two launches apart ran more shots together and gave 0.987x: the model overrates
+// one launch of two large grids.
 constexpr long long kBacklogPoints = 3 * kFillPoints;
 
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }

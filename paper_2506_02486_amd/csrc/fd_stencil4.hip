@@ -86,7 +86,8 @@ struct P4 {
   const int32_t* rmap;
   int rk;
   float* rrow;
-  bool radd;  // rrow is a row to add at the receivers, scaled by vdt2 / (1+eta)
+  bool radd;    // rrow is a row to add at the receivers, scaled by vdt2 / (1+eta)
+  bool narrow;  // multi-grid launch: this grid's tiles are 64 x 64 (tiles_x, tiles_y so)
 };
 
 __device__ __forceinline__ int remap_block4(int bid, int nb) {
@@ -103,10 +104,10 @@ __device__ __forceinline__ f4 ld4_nt(const char* base, unsigned boff) {
 }
 
 // The work of one block: tile (bx, by) of the x-y plane, z chunk bz, of the grid
-// and operands p describes.
+// and operands p describes; the thread is lane lx of thread row tr (SH's shape).
 template <class SH, bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
 __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const int by,
-                                               const int bz) {
+                                               const int bz, const int lx, const int tr) {
   constexpr int LANES = SH::LANES;
   constexpr int TX = 4 * LANES;           // x points per tile
   constexpr int TY = SH::TROWS * RY;      // y rows per tile
@@ -115,8 +116,6 @@ __device__ __forceinline__ void stencil4_block(const P4& p, const int bx, const 
   constexpr int XH = 2 * TY / LANES;      // thread rows that load the x halo
   __shared__ __attribute__((aligned(16))) float sm[2][LY * LX];
 
-  const int lx = threadIdx.x;
-  const int tr = threadIdx.y;
   const int nx = p.g.nx, ny = p.g.ny, nz = p.g.nz;
   const int sy = p.g.sy;
   const long long szb = 4LL * p.g.sz;
@@ -439,7 +438,8 @@ __global__ void __launch_bounds__(SH::LANES * SH::TROWS) stencil4_kernel(P4 p) {
   const int logical = remap_block4(blockIdx.x, gridDim.x);
   const int bx = logical % p.tiles_x;
   const int rest = logical / p.tiles_x;
-  stencil4_block<SH, SPONGE, FUSE, XCH, GRAD>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
+  stencil4_block<SH, SPONGE, FUSE, XCH, GRAD>(p, bx, rest % p.tiles_y, rest / p.tiles_y,
+                                              threadIdx.x, threadIdx.y);
 }
 
 // Many grids in one launch: block b runs tile tiles[remap(b)] = (slot, bx, by, bz) of
@@ -474,13 +474,16 @@ __global__ void __launch_bounds__(LANES * TROWS) batched4_kernel(const BatchShot
   p.rk = b.rmap ? b.rk : -1;
   p.rrow = b.traces + (size_t)n * (size_t)b.nrec;
   p.radd = false;  // the trace row is written, not added to
-  stencil4_block<Wide128, true, true, false>(p, t.y, t.z, t.w);
+  p.narrow = false;
+  stencil4_block<Wide128, true, true, false>(p, t.y, t.z, t.w, threadIdx.x, threadIdx.y);
 }
 
 // Up to kWideMulti grids in one launch, their parameters in the kernel arguments:
 // grid i owns blocks [start[i], start[i+1]) (tiles in the order of stencil4_kernel);
 // a block finds its grid by comparing uniform values, with no memory look-up before
-// its first loads.
+// its first loads.  Each grid has its own tile shape: the block's 512 threads are
+// 32 x 16 for 128 x 32 tiles and, renumbered in the same order, 16 x 32 for 64 x 64
+// (the branch is uniform over the block; both shapes compute the same bits).
 struct MultiArgs {
   int n;
   int start[kWideMulti + 1];
@@ -495,7 +498,14 @@ __global__ void __launch_bounds__(LANES * TROWS) multi4_kernel(MultiArgs A) {
   const int t = b - A.start[i];
   const int bx = t % p.tiles_x;
   const int rest = t / p.tiles_x;
-  stencil4_block<Wide128, true, true, false>(p, bx, rest % p.tiles_y, rest / p.tiles_y);
+  if (p.narrow) {
+    const int lin = threadIdx.x + LANES * threadIdx.y;
+    stencil4_block<Wide64, true, true, false>(p, bx, rest % p.tiles_y, rest / p.tiles_y,
+                                              lin % Wide64::LANES, lin / Wide64::LANES);
+  } else {
+    stencil4_block<Wide128, true, true, false>(p, bx, rest % p.tiles_y, rest / p.tiles_y,
+                                               threadIdx.x, threadIdx.y);
+  }
 }
 
 template <class SH, bool SPONGE, bool FUSE, bool XCH, bool GRAD = false>
@@ -553,11 +563,15 @@ hipError_t launch_batched4(const BatchShot* shots, const int4* tiles, int ntiles
 hipError_t launch_wide_multi(const WideStep* steps, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n > kWideMulti) return hipErrorInvalidValue;
-  // one z chunk for all the grids, from the launch model over them
+  // each grid's tile shape, then one z chunk for all the grids, from the launch
+  // model over them
   long long xy[kWideMulti];
   int nz[kWideMulti];
+  bool narrow[kWideMulti];
   for (int i = 0; i < n; ++i) {
-    xy[i] = (long long)((steps[i].g.nx + TX - 1) / TX) * ((steps[i].g.ny + TY - 1) / TY);
+    narrow[i] = wide_narrow_in_multi(steps[i].g);
+    const int tx = narrow[i] ? 64 : TX, ty = narrow[i] ? 64 : TY;
+    xy[i] = (long long)((steps[i].g.nx + tx - 1) / tx) * ((steps[i].g.ny + ty - 1) / ty);
     nz[i] = steps[i].g.nz;
   }
   const int kc = choose_kchunk(xy, nz, n, 16, 0, 0x7fffffffLL);
@@ -577,8 +591,9 @@ hipError_t launch_wide_multi(const WideStep* steps, int n, hipStream_t s) {
     p.ex = w.ex;
     p.ey = w.ey;
     p.ez = w.ez;
-    p.tiles_x = (w.g.nx + TX - 1) / TX;
-    p.tiles_y = (w.g.ny + TY - 1) / TY;
+    p.narrow = narrow[i];
+    p.tiles_x = (w.g.nx + (narrow[i] ? 64 : TX) - 1) / (narrow[i] ? 64 : TX);
+    p.tiles_y = (w.g.ny + (narrow[i] ? 64 : TY) - 1) / (narrow[i] ? 64 : TY);
     p.kchunk = std::min(kc, w.g.nz);
     p.si = w.src.i;
     p.sj = w.src.j;
@@ -634,6 +649,17 @@ bool wide_narrow_tiles(const Geo& g) {
   // 64 x 64 where they cut the modelled launch time by a tenth: where a 128-wide
   // tile column would be mostly empty (nx = 257: 3 columns of 128, 5 of 64)
   return stencil_cost(g, 64, 64, 16) < 0.9 * stencil_cost(g, TX, TY, 16);
+}
+
+bool wide_narrow_in_multi(const Geo& g) {
+  const int mode = tile_override();
+  if (mode == 5) return true;
+  if (mode == 4) return false;
+  // in a launch shared with other grids only the tiles' area counts: 64 x 64 where
+  // it covers the plane with a tenth fewer points than 128 x 32
+  const long long a128 = (long long)((g.nx + TX - 1) / TX) * TX * (((g.ny + TY - 1) / TY) * TY);
+  const long long a64 = (long long)((g.nx + 63) / 64) * 64 * (((g.ny + 63) / 64) * 64);
+  return 10 * a64 < 9 * a128;
 }
 
 void wide_forward_shape(const Geo& g, int out[4]) {

@@ -252,7 +252,9 @@ def test_both_kernel_families_in_one_step():
     """A grid of at least 7.5M points running in the same steps as small grids: all of
     them then take the 16-byte-lane kernel, in one launch with their parameters as
     kernel arguments (the small grids' tiles fill the large grid's launch; receiver
-    rows in the kernel); ten small grids in the one-float-per-lane tile table; the
+    rows in the kernel; the small grids, whose 128-wide tile columns would be mostly
+    empty, in 64 x 64 tiles and the large one in 128 x 32, then all of them in 64 x 64
+    with fd_set_tiles(5)); ten small grids in the one-float-per-lane tile table; the
     same ten forced onto 16-byte lanes (fd_set_tiles(4)), more than one such launch
     carries, through its tile table: traces equal to the solo runs bit for bit."""
     v = smooth_velocity(200, 200, 192, seed=2, sigma=4.0)  # the 10 small grids fit inside
@@ -268,7 +270,7 @@ def test_both_kernel_families_in_one_step():
            shot(52, 47, 33, (26, 23, 16)), shot(37, 61, 29, (18, 30, 14))]
     many = [shot(20 + 3 * i, 18 + 2 * i, 12 + i, (9, 8, 6)) for i in range(10)]
     assert api.step_kernel(api.Grid(200, 200, 192))["kernel"] == "wide_128x32"
-    for tiles, shots in ((0, mix), (0, many), (4, many)):
+    for tiles, shots in ((0, mix), (5, mix), (0, many), (4, many)):
         api.set_tiles(tiles)
         try:
             with serving.ShotServer(4 << 30, max_slots=16, max_active_points=1 << 40) as srv:
@@ -287,14 +289,14 @@ def test_both_kernel_families_in_one_step():
 
 def test_default_policy_runs_device_filling_grids_alone():
     """Under the default policy a shot joins running ones within 8,388,608 points, or
-    within 25,165,824 while more shots wait behind it: grids of 13.8M points (320 x 240
-    x 180), submitted together, run one after the other, each activated when the one
+    within 25,165,824 while more shots wait behind it: grids of 37.7M points (384 x 384
+    x 256), submitted together, run one after the other, each activated when the one
     before has finished; grids of 10.6M (220^3) share the steps while a backlog waits
     (small grids share them too: test_mix_equals_solo_bitwise_and_overlaps)."""
-    v = smooth_velocity(320, 240, 220, seed=2, sigma=4.0)
+    v = smooth_velocity(384, 384, 256, seed=2, sigma=4.0)
     vd = torch.from_numpy(v).cuda()
     dt = ora.cfl_dt(v, 10.0)
-    shots = [serving.Shot(vd[:180], 15, dt, (160, 120, 80 + i), receivers_xline(320, 120, 4),
+    shots = [serving.Shot(vd, 15, dt, (192, 192, 100 + i), receivers_xline(384, 192, 4),
                           sponge_width=16, sponge_vmax=float(v.max())) for i in range(3)]
     with serving.ShotServer(10 << 30, max_slots=8) as srv:
         ids = [srv.submit(s) for s in shots]
