@@ -13,9 +13,12 @@
 // behind the others' MFMAs.  The K loop takes 16 columns of A and 16 rows of B per stage, staged in
 // double-buffered LDS; the next stage is loaded into registers while the MFMAs of the
 // current one run.
-// Operands of any shape and leading dimension: loads past an edge read 0 and stores
-// past an edge are skipped.  Blocks sharing a B panel (a column of tiles) run on
-// one XCD in succession, so that the panel is read from HBM about once.
+// Operands of any shape and leading dimension: K is split into a first stage of
+// 1..16 columns, whose loads past K read 0, and whole stages, whose loads need no
+// bounds arithmetic (a pointer per thread plus the stage's offset); rows past m and
+// columns past n are read clamped and their results not stored.  Blocks sharing a B
+// panel (a column of tiles) run on one XCD in succession, so that the panel is read
+// from HBM about once.
 #include <stdint.h>
 
 #include <algorithm>
@@ -90,24 +93,33 @@ __global__ void __launch_bounds__(GT, WAVES_PER_SIMD) gemm_f64_kernel(GemmArgs g
   const int ar = t / BK;
   const int bc = t % BN;
   const int br = t / BN;
-  // Every load is unconditional: one past an edge reads the clamped element (in
-  // bounds) and is replaced by 0, so no branch splits the loads of a stage.
+  // K is taken as a first stage of kt = k - (stages - 1) BK columns (1..BK), then
+  // whole stages of BK.  Rows of A past m and columns of B past n are read clamped and
+  // not cleared: they only reach rows and columns of the tile that are not stored.
+  // Only the first stage clears what lies past its kt columns (in both operands: 0 x
+  // Inf would be NaN).  So a load of a whole stage is a per-thread pointer plus the
+  // stage's uniform offset, with no bounds arithmetic, and every load is unconditional
+  // (a load under a branch would make the compiler wait for it where the branch joins).
+  const int64_t stages = (g.k + BK - 1) / BK;
+  const int64_t kt = g.k - (stages - 1) * BK;
+  const double* pa[A_PER];
+  const double* pb[B_PER];
+  const int64_t bcol = std::min(n0 + bc, g.n - 1);
+#pragma unroll
+  for (int i = 0; i < A_PER; ++i)  // (k < BK: a single stage, read clamped in K)
+    pa[i] = g.a + std::min(m0 + ar + (GT / BK) * i, g.m - 1) * g.lda +
+            std::min<int64_t>(ak, g.k - 1);
+#pragma unroll
+  for (int i = 0; i < B_PER; ++i)
+    pb[i] = g.b + std::min<int64_t>(br + (GT / BN) * i, g.k - 1) * g.ldb + bcol;
   double ra[A_PER], rb[B_PER];
+  // whole stage at column k0 = kt + (s - 1) BK of A, row k0 of B (s >= 1)
   auto load_stage = [&](int64_t k0) {
+    const int64_t boff = k0 * g.ldb;
 #pragma unroll
-    for (int i = 0; i < A_PER; ++i) {
-      const int64_t row = m0 + ar + (GT / BK) * i;
-      const int64_t col = k0 + ak;
-      const double x = g.a[std::min(row, g.m - 1) * g.lda + std::min(col, g.k - 1)];
-      ra[i] = (row < g.m && col < g.k) ? x : 0.0;
-    }
+    for (int i = 0; i < A_PER; ++i) ra[i] = pa[i][k0];
 #pragma unroll
-    for (int i = 0; i < B_PER; ++i) {
-      const int64_t row = k0 + br + (GT / BN) * i;
-      const int64_t col = n0 + bc;
-      const double x = g.b[std::min(row, g.k - 1) * g.ldb + std::min(col, g.n - 1)];
-      rb[i] = (row < g.k && col < g.n) ? x : 0.0;
-    }
+    for (int i = 0; i < B_PER; ++i) rb[i] = pb[i][boff];
   };
   auto store_stage = [&](int buf) {
 #pragma unroll
@@ -122,9 +134,21 @@ __global__ void __launch_bounds__(GT, WAVES_PER_SIMD) gemm_f64_kernel(GemmArgs g
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t stages = (g.k + BK - 1) / BK;
   if (stages > 0) {
-    load_stage(0);
+    // the first stage: columns 0 .. kt-1 of A and rows 0 .. kt-1 of B, the rest 0
+    // (a cleared element reads the stage's last valid one, in bounds)
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const double x = g.a[std::min(m0 + ar + (GT / BK) * i, g.m - 1) * g.lda +
+                           std::min<int64_t>(ak, kt - 1)];
+      ra[i] = ak < kt ? x : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) {
+      const int64_t row = br + (GT / BN) * i;
+      const double x = g.b[std::min(row, kt - 1) * g.ldb + bcol];
+      rb[i] = row < kt ? x : 0.0;
+    }
     store_stage(0);
   }
   __syncthreads();
@@ -136,7 +160,7 @@ __global__ void __launch_bounds__(GT, WAVES_PER_SIMD) gemm_f64_kernel(GemmArgs g
     // the next stage's loads, unconditional (the last iteration reloads its own
     // stage into the buffer nobody reads again): a load under a branch would make
     // the compiler wait for it where the branch joins, before the MFMAs
-    load_stage(std::min(s + 1, stages - 1) * BK);
+    load_stage(std::max<int64_t>(kt + (std::min(s + 1, stages - 1) - 1) * BK, 0));
     const double* A = sa[buf];
     const double* B = sb[buf];
 #pragma unroll
