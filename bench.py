@@ -180,11 +180,12 @@ def host_cpu() -> str:
 
 
 def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.0,
-                  warm=16, load=2.0, reps=3, buddy=False):
+                  warm=16, load=2.0, reps=3, buddy=False, cap=0):
     """Poisson stream of shots of uneven size: the batching server against the plain
     per-shot loop (same kernels, one shot at a time, arrival order), each run `reps`
     times, alternately, on the same arrivals; reported per run, as the mean, and as
-    the spread (max - min) of the runs."""
+    the spread (max - min) of the runs.  cap > 0: the server's admission cap on the
+    points running at once (fd_server_set_admission) in place of its default policy."""
     import threading
 
     import numpy as np
@@ -237,7 +238,7 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
 
     def run_server(allocator):
         srv = serving.ShotServer(int(arena_gb * (1 << 30)), max_slots=max_slots,
-                                 allocator=allocator)
+                                 allocator=allocator, max_active_points=cap)
         ids = [None] * nshots
         t_arr = [0] * nshots
 
@@ -314,6 +315,7 @@ def serving_bench(nshots=256, nt=500, lo=128, hi=384, max_slots=32, arena_gb=48.
         "server": srv,
         "max_slots": max_slots,
         "arena_GB": arena_gb,
+        "admission": f"cap {cap} points" if cap else "default policy",
     }
     if buddy:  # the same with the buddy arena, one run
         log("serving: batching server (buddy arena)")
@@ -655,6 +657,9 @@ def main():
     ap.add_argument("--no-cannon", action="store_true",
                     help="skip the Cannon block-product leg (N=30240, P=8)")
     ap.add_argument("--shots", type=int, default=256, help="shots in the serving stream")
+    ap.add_argument("--serving-cap", type=int, default=0,
+                    help="with --only serving: the server's cap on running points (0: its "
+                         "default admission policy)")
     ap.add_argument("--only", choices=["cannon", "fwi", "large", "serving"], default=None,
                     help="run only this leg (no 512^3 step) and print its JSON object; for "
                          "profiling a leg by itself")
@@ -684,7 +689,7 @@ def main():
         elif args.only == "large":
             leg = large_bench(steps=args.large_steps, cpu=cpu, vcache=args.vcache_large)
         else:  # the three serving legs of the full run
-            leg = {"serving": serving_bench(nshots=args.shots, buddy=True),
+            leg = {"serving": serving_bench(nshots=args.shots, buddy=True, cap=args.serving_cap),
                    "serving_latency": serving_bench(nshots=max(16, args.shots // 2), load=0.5),
                    "serving_small": serving_bench(nshots=args.shots, lo=48, hi=128)}
         print(json.dumps(leg), flush=True)

@@ -568,7 +568,7 @@ int shot_poll(void* srv, int64_t shot_id, float* traces_host, size_t cap, int64_
  * default) a shot joins if the interior points of the running shots and its own stay
  * within the fill, 256 x 128 x 32 x 8 = 8,388,608 (each of the 256 CUs one 128 x 32
  * tile of 8 z planes: grids that together leave the device short of work), or, while
- * more shots wait behind it (a backlog), within 3 times that (one launch of two
+ * more shots wait behind it (a backlog), within twice that (one launch of two
  * mid-size grids beats two launches); with max_active_points > 0 if they
  * stay within that many.  A shot always joins when none runs.  FD_EINVAL for a NULL
  * server or a negative limit.  Thread-safe. */

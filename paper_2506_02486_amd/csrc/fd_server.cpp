@@ -84,12 +84,15 @@ constexpr long long kFillPoints = 256LL * 128 * 32 * 8;
 // two mid-size grids beats two launches (336 x 150 x 174 twice: 59.0 us against 2 x
 // 32.8; 256^3 twice: 90.6 against 2 x 47.8), of a large and a small grid it does not
 // (384^3 and 256^3: 222 us against 162 + 48).  Throughput at twice the plain loop's
-// rate on the 128..384^3 mix, with this cap on all steps: 8.4M points 1.006x, 16.8M
-// 1.009x, 25.2M 1.020x, 33.6M 1.016x, 67.1M 0.916x.  Joining wherever the launch model
-// (choose_kchunk's) prices one launch of the running shots and the new one below the
-// two launches apart ran more shots together and gave 0.987x: the model overrates
-// one launch of two large grids.
-constexpr long long kBacklogPoints = 3 * kFillPoints;
+// rate on the 128..384^3 mix, with a cap on the running points at all steps (the same
+// box, three alternating runs each): 8.4M points 1.001x, 16.8M 1.004x, no co-running
+// 1.003x, against 0.999x for the fill with 25.2M under a backlog (before the 64 x 64
+// tiles for ragged grids, on another box: 8.4M 1.006x, 16.8M 1.009x, 25.2M 1.020x,
+// 33.6M 1.016x, 67.1M 0.916x).  Joining wherever the launch model (choose_kchunk's)
+// prices one launch of the running shots and the new one below the two launches apart
+// ran more shots together and gave 0.987x: the model overrates one launch of two large
+// grids.
+constexpr long long kBacklogPoints = 2 * kFillPoints;
 
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 

@@ -89,7 +89,7 @@ class ShotServer:
     def set_admission(self, max_active_points: int):
         """Activation policy (fd_server_set_admission): 0 (default) a shot joins the
         running ones when their interior points and its own stay within 8,388,608
-        (one 128 x 32 tile of 8 planes per CU), or within 3 times that while more
+        (one 128 x 32 tile of 8 planes per CU), or within twice that while more
         shots wait behind it; > 0 when they stay within this many.  A shot always
         joins when none runs."""
         check(lib().fd_server_set_admission(self.h, int(max_active_points)),
