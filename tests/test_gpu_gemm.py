@@ -3,9 +3,10 @@ FP64 oracle's definition (oracle.block_gemm, oracle.cannon).
 
 With small integer operands every partial sum is exact in FP64, so the matrix-core
 product must equal the oracle bit for bit in any summation order: these cases span
-several 128 x 128 tiles with ragged edges in m, n and k, leading dimensions wider
-than the rows, accumulate on and off, and a single 16 x 16 x 4 tile (the MFMA lane
-layout).  Random normal operands are compared with the oracle within the FP64 error
+several 256 x 128 tiles with ragged edges in m, n and k, leading dimensions wider
+than the rows, accumulate on and off, a single 16 x 16 x 4 tile (the MFMA lane
+layout), and first K stages (the only ones that clear past K) of 1, 6, 12 and 16
+columns, alone or followed by whole stages (k = 16, 17, 32, 33, 70, 300).  Random normal operands are compared with the oracle within the FP64 error
 bound of a k-term dot product, 4 k u (|A| |B| + |C0|) elementwise.  The Cannon
 schedule of every rank reproduces the oracle's P-rank product, and at the full size of
 the paper's experiment (N = 30240, P = 8: rank 0's eight steps of 3780 x 30240 x 3780)
@@ -39,7 +40,8 @@ def _padded(x: np.ndarray, extra: int, fill: float = 0.0) -> torch.Tensor:
 
 
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (16, 16, 4), (128, 128, 16), (130, 257, 33),
-                                   (300, 129, 70), (17, 5, 300), (255, 384, 1)])
+                                   (300, 129, 70), (17, 5, 300), (255, 384, 1), (64, 64, 32),
+                                   (257, 129, 17)])
 @pytest.mark.parametrize("accumulate", [False, True])
 def test_integer_operands_bit_exact(m, n, k, accumulate):
     rng = np.random.default_rng(m + 7 * n + 31 * k)
